@@ -1,0 +1,285 @@
+/*
+ * qx.h -- C ABI of libqx.so: the staggered Dirac operator (Dslash), the
+ * even-odd preconditioned conjugate-gradient solve of (m^2 - D_eo D_oe) x = b
+ * and the fermion force, on AMD Instinct MI355X (gfx950).
+ *
+ * The paper (Sec. 4) describes a lattice framework whose hot path is a
+ * staggered Dirac operator on SU(N) links (Sec. 1: a 4-D grid with one SU(3)
+ * matrix per link) inside single- and double-precision conjugate-gradient
+ * solvers, and hybrid Monte Carlo (which needs the fermion force).  The paper
+ * gives no formulas; this library implements the textbook Kogut-Susskind
+ * operator
+ *
+ *   (D chi)(x) = 1/2 sum_mu eta_mu(x) [ bc_mu(x) U_mu(x) chi(x+mu)
+ *                                      - bc_mu(x-mu) U_mu(x-mu)^dag chi(x-mu) ]
+ *   eta_mu(x)  = (-1)^(x_0 + ... + x_{mu-1}),  mu = 0..3 = x, y, z, t,
+ *   bc_mu(x)   = -1 for mu = 3, x_3 = L_3 - 1 if QX_BC_T_ANTIPERIODIC, else +1,
+ *
+ * periodic in all directions, and the Hermitian positive-definite even-site
+ * operator A = m^2 - D_eo D_oe (= M^dag M on even sites for M = m + D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: every call returns QX_OK (0) or a QX_E* code; the message of the
+ *    last failure on the calling thread is returned by qx_last_error().  No
+ *    C++ exception crosses this boundary.
+ *  - Memory: the caller owns every device buffer (gauge fields, packed fields,
+ *    workspaces, outputs) and passes plain device pointers; the sizes come
+ *    from the qx_*_bytes queries.  The library owns only small host handles
+ *    and, for solver/batch handles, a few hundred bytes of device metadata
+ *    that it frees in the matching destroy call.  Handles are not safe for
+ *    concurrent use from several threads.
+ *  - Streams: all device work is enqueued on the hipStream_t passed in
+ *    (0 = the legacy default stream).  Calls that return host results (solver
+ *    statistics, the action, the unitarity check) synchronise that stream
+ *    before they return; all others are asynchronous.
+ *  - Lattice: dims[4] = (L_x, L_y, L_z, L_t), every extent even and >= 2,
+ *    V = L_x L_y L_z L_t < 2^31.  Lexicographic site order
+ *    lex = x + L_x (y + L_y (z + L_z t)); parity = (x+y+z+t) mod 2;
+ *    checkerboard index cb = lex >> 1; even-odd index eo = parity*V/2 + cb.
+ *  - Canonical (caller-facing) layouts, complex = two IEEE doubles (re, im):
+ *      gauge field   complex128 [4][V][3][3]   (mu, lex, row, column)
+ *      half field    complex128 [nrhs][V/2][3] (source, cb, colour), one parity
+ *      link gradient complex128 [4][V][3][3]
+ *  - Packed (internal, device) layouts are opaque byte buffers produced by the
+ *    pack calls; their sizes come from qx_gauge_bytes / qx_field_bytes.
+ */
+#ifndef QX_H
+#define QX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QX_VERSION 1
+
+/* status codes */
+enum {
+  QX_OK = 0,
+  QX_EINVAL = 1,        /* bad argument (shape, pointer, enum, odd extent) */
+  QX_ENOMEM = 2,        /* caller workspace too small, or host allocation failed */
+  QX_EHIP = 3,          /* a HIP runtime call failed (message in qx_last_error) */
+  QX_ENOTUNITARY = 4,   /* 12-real link compression asked for non-SU(3) links */
+  QX_ENOTCONVERGED = 5, /* max_iter reached before the tolerance */
+  QX_EBREAKDOWN = 6,    /* <p, A p> <= 0 or non-finite (e.g. NaN/Inf in the input) */
+  QX_ENOLIB = 7         /* no usable gfx950 device */
+};
+
+/* lattice flags */
+enum { QX_BC_T_ANTIPERIODIC = 1 };
+
+/* storage precision of packed fields */
+enum { QX_PREC_F64 = 0, QX_PREC_F32 = 1 };
+
+/* link storage: 18 reals, or 12 reals (rows 0-1, row 2 rebuilt in-kernel as
+   sign * conj(row0 x row1); exact for SU(3) links) */
+enum { QX_RECON_18 = 18, QX_RECON_12 = 12 };
+
+/* solver modes */
+enum {
+  QX_CG_FP64 = 0,      /* all vectors, links and dot products in FP64 */
+  QX_CG_MIXED_F32 = 1  /* FP32 inner iteration, FP64 reliable updates, solution and dots */
+};
+
+typedef struct qx_lattice qx_lattice_t;
+typedef struct qx_gauge qx_gauge_t;
+typedef struct qx_batch qx_batch_t;
+
+/* Solver parameters.  tol: relative residual |b - A x| / |b| to reach, measured
+   in FP64 on the returned x.  max_iter: cap on inner iterations per source.
+   delta: reliable-update trigger, an update happens when |r| < delta * max|r|
+   since the last update (ignored by QX_CG_FP64, which updates only to confirm
+   convergence).  use_x0: x holds an initial guess on entry.  chunk: inner
+   iterations enqueued between host convergence checks (0 = default). */
+typedef struct {
+  double tol;
+  int max_iter;
+  int mode;
+  double delta;
+  int use_x0;
+  int chunk;
+} qx_cg_params_t;
+
+/* Per-source solver statistics. */
+typedef struct {
+  int status;               /* QX_OK, QX_ENOTCONVERGED or QX_EBREAKDOWN */
+  int iters;                /* inner iterations */
+  int reliable_updates;     /* FP64 residual recomputations, including the final one */
+  double true_rel_residual; /* FP64 |b - A x| / |b| of the returned x, as computed on the GPU */
+  double seconds;           /* wall time of the whole call */
+} qx_cg_stats_t;
+
+/* ------------------------------------------------------------------ misc */
+
+int qx_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* qx_last_error(void);
+
+/* ------------------------------------------------------------- lattice */
+
+/* Create a lattice description (host only).  flags: QX_BC_T_ANTIPERIODIC or 0.
+   QX_EINVAL for an odd extent, an extent < 2 or V >= 2^31. */
+int qx_lattice_create(const int32_t dims[4], uint32_t flags, qx_lattice_t** out);
+int qx_lattice_destroy(qx_lattice_t* lat);
+/* Number of sites V, or -1 for a NULL handle. */
+int64_t qx_lattice_volume(const qx_lattice_t* lat);
+
+/* Copy the even-odd index maps computed by the device geometry code into
+   device buffers: lex_of_eo[V] (int32) and nbr_eo[V][8] (int32; entry k < 4
+   is the eo index of x + mu_k, entry 4 + k that of x - mu_k, periodic wrap).
+   Exists so that tests can check the on-the-fly neighbour arithmetic of the
+   Dslash kernels bit for bit. */
+int qx_debug_index_maps(const qx_lattice_t* lat, int32_t* lex_of_eo, int32_t* nbr_eo,
+                        hipStream_t stream);
+
+/* ---------------------------------------------------------- gauge field */
+
+/* Bytes of a packed gauge field of the given precision and link storage. */
+int qx_gauge_bytes(const qx_lattice_t* lat, int prec, int recon, size_t* bytes);
+
+/* Pack the canonical complex128 [4][V][3][3] gauge field U_canon (device) into
+   `packed` (device, qx_gauge_bytes long, owned by the caller and borrowed by
+   the handle, which must not outlive it).  The staggered phase eta and the
+   boundary sign are folded into the packed links.  With QX_RECON_12 the call
+   synchronises the stream and checks that every link satisfies
+   row2 = conj(row0 x row1) to 1e-10 (returns QX_ENOTUNITARY otherwise). */
+int qx_gauge_load(const qx_lattice_t* lat, const void* U_canon, int prec, int recon, void* packed,
+                  hipStream_t stream, qx_gauge_t** out);
+int qx_gauge_destroy(qx_gauge_t* g);
+
+/* ------------------------------------------------------------ fields */
+
+/* Bytes of a packed half-lattice field holding nrhs sources. */
+int qx_field_bytes(const qx_lattice_t* lat, int nrhs, int prec, size_t* bytes);
+
+/* canonical complex128 [nrhs][V/2][3] <-> packed (device buffers). */
+int qx_field_pack(const qx_lattice_t* lat, int nrhs, int prec, const void* canon, void* packed,
+                  hipStream_t stream);
+int qx_field_unpack(const qx_lattice_t* lat, int nrhs, int prec, const void* packed, void* canon,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------- operators */
+
+/* out = D in, from parity 1 - out_parity to parity out_parity, with the factor
+   1/2, for nrhs sources at once (each link is loaded once per site and applied
+   to every source).  in/out are packed fields of the gauge handle's precision;
+   they must not alias. */
+int qx_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const void* in, void* out,
+              hipStream_t stream);
+
+/* out = (m_s^2 - D_eo D_oe) in for each source s on even sites; masses is a
+   host array of nrhs values; tmp_odd is a packed odd field of nrhs sources
+   used as scratch.  Buffers must not alias. */
+int qx_apply_A(const qx_gauge_t* g, int nrhs, const double* masses, const void* in, void* out,
+               void* tmp_odd, hipStream_t stream);
+
+/* ------------------------------------------------------------- solver */
+
+/* Workspace bytes for qx_cg_solve with nrhs sources. */
+int qx_cg_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params, int nrhs,
+                          size_t* bytes);
+
+/* Solve (m_s^2 - D_eo D_oe) x_s = b_s for s < nrhs, every source with its own
+   CG recurrence (no block Krylov).  g64: FP64 gauge handle (reliable updates
+   and the final residual); glo: the inner-precision handle for
+   QX_CG_MIXED_F32 (FP32 links, 18 or 12 reals) or NULL for QX_CG_FP64.
+   b, x: canonical complex128 [nrhs][V/2][3] device buffers (x holds the
+   initial guess on entry if params->use_x0).  ws: device workspace of at
+   least qx_cg_workspace_bytes.  stats: host array of nrhs entries.
+   Synchronises the stream.  Returns QX_OK if every source converged, else the
+   first failing source's status (the others are still solved and reported). */
+int qx_cg_solve(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_cg_params_t* params,
+                int nrhs, const double* masses, const void* b, void* x, void* ws,
+                size_t ws_bytes, qx_cg_stats_t* stats, hipStream_t stream);
+
+/* ------------------------------------------------------------- batches */
+
+/* One system of a batch: a lattice with its gauge handles (g64 FP64, glo the
+   inner precision or NULL for QX_CG_FP64), nrhs sources with their masses
+   (host array, copied at create), and canonical b / x device buffers. */
+typedef struct {
+  const qx_gauge_t* g64;
+  const qx_gauge_t* glo;
+  int nrhs;
+  const double* masses;
+  const void* b;
+  void* x;
+} qx_system_t;
+
+/* Workspace bytes for a batch of systems. */
+int qx_batch_workspace_bytes(int nsys, const qx_system_t* systems, const qx_cg_params_t* params,
+                             size_t* bytes);
+
+/* Plan a batch: every system (any mix of lattice sizes) is solved by one set
+   of launches per CG step that covers all systems, converged sources are
+   masked out, and the launch sequence of a chunk of iterations is captured
+   once into a HIP graph that qx_batch_solve replays.  ws must stay valid and
+   unchanged in size for the life of the batch. */
+int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg_params_t* params, void* ws,
+                    size_t ws_bytes, hipStream_t stream, qx_batch_t** out);
+
+/* Solve every system of the batch; stats: host array with one entry per
+   source, systems in order.  Synchronises the stream. */
+int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream);
+int qx_batch_destroy(qx_batch_t* batch);
+
+/* -------------------------------------------------------------- force */
+
+/* Link gradient of a real function L of the solution x = A^{-1} b, in the
+   PyTorch convention for complex tensors (G = dL/dRe U + i dL/dIm U):
+   given x and lam = A^{-1} (dL/dRe x + i dL/dIm x) (packed FP64 even fields,
+   nrhs sources, summed over sources), with y = D_oe x, nu = D_oe lam,
+   W1 = (lam on even, y on odd), W2 = (x on even, nu on odd):
+     G_mu(z) = 1/2 eps(z) eta_mu(z) bc_mu(z) sum_s [W1 W1(z+mu)^dag + W2 W2(z+mu)^dag](z)
+   with eps = +1 (-1) on even (odd) z.  g64 must be an FP64 handle; tmp_odd
+   is scratch for two packed FP64 odd fields of nrhs sources
+   (2 * qx_field_bytes).  grad_U: canonical complex128 [4][V][3][3]. */
+int qx_force_from_fields(const qx_gauge_t* g64, int nrhs, const void* x_packed,
+                         const void* lam_packed, void* tmp_odd, void* grad_U, hipStream_t stream);
+
+/* Workspace bytes for qx_force. */
+int qx_force_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params, int nrhs,
+                             size_t* bytes);
+
+/* Action S = sum_s phi_s^dag A^{-1} phi_s and its link gradient G (as in
+   qx_force_from_fields with lam = x): one solve (params as for qx_cg_solve,
+   mass shared by all sources), one extra half-Dslash and one outer-product
+   pass.  phi: canonical [nrhs][V/2][3]; x_out (nullable): canonical solution.
+   Synchronises the stream. */
+int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_cg_params_t* params,
+             int nrhs, double mass, const void* phi, void* grad_U, double* S_out, void* x_out,
+             void* ws, size_t ws_bytes, qx_cg_stats_t* stats, hipStream_t stream);
+
+/* su(3) force along the generators T_a = lambda_a / 2 (Gell-Mann matrices)
+   for the left variation U -> exp(i e T_a) U: F^a = Re[i tr(T_a U G^dag)].
+   U, G: canonical complex128 [4][V][3][3]; F: double [4][V][8] (device). */
+int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_U, double* F,
+                 hipStream_t stream);
+
+/* ------------------------------------------------------------- tuning */
+
+/* Pick the launch shape (threads per block, XCD-aware block order) of the
+   Dslash kernels for this gauge handle and nrhs by timing the candidates on
+   the stream (scratch: two packed fields of nrhs sources of the handle's
+   precision, 2 * qx_field_bytes).  The result is cached per
+   (lattice, precision, link storage, nrhs) in the process and in the JSON
+   file named by QX_TUNE_CACHE if set.  Synchronises the stream. */
+int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream);
+
+/* Launch shape currently used for (handle, nrhs): threads per block and the
+   XCD-aware ordering flag. */
+int qx_get_launch(const qx_gauge_t* g, int nrhs, int* block, int* xcd_order);
+/* Force a launch shape (block in {64,128,256,512}); the next solves use it. */
+int qx_set_launch(const qx_gauge_t* g, int nrhs, int block, int xcd_order);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QX_H */

@@ -1,1 +1,408 @@
-"""MI355X-native staggered Dslash, even-odd CG and fermion force (binding placeholder)."""
+"""MI355X-native staggered Dslash, even-odd CG and fermion force.
+
+A thin ctypes binding of libqx.so (see include/qx.h for the C ABI).  PyTorch
+provides device memory and streams only; every step of the computation runs in
+the library's gfx950 kernels.  There is no CPU fallback: every entry point
+raises if libqx.so is missing or no GPU is present.
+
+Canonical layouts (complex128, on the GPU):
+  gauge field  U   (4, V, 3, 3)        mu-major, lexicographic sites (x fastest)
+  half field   b/x (nrhs, V/2, 3)      one parity, checkerboard order cb = lex >> 1
+  link gradient G  (4, V, 3, 3)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqx.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTUNITARY, ENOTCONVERGED, EBREAKDOWN, ENOLIB = range(8)
+BC_T_ANTIPERIODIC = 1
+PREC_F64, PREC_F32 = 0, 1
+CG_FP64, CG_MIXED_F32 = 0, 1
+
+_PREC = {"f64": PREC_F64, "f32": PREC_F32, PREC_F64: PREC_F64, PREC_F32: PREC_F32}
+
+
+class QXError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qx error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("mode", ctypes.c_int),
+                ("delta", ctypes.c_double), ("use_x0", ctypes.c_int), ("chunk", ctypes.c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("reliable_updates", ctypes.c_int), ("true_rel_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class _System(ctypes.Structure):
+    _fields_ = [("g64", ctypes.c_void_p), ("glo", ctypes.c_void_p), ("nrhs", ctypes.c_int),
+                ("masses", ctypes.POINTER(ctypes.c_double)), ("b", ctypes.c_void_p),
+                ("x", ctypes.c_void_p)]
+
+
+@dataclass
+class Stats:
+    status: int
+    iters: int
+    reliable_updates: int
+    true_rel_residual: float
+    seconds: float
+
+
+_lib = None
+_P, _I, _U32, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
+
+
+def load():
+    """Load libqx.so (built by paper_1612_02750_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise QXError(ENOLIB, f"{LIB_PATH} is missing: build it with python -m paper_1612_02750_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "qx_version": ([], _I),
+        "qx_last_error": ([], ctypes.c_char_p),
+        "qx_lattice_create": ([_P, _U32, _P], _I),
+        "qx_lattice_destroy": ([_P], _I),
+        "qx_lattice_volume": ([_P], ctypes.c_int64),
+        "qx_debug_index_maps": ([_P, _P, _P, _P], _I),
+        "qx_gauge_bytes": ([_P, _I, _I, _P], _I),
+        "qx_gauge_load": ([_P, _P, _I, _I, _P, _P, _P], _I),
+        "qx_gauge_destroy": ([_P], _I),
+        "qx_field_bytes": ([_P, _I, _I, _P], _I),
+        "qx_field_pack": ([_P, _I, _I, _P, _P, _P], _I),
+        "qx_field_unpack": ([_P, _I, _I, _P, _P, _P], _I),
+        "qx_dslash": ([_P, _I, _I, _P, _P, _P], _I),
+        "qx_apply_A": ([_P, _I, _P, _P, _P, _P, _P], _I),
+        "qx_cg_workspace_bytes": ([_P, _P, _I, _P], _I),
+        "qx_cg_solve": ([_P, _P, _P, _I, _P, _P, _P, _P, _SZ, _P, _P], _I),
+        "qx_batch_workspace_bytes": ([_I, _P, _P, _P], _I),
+        "qx_batch_create": ([_I, _P, _P, _P, _SZ, _P, _P], _I),
+        "qx_batch_solve": ([_P, _P, _P], _I),
+        "qx_batch_destroy": ([_P], _I),
+        "qx_force_from_fields": ([_P, _I, _P, _P, _P, _P, _P], _I),
+        "qx_force_workspace_bytes": ([_P, _P, _I, _P], _I),
+        "qx_force": ([_P, _P, _P, _I, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P, _P], _I),
+        "qx_force_su3": ([_P, _P, _P, _P, _P], _I),
+        "qx_tune_dslash": ([_P, _I, _P, _P], _I),
+        "qx_get_launch": ([_P, _I, _P, _P], _I),
+        "qx_set_launch": ([_P, _I, _I, _I], _I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise QXError(ENOLIB, "no GPU: the qx library has no CPU path")
+    return torch
+
+
+def _check(rc, allowed=(OK,)):
+    if rc not in allowed:
+        raise QXError(rc, load().qx_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t, dtype=None, shape=None, name="tensor"):
+    torch = _torch()
+    if not t.is_cuda:
+        raise QXError(EINVAL, f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise QXError(EINVAL, f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise QXError(EINVAL, f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise QXError(EINVAL, f"{name} must be contiguous")
+    return t
+
+
+def _bytes(n):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device="cuda")
+
+
+# ----------------------------------------------------------------- lattice
+
+class Lattice:
+    """A 4-D lattice with even extents (the even-odd split needs them)."""
+
+    def __init__(self, dims: Sequence[int], antiperiodic_t: bool = False):
+        L = load()
+        self.dims = tuple(int(d) for d in dims)
+        arr = (ctypes.c_int32 * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        _check(L.qx_lattice_create(arr, BC_T_ANTIPERIODIC if antiperiodic_t else 0,
+                                   ctypes.byref(h)))
+        self._h = h
+        self.V = int(L.qx_lattice_volume(h))
+        self.hv = self.V // 2
+        self.flags = BC_T_ANTIPERIODIC if antiperiodic_t else 0
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qx_lattice_destroy(self._h)
+            self._h = None
+
+    def field_bytes(self, nrhs: int, prec="f64") -> int:
+        n = ctypes.c_size_t()
+        _check(load().qx_field_bytes(self._h, nrhs, _PREC[prec], ctypes.byref(n)))
+        return n.value
+
+    def index_maps(self, stream=None):
+        """(lex_of_eo[V], nbr_eo[V, 8]) int32 computed by the device geometry code."""
+        torch = _torch()
+        lex = torch.empty(self.V, dtype=torch.int32, device="cuda")
+        nbr = torch.empty((self.V, 8), dtype=torch.int32, device="cuda")
+        _check(load().qx_debug_index_maps(self._h, _ptr(lex), _ptr(nbr), _stream(stream)))
+        return lex, nbr
+
+
+# ------------------------------------------------------------------- gauge
+
+class Gauge:
+    """Packed gauge field (eta and boundary signs folded in) of one precision."""
+
+    def __init__(self, lat: Lattice, U, prec="f64", recon: int = 18, stream=None):
+        torch = _torch()
+        L = load()
+        _dev(U, torch.complex128, (4, lat.V, 3, 3), "U")
+        self.lat = lat
+        self.prec = _PREC[prec]
+        self.recon = int(recon)
+        n = ctypes.c_size_t()
+        _check(L.qx_gauge_bytes(lat._h, self.prec, self.recon, ctypes.byref(n)))
+        self.packed = _bytes(n.value)
+        h = ctypes.c_void_p()
+        _check(L.qx_gauge_load(lat._h, _ptr(U), self.prec, self.recon, _ptr(self.packed),
+                               _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qx_gauge_destroy(self._h)
+            self._h = None
+
+    def tune(self, nrhs: int = 1, stream=None):
+        scratch = _bytes(2 * self.lat.field_bytes(nrhs, self.prec))
+        _check(load().qx_tune_dslash(self._h, nrhs, _ptr(scratch), _stream(stream)))
+        return self.launch(nrhs)
+
+    def launch(self, nrhs: int = 1):
+        b, x = ctypes.c_int(), ctypes.c_int()
+        _check(load().qx_get_launch(self._h, nrhs, ctypes.byref(b), ctypes.byref(x)))
+        return b.value, x.value
+
+    def set_launch(self, nrhs: int, block: int, xcd_order: int):
+        _check(load().qx_set_launch(self._h, nrhs, block, xcd_order))
+
+
+# ------------------------------------------------------------------ fields
+
+def pack(lat: Lattice, canon, prec="f64", stream=None):
+    """canonical complex128 (nrhs, V/2, 3) -> packed bytes."""
+    torch = _torch()
+    _dev(canon, torch.complex128, None, "field")
+    nrhs = canon.shape[0]
+    assert tuple(canon.shape[1:]) == (lat.hv, 3), "field must be (nrhs, V/2, 3)"
+    out = _bytes(lat.field_bytes(nrhs, prec))
+    _check(load().qx_field_pack(lat._h, nrhs, _PREC[prec], _ptr(canon), _ptr(out), _stream(stream)))
+    return out
+
+
+def unpack(lat: Lattice, packed, nrhs: int, prec="f64", stream=None):
+    torch = _torch()
+    out = torch.empty((nrhs, lat.hv, 3), dtype=torch.complex128, device="cuda")
+    _check(load().qx_field_unpack(lat._h, nrhs, _PREC[prec], _ptr(packed), _ptr(out),
+                                  _stream(stream)))
+    return out
+
+
+def dslash(g: Gauge, packed_in, out_parity: int, nrhs: int = 1, out=None, stream=None):
+    """D (with 1/2) from parity 1 - out_parity to out_parity on packed fields."""
+    if out is None:
+        out = _bytes(g.lat.field_bytes(nrhs, g.prec))
+    _check(load().qx_dslash(g._h, out_parity, nrhs, _ptr(packed_in), _ptr(out), _stream(stream)))
+    return out
+
+
+def apply_A(g: Gauge, packed_in, masses: Sequence[float], out=None, tmp=None, stream=None):
+    """(m^2 - D_eo D_oe) on packed even fields, one mass per source."""
+    nrhs = len(masses)
+    fb = g.lat.field_bytes(nrhs, g.prec)
+    out = _bytes(fb) if out is None else out
+    tmp = _bytes(fb) if tmp is None else tmp
+    m = (ctypes.c_double * nrhs)(*masses)
+    _check(load().qx_apply_A(g._h, nrhs, m, _ptr(packed_in), _ptr(out), _ptr(tmp),
+                             _stream(stream)))
+    return out
+
+
+# ------------------------------------------------------------------ solver
+
+def _params(tol, max_iter, mode, delta, use_x0, chunk):
+    return _Params(float(tol), int(max_iter), int(mode), float(delta), int(use_x0), int(chunk))
+
+
+def _stats(arr, n):
+    return [Stats(arr[i].status, arr[i].iters, arr[i].reliable_updates,
+                  arr[i].true_rel_residual, arr[i].seconds) for i in range(n)]
+
+
+def cg(g64: Gauge, b, masses, glo: Optional[Gauge] = None, tol=1e-10, max_iter=100000,
+       mode=None, delta=0.1, x0=None, chunk=0, ws=None, stream=None, raise_on_fail=True):
+    """Solve (m_s^2 - D_eo D_oe) x_s = b_s; b (nrhs, V/2, 3) complex128.  Returns (x, stats).
+    mode defaults to mixed FP32/FP64 when glo is given, else FP64."""
+    torch = _torch()
+    L = load()
+    lat = g64.lat
+    _dev(b, torch.complex128, None, "b")
+    nrhs = b.shape[0]
+    if isinstance(masses, (int, float)):
+        masses = [float(masses)] * nrhs
+    if mode is None:
+        mode = CG_MIXED_F32 if glo is not None else CG_FP64
+    p = _params(tol, max_iter, mode, delta, x0 is not None, chunk)
+    n = ctypes.c_size_t()
+    _check(L.qx_cg_workspace_bytes(lat._h, ctypes.byref(p), nrhs, ctypes.byref(n)))
+    if ws is None:
+        ws = _bytes(n.value)
+    x = x0.clone() if x0 is not None else torch.empty_like(b)
+    st = (_Stats * nrhs)()
+    m = (ctypes.c_double * nrhs)(*masses)
+    rc = L.qx_cg_solve(g64._h, glo._h if glo is not None else None, ctypes.byref(p), nrhs, m,
+                       _ptr(b), _ptr(x), _ptr(ws), ws.numel(), st, _stream(stream))
+    if raise_on_fail:
+        _check(rc)
+    return x, _stats(st, nrhs)
+
+
+class Batch:
+    """Many systems (lattices of any size, several sources each) solved together:
+    one launch per CG step for all of them, replayed from a captured HIP graph."""
+
+    def __init__(self, systems, tol=1e-10, max_iter=100000, mode=CG_MIXED_F32, delta=0.1,
+                 chunk=0, stream=None):
+        """systems: list of (g64, glo_or_None, b (nrhs,V/2,3), masses, x_out)."""
+        L = load()
+        self.systems = systems
+        self.p = _params(tol, max_iter, mode, delta, 0, chunk)
+        arr = (_System * len(systems))()
+        self._masses = []
+        self.nsrc = 0
+        for i, (g64, glo, b, masses, x) in enumerate(systems):
+            nrhs = b.shape[0]
+            m = (ctypes.c_double * nrhs)(*masses)
+            self._masses.append(m)
+            arr[i] = _System(g64._h, glo._h if glo is not None else None, nrhs,
+                             ctypes.cast(m, ctypes.POINTER(ctypes.c_double)), b.data_ptr(),
+                             x.data_ptr())
+            self.nsrc += nrhs
+        self._arr = arr
+        n = ctypes.c_size_t()
+        _check(L.qx_batch_workspace_bytes(len(systems), arr, ctypes.byref(self.p),
+                                          ctypes.byref(n)))
+        self.ws = _bytes(n.value)
+        h = ctypes.c_void_p()
+        _check(L.qx_batch_create(len(systems), arr, ctypes.byref(self.p), _ptr(self.ws),
+                                 self.ws.numel(), _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def solve(self, stream=None, raise_on_fail=True):
+        st = (_Stats * self.nsrc)()
+        rc = load().qx_batch_solve(self._h, st, _stream(stream))
+        if raise_on_fail:
+            _check(rc)
+        return _stats(st, self.nsrc)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qx_batch_destroy(self._h)
+            self._h = None
+
+
+# ------------------------------------------------------------------- force
+
+def force(g64: Gauge, phi, mass: float, glo: Optional[Gauge] = None, tol=1e-10,
+          max_iter=100000, mode=None, delta=0.1, stream=None):
+    """S = sum_s phi_s^dag A^-1 phi_s and G = dS/dRe U + i dS/dIm U (4,V,3,3).
+    Returns (S, G, x, stats)."""
+    torch = _torch()
+    L = load()
+    lat = g64.lat
+    _dev(phi, torch.complex128, None, "phi")
+    nrhs = phi.shape[0]
+    if mode is None:
+        mode = CG_MIXED_F32 if glo is not None else CG_FP64
+    p = _params(tol, max_iter, mode, delta, 0, 0)
+    n = ctypes.c_size_t()
+    _check(L.qx_force_workspace_bytes(lat._h, ctypes.byref(p), nrhs, ctypes.byref(n)))
+    ws = _bytes(n.value)
+    G = torch.empty((4, lat.V, 3, 3), dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(phi)
+    S = ctypes.c_double()
+    st = (_Stats * nrhs)()
+    _check(L.qx_force(g64._h, glo._h if glo is not None else None, ctypes.byref(p), nrhs,
+                      float(mass), _ptr(phi), _ptr(G), ctypes.byref(S), _ptr(x), _ptr(ws),
+                      ws.numel(), st, _stream(stream)))
+    return S.value, G, x, _stats(st, nrhs)
+
+
+def force_from_fields(g64: Gauge, x, lam, stream=None):
+    """Link gradient of L(x), x = A^-1 b, given lam = A^-1 dL/dx; x, lam canonical."""
+    torch = _torch()
+    lat = g64.lat
+    nrhs = x.shape[0]
+    xp = pack(lat, x, "f64", stream)
+    lp = xp if lam is x else pack(lat, lam, "f64", stream)
+    tmp = _bytes(2 * lat.field_bytes(nrhs, "f64"))
+    G = torch.empty((4, lat.V, 3, 3), dtype=torch.complex128, device="cuda")
+    _check(load().qx_force_from_fields(g64._h, nrhs, _ptr(xp), _ptr(lp), _ptr(tmp), _ptr(G),
+                                       _stream(stream)))
+    return G
+
+
+def force_su3(lat: Lattice, U, G, stream=None):
+    """F^a = Re[i tr(T_a U G^dag)], T_a = lambda_a / 2: (4, V, 8) float64."""
+    torch = _torch()
+    F = torch.empty((4, lat.V, 8), dtype=torch.float64, device="cuda")
+    _check(load().qx_force_su3(lat._h, _ptr(U), _ptr(G), _ptr(F), _stream(stream)))
+    return F
+
+
+def __getattr__(name):
+    # the autograd wrappers import torch; load them on first use only
+    if name in ("StaggeredSolve", "staggered_action", "StaggeredAction"):
+        from . import autograd
+
+        return getattr(autograd, name)
+    raise AttributeError(name)

@@ -1,0 +1,895 @@
+// C ABI of libqx.so: handles, argument checks, the solver driver (host side of
+// the conjugate-gradient engine), batches with HIP-graph replay, the force
+// entry points and the launch-shape tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/qx.h"
+#include "qx_internal.h"
+#include "qx_launch.h"
+
+using namespace qx;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(QX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define QX_HIP(call, what)                    \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ handles
+
+struct qx_lattice {
+  int32_t dims[4];
+  uint32_t flags;
+  Geo geo;
+  int64_t V;
+};
+
+struct qx_gauge {
+  int32_t dims[4];
+  uint32_t flags;
+  Geo geo;
+  int prec, recon;
+  const void* packed;
+  std::map<int, LaunchShape> shapes;  // per nrhs
+};
+
+namespace {
+
+Geo make_geo(const int32_t d[4], uint32_t flags) {
+  Geo g;
+  g.L0 = d[0];
+  g.L1 = d[1];
+  g.L2 = d[2];
+  g.L3 = d[3];
+  g.Lh = d[0] / 2;
+  g.hv = (int)((int64_t)d[0] * d[1] * d[2] * d[3] / 2);
+  g.s1 = g.Lh;
+  g.s2 = g.Lh * d[1];
+  g.s3 = g.Lh * d[1] * d[2];
+  g.anti_t = (flags & QX_BC_T_ANTIPERIODIC) ? 1 : 0;
+  return g;
+}
+
+bool same_lattice(const qx_gauge* a, const qx_gauge* b) {
+  return !memcmp(a->dims, b->dims, sizeof a->dims) && a->flags == b->flags;
+}
+
+// ------------------------------------------------------------ tuning cache
+
+std::mutex g_tune_mu;
+std::map<std::string, LaunchShape> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const qx_gauge* g, int nrhs) {
+  char buf[128];
+  snprintf(buf, sizeof buf, "gfx950:%dx%dx%dx%d:p%d:r%d:n%d", g->dims[0], g->dims[1], g->dims[2],
+           g->dims[3], g->prec, g->recon, nrhs);
+  return buf;
+}
+
+// The cache file is a flat JSON object {"key": [block, xcd], ...}.
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("QX_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+  fclose(f);
+  size_t i = 0;
+  while ((i = s.find('"', i)) != std::string::npos) {
+    const size_t j = s.find('"', i + 1);
+    if (j == std::string::npos) break;
+    const std::string key = s.substr(i + 1, j - i - 1);
+    int b = 0, x = 0;
+    if (sscanf(s.c_str() + j + 1, " : [ %d , %d ]", &b, &x) == 2 &&
+        (b == 64 || b == 128 || b == 256 || b == 512))
+      g_tune[key] = LaunchShape{b, x ? 1 : 0};
+    i = j + 1;
+  }
+}
+
+void tune_save_locked() {
+  const char* path = getenv("QX_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t k = 0;
+  for (const auto& kv : g_tune)
+    fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.block, kv.second.xcd,
+            ++k < g_tune.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+LaunchShape shape_for(const qx_gauge* g, int nrhs) {
+  auto it = g->shapes.find(nrhs);
+  if (it != g->shapes.end()) return it->second;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto jt = g_tune.find(tune_key(g, nrhs));
+  if (jt != g_tune.end()) return jt->second;
+  return LaunchShape{};
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------- misc
+
+extern "C" int qx_version(void) { return QX_VERSION; }
+
+extern "C" const char* qx_last_error(void) { return g_err.c_str(); }
+
+// ----------------------------------------------------------------- lattice
+
+extern "C" int qx_lattice_create(const int32_t dims[4], uint32_t flags, qx_lattice_t** out) {
+  if (!dims || !out) return fail(QX_EINVAL, "qx_lattice_create: NULL argument");
+  if (flags & ~(uint32_t)QX_BC_T_ANTIPERIODIC)
+    return fail(QX_EINVAL, "qx_lattice_create: unknown flags 0x%x", flags);
+  int64_t V = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (dims[mu] < 2 || (dims[mu] & 1))
+      return fail(QX_EINVAL, "qx_lattice_create: extent %d of direction %d must be even and >= 2",
+                  dims[mu], mu);
+    V *= dims[mu];
+  }
+  if (V >= ((int64_t)1 << 31)) return fail(QX_EINVAL, "qx_lattice_create: volume %lld too large", (long long)V);
+  qx_lattice* l = new (std::nothrow) qx_lattice;
+  if (!l) return fail(QX_ENOMEM, "qx_lattice_create: out of host memory");
+  memcpy(l->dims, dims, sizeof l->dims);
+  l->flags = flags;
+  l->geo = make_geo(dims, flags);
+  l->V = V;
+  *out = l;
+  return QX_OK;
+}
+
+extern "C" int qx_lattice_destroy(qx_lattice_t* lat) {
+  delete lat;
+  return QX_OK;
+}
+
+extern "C" int64_t qx_lattice_volume(const qx_lattice_t* lat) { return lat ? lat->V : -1; }
+
+extern "C" int qx_debug_index_maps(const qx_lattice_t* lat, int32_t* lex_of_eo, int32_t* nbr_eo,
+                                   hipStream_t stream) {
+  if (!lat || !lex_of_eo || !nbr_eo) return fail(QX_EINVAL, "qx_debug_index_maps: NULL argument");
+  QX_HIP(launch_index_maps(lat->geo, lex_of_eo, nbr_eo, stream), "qx_debug_index_maps");
+  return QX_OK;
+}
+
+// ------------------------------------------------------------------- gauge
+
+namespace {
+bool prec_ok(int p) { return p == QX_PREC_F64 || p == QX_PREC_F32; }
+bool recon_ok(int r) { return r == QX_RECON_18 || r == QX_RECON_12; }
+size_t gauge_bytes(const Geo& g, int prec, int recon) {
+  return (size_t)8 * g.hv * (recon == 12 ? 6 : 9) * cplx_bytes(prec);
+}
+size_t field_bytes(const Geo& g, int nrhs, int prec) {
+  return (size_t)nrhs * 3 * g.hv * cplx_bytes(prec);
+}
+}  // namespace
+
+extern "C" int qx_gauge_bytes(const qx_lattice_t* lat, int prec, int recon, size_t* bytes) {
+  if (!lat || !bytes || !prec_ok(prec) || !recon_ok(recon))
+    return fail(QX_EINVAL, "qx_gauge_bytes: bad argument");
+  *bytes = gauge_bytes(lat->geo, prec, recon);
+  return QX_OK;
+}
+
+extern "C" int qx_gauge_load(const qx_lattice_t* lat, const void* U_canon, int prec, int recon,
+                             void* packed, hipStream_t stream, qx_gauge_t** out) {
+  if (!lat || !U_canon || !packed || !out) return fail(QX_EINVAL, "qx_gauge_load: NULL argument");
+  if (!prec_ok(prec) || !recon_ok(recon))
+    return fail(QX_EINVAL, "qx_gauge_load: bad precision %d or link storage %d", prec, recon);
+  unsigned long long* d_err = nullptr;
+  if (recon == 12) {
+    QX_HIP(hipMalloc(&d_err, sizeof *d_err), "qx_gauge_load: hipMalloc");
+    hipError_t e = hipMemsetAsync(d_err, 0, sizeof *d_err, stream);
+    if (e != hipSuccess) {
+      hipFree(d_err);
+      return hip_fail(e, "qx_gauge_load: hipMemsetAsync");
+    }
+  }
+  hipError_t e = launch_pack_gauge(lat->geo, U_canon, prec, recon, packed, d_err, stream);
+  if (e != hipSuccess) {
+    if (d_err) hipFree(d_err);
+    return hip_fail(e, "qx_gauge_load: pack kernel");
+  }
+  if (recon == 12) {
+    unsigned long long bits = 0;
+    e = hipMemcpyAsync(&bits, d_err, sizeof bits, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    hipFree(d_err);
+    if (e != hipSuccess) return hip_fail(e, "qx_gauge_load: unitarity check");
+    double err;
+    memcpy(&err, &bits, sizeof err);
+    if (!(err <= 1e-10))
+      return fail(QX_ENOTUNITARY,
+                  "qx_gauge_load: 12-real links need SU(3) links; max |row2 - conj(row0 x row1)| = %g",
+                  err);
+  }
+  qx_gauge* g = new (std::nothrow) qx_gauge;
+  if (!g) return fail(QX_ENOMEM, "qx_gauge_load: out of host memory");
+  memcpy(g->dims, lat->dims, sizeof g->dims);
+  g->flags = lat->flags;
+  g->geo = lat->geo;
+  g->prec = prec;
+  g->recon = recon;
+  g->packed = packed;
+  *out = g;
+  return QX_OK;
+}
+
+extern "C" int qx_gauge_destroy(qx_gauge_t* g) {
+  delete g;
+  return QX_OK;
+}
+
+// ------------------------------------------------------------------ fields
+
+extern "C" int qx_field_bytes(const qx_lattice_t* lat, int nrhs, int prec, size_t* bytes) {
+  if (!lat || !bytes || nrhs < 1 || !prec_ok(prec))
+    return fail(QX_EINVAL, "qx_field_bytes: bad argument");
+  *bytes = field_bytes(lat->geo, nrhs, prec);
+  return QX_OK;
+}
+
+extern "C" int qx_field_pack(const qx_lattice_t* lat, int nrhs, int prec, const void* canon,
+                             void* packed, hipStream_t stream) {
+  if (!lat || !canon || !packed || nrhs < 1 || !prec_ok(prec))
+    return fail(QX_EINVAL, "qx_field_pack: bad argument");
+  QX_HIP(launch_pack_field(lat->geo, nrhs, prec, canon, packed, stream), "qx_field_pack");
+  return QX_OK;
+}
+
+extern "C" int qx_field_unpack(const qx_lattice_t* lat, int nrhs, int prec, const void* packed,
+                               void* canon, hipStream_t stream) {
+  if (!lat || !canon || !packed || nrhs < 1 || !prec_ok(prec))
+    return fail(QX_EINVAL, "qx_field_unpack: bad argument");
+  QX_HIP(launch_unpack_field(lat->geo, nrhs, prec, packed, canon, stream), "qx_field_unpack");
+  return QX_OK;
+}
+
+// --------------------------------------------------------------- operators
+
+extern "C" int qx_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const void* in, void* out,
+                         hipStream_t stream) {
+  if (!g || !in || !out || nrhs < 1 || (out_parity != 0 && out_parity != 1))
+    return fail(QX_EINVAL, "qx_dslash: bad argument");
+  if (in == out) return fail(QX_EINVAL, "qx_dslash: in and out must not alias");
+  QX_HIP(launch_dslash(g->geo, g->prec, g->recon, g->packed, out_parity, in, out, nrhs, 0.5,
+                       shape_for(g, nrhs), stream),
+         "qx_dslash");
+  return QX_OK;
+}
+
+extern "C" int qx_apply_A(const qx_gauge_t* g, int nrhs, const double* masses, const void* in,
+                          void* out, void* tmp_odd, hipStream_t stream) {
+  if (!g || !masses || !in || !out || !tmp_odd || nrhs < 1)
+    return fail(QX_EINVAL, "qx_apply_A: bad argument");
+  if (in == out || in == tmp_odd || out == tmp_odd)
+    return fail(QX_EINVAL, "qx_apply_A: buffers must not alias");
+  std::vector<double> m2(nrhs);
+  for (int k = 0; k < nrhs; ++k) m2[k] = masses[k] * masses[k];
+  QX_HIP(launch_apply_A(g->geo, g->prec, g->recon, g->packed, nrhs, m2.data(), in, out, tmp_odd,
+                        shape_for(g, nrhs), stream),
+         "qx_apply_A");
+  return QX_OK;
+}
+
+// ------------------------------------------------------------------ solver
+
+namespace {
+
+constexpr int kMaxSrcPerSys = 12;
+constexpr double kStopFactor = 0.9;  // stop at an FP64 residual of 0.9 tol
+
+struct SysSpec {
+  const qx_gauge* g64;
+  const qx_gauge* glo;  // == g64 for QX_CG_FP64
+  int nrhs;
+  std::vector<double> masses;
+  const void* b;  // canonical, already offset to the first source of this system
+  void* x;
+};
+
+struct Layout {
+  size_t sys_off = 0, st_off = 0, total = 0;
+  std::vector<size_t> counter_off, partial_off, vlo_off, vhi_off;
+  std::vector<int> nblk_max;
+};
+
+int lo_prec(const qx_cg_params_t* p) { return p->mode == QX_CG_FP64 ? QX_PREC_F64 : QX_PREC_F32; }
+
+Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
+  Layout L;
+  size_t off = 0;
+  L.sys_off = off;
+  off = align_up(off + sizeof(SysDesc) * specs.size(), 256);
+  L.st_off = off;
+  size_t nsrc = 0;
+  for (const auto& s : specs) nsrc += s.nrhs;
+  off = align_up(off + sizeof(SrcState) * nsrc, 256);
+  for (const auto& s : specs) {
+    const Geo& g = s.g64->geo;
+    const int nblk = (g.hv + 63) / 64;
+    L.nblk_max.push_back(nblk);
+    L.counter_off.push_back(off);
+    off = align_up(off + 256, 256);
+    L.partial_off.push_back(off);
+    off = align_up(off + sizeof(double) * s.nrhs * nblk, 256);
+    L.vlo_off.push_back(off);
+    off = align_up(off + 5 * field_bytes(g, s.nrhs, prec_lo), 256);
+    L.vhi_off.push_back(off);
+    off = align_up(off + 4 * field_bytes(g, s.nrhs, QX_PREC_F64), 256);
+  }
+  L.total = off;
+  return L;
+}
+
+int check_params(const qx_cg_params_t* p) {
+  if (!p) return fail(QX_EINVAL, "solver: NULL params");
+  if (!(p->tol > 0.0) || p->max_iter < 1) return fail(QX_EINVAL, "solver: tol must be > 0 and max_iter >= 1");
+  if (p->mode != QX_CG_FP64 && p->mode != QX_CG_MIXED_F32)
+    return fail(QX_EINVAL, "solver: unknown mode %d", p->mode);
+  if (p->mode == QX_CG_MIXED_F32 && !(p->delta > 0.0 && p->delta < 1.0))
+    return fail(QX_EINVAL, "solver: delta must be in (0, 1) for the mixed mode");
+  if (p->chunk < 0) return fail(QX_EINVAL, "solver: chunk must be >= 0");
+  return QX_OK;
+}
+
+int check_system(const qx_gauge* g64, const qx_gauge* glo, const qx_cg_params_t* p) {
+  if (!g64) return fail(QX_EINVAL, "solver: NULL FP64 gauge handle");
+  if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "solver: g64 must be an FP64 gauge handle");
+  if (p->mode == QX_CG_MIXED_F32) {
+    if (!glo) return fail(QX_EINVAL, "solver: the mixed mode needs an FP32 gauge handle");
+    if (glo->prec != QX_PREC_F32) return fail(QX_EINVAL, "solver: glo must be an FP32 gauge handle");
+    if (!same_lattice(g64, glo)) return fail(QX_EINVAL, "solver: g64 and glo are on different lattices");
+  }
+  return QX_OK;
+}
+
+// Split a caller system into pieces of at most kMaxSrcPerSys sources.
+void add_specs(std::vector<SysSpec>& out, const qx_gauge* g64, const qx_gauge* glo,
+               const qx_cg_params_t* p, int nrhs, const double* masses, const void* b, void* x) {
+  const size_t fb = field_bytes(g64->geo, 1, QX_PREC_F64);  // canonical bytes per source
+  for (int k0 = 0; k0 < nrhs; k0 += kMaxSrcPerSys) {
+    SysSpec s;
+    s.g64 = g64;
+    s.glo = p->mode == QX_CG_FP64 ? g64 : glo;
+    s.nrhs = std::min(kMaxSrcPerSys, nrhs - k0);
+    s.masses.assign(masses + k0, masses + k0 + s.nrhs);
+    s.b = (const char*)b + k0 * fb;
+    s.x = (char*)x + k0 * fb;
+    out.push_back(s);
+  }
+}
+
+}  // namespace
+
+// A planned solve: systems, their device descriptors and states inside the
+// caller's workspace, a pinned host mirror of the states, and (optionally) the
+// captured graph of one chunk of iterations.
+struct qx_batch {
+  std::vector<SysSpec> specs;
+  qx_cg_params_t params;
+  Layout layout;
+  EngineCfg cfg;
+  std::vector<SysDesc> sys;
+  std::vector<SrcState> st0;
+  SrcState* h_st = nullptr;  // pinned
+  char* ws = nullptr;
+  int chunk = 16, ru_every = 4;
+  bool use_graph = false;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+
+  ~qx_batch() {
+    if (graph) hipGraphExecDestroy(graph);
+    if (h_st) hipHostFree(h_st);
+  }
+};
+
+namespace {
+
+int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
+  const qx_cg_params_t& p = B->params;
+  const int prec_lo = lo_prec(&p);
+  B->layout = plan_layout(B->specs, prec_lo);
+  if (!ws) return fail(QX_EINVAL, "solver: NULL workspace");
+  if (ws_bytes < B->layout.total)
+    return fail(QX_ENOMEM, "solver: workspace of %zu bytes, %zu needed", ws_bytes, B->layout.total);
+  B->ws = (char*)ws;
+
+  // launch shape: the tuned (or default) shape of the first system's inner links
+  const SysSpec& s0 = B->specs[0];
+  LaunchShape sh = shape_for(s0.glo, s0.nrhs);
+  int nb = 1;
+  for (const auto& s : B->specs) nb = std::max(nb, s.nrhs);
+
+  B->cfg = EngineCfg{};
+  B->cfg.prec_lo = prec_lo;
+  B->cfg.recon_lo = s0.glo->recon;
+  B->cfg.recon_hi = s0.g64->recon;
+  for (const auto& s : B->specs) {
+    if (s.glo->recon != B->cfg.recon_lo || s.g64->recon != B->cfg.recon_hi)
+      return fail(QX_EINVAL, "batch: all systems must use the same link storage");
+  }
+  B->cfg.nb = nb;
+  B->cfg.shape = sh;
+  B->cfg.nsys = (int)B->specs.size();
+  B->cfg.d_sys = (const SysDesc*)(B->ws + B->layout.sys_off);
+  B->cfg.d_st = (SrcState*)(B->ws + B->layout.st_off);
+
+  B->sys.clear();
+  B->st0.clear();
+  int blk = 0, src = 0;
+  const double stop = kStopFactor * p.tol;
+  for (size_t i = 0; i < B->specs.size(); ++i) {
+    const SysSpec& s = B->specs[i];
+    SysDesc d{};
+    d.g = s.g64->geo;
+    d.nsrc = s.nrhs;
+    d.src0 = src;
+    d.blk0 = blk;
+    d.nblk = (d.g.hv + sh.block - 1) / sh.block;
+    d.links_lo = s.glo->packed;
+    d.links_hi = s.g64->packed;
+    d.vlo = B->ws + B->layout.vlo_off[i];
+    d.vhi = B->ws + B->layout.vhi_off[i];
+    d.partials = (double*)(B->ws + B->layout.partial_off[i]);
+    d.counter = (unsigned*)(B->ws + B->layout.counter_off[i]);
+    blk += d.nblk;
+    src += d.nsrc;
+    B->sys.push_back(d);
+    for (int k = 0; k < s.nrhs; ++k) {
+      SrcState q{};
+      q.m2 = s.masses[k] * s.masses[k];
+      q.delta = p.mode == QX_CG_FP64 ? 0.0 : p.delta;
+      q.stop2 = stop * stop;  // multiplied by |b|^2 on the device
+      q.phase = PH_RU;
+      q.reason = RU_INIT;
+      q.status = QX_ENOTCONVERGED;
+      q.max_iter = p.max_iter;
+      B->st0.push_back(q);
+    }
+  }
+  B->cfg.nblk_total = blk;
+  B->cfg.nsrc_total = src;
+  if (!engine_supported(B->cfg)) return fail(QX_EINVAL, "solver: unsupported configuration");
+  if (!B->h_st) QX_HIP(hipHostMalloc((void**)&B->h_st, sizeof(SrcState) * src), "solver: hipHostMalloc");
+  B->chunk = p.chunk > 0 ? p.chunk : 16;
+  B->ru_every = std::min(B->chunk, 4);
+  return QX_OK;
+}
+
+// Upload the descriptor table and clear the last-block counters.
+int upload_plan(qx_batch* B, hipStream_t s) {
+  QX_HIP(hipMemcpyAsync(B->ws + B->layout.sys_off, B->sys.data(), sizeof(SysDesc) * B->sys.size(),
+                        hipMemcpyHostToDevice, s),
+         "solver: descriptor upload");
+  for (size_t i = 0; i < B->sys.size(); ++i)
+    QX_HIP(hipMemsetAsync(B->ws + B->layout.counter_off[i], 0, 256, s), "solver: counter reset");
+  QX_HIP(hipStreamSynchronize(s), "solver: upload");
+  return QX_OK;
+}
+
+// The work of one chunk: `chunk` inner iterations with a reliable-update
+// sequence after every `ru_every` of them and at the end, then a copy of the
+// source states to the pinned host mirror.
+int enqueue_chunk(qx_batch* B, hipStream_t s) {
+  for (int i = 0; i < B->chunk; ++i) {
+    QX_HIP(engine_iteration(B->cfg, s), "solver: iteration");
+    if ((i + 1) % B->ru_every == 0 || i + 1 == B->chunk)
+      QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
+  }
+  QX_HIP(hipMemcpyAsync(B->h_st, B->cfg.d_st, sizeof(SrcState) * B->cfg.nsrc_total,
+                        hipMemcpyDeviceToHost, s),
+         "solver: state readback");
+  return QX_OK;
+}
+
+int capture_graph(qx_batch* B, hipStream_t s) {
+  if (B->graph) {
+    hipGraphExecDestroy(B->graph);
+    B->graph = nullptr;
+  }
+  if (!B->use_graph || s == nullptr) return QX_OK;
+  hipGraph_t graph = nullptr;
+  QX_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "batch: begin capture");
+  int rc = enqueue_chunk(B, s);
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  if (rc != QX_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "batch: end capture");
+  e = hipGraphInstantiate(&B->graph, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    B->graph = nullptr;
+    return hip_fail(e, "batch: graph instantiate");
+  }
+  B->graph_stream = s;
+  return QX_OK;
+}
+
+int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const qx_cg_params_t& p = B->params;
+  // initial states
+  memcpy(B->h_st, B->st0.data(), sizeof(SrcState) * B->st0.size());
+  QX_HIP(hipMemcpyAsync(B->cfg.d_st, B->h_st, sizeof(SrcState) * B->st0.size(),
+                        hipMemcpyHostToDevice, s),
+         "solver: state upload");
+  for (size_t i = 0; i < B->specs.size(); ++i) {
+    const SysSpec& sp = B->specs[i];
+    const SysDesc& d = B->sys[i];
+    const size_t vs = field_bytes(d.g, d.nsrc, QX_PREC_F64);
+    QX_HIP(launch_pack_field(d.g, d.nsrc, QX_PREC_F64, sp.b, (char*)d.vhi + 2 * vs, s),
+           "solver: pack b");
+    if (p.use_x0)
+      QX_HIP(launch_pack_field(d.g, d.nsrc, QX_PREC_F64, sp.x, d.vhi, s), "solver: pack x0");
+  }
+  QX_HIP(engine_init(B->cfg, p.use_x0 ? 0 : 1, s), "solver: init");
+  QX_HIP(engine_reliable_update(B->cfg, s), "solver: initial residual");
+  if (B->use_graph && B->graph && B->graph_stream != s) {
+    int rc = capture_graph(B, s);
+    if (rc != QX_OK) return rc;
+  }
+  const long max_chunks = (long)p.max_iter + 64;
+  bool done = false;
+  for (long c = 0; c < max_chunks && !done; ++c) {
+    if (B->graph) {
+      QX_HIP(hipGraphLaunch(B->graph, s), "solver: graph launch");
+    } else {
+      int rc = enqueue_chunk(B, s);
+      if (rc != QX_OK) return rc;
+    }
+    QX_HIP(hipStreamSynchronize(s), "solver: chunk");
+    done = true;
+    for (int k = 0; k < B->cfg.nsrc_total; ++k)
+      if (B->h_st[k].phase != PH_DONE) done = false;
+  }
+  if (!done) return fail(QX_EHIP, "solver: the state machine did not terminate");
+  for (size_t i = 0; i < B->specs.size(); ++i) {
+    const SysDesc& d = B->sys[i];
+    QX_HIP(launch_unpack_field(d.g, d.nsrc, QX_PREC_F64, d.vhi, B->specs[i].x, s),
+           "solver: unpack x");
+  }
+  QX_HIP(hipStreamSynchronize(s), "solver: finish");
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int rc = QX_OK;
+  for (int k = 0; k < B->cfg.nsrc_total; ++k) {
+    const SrcState& q = B->h_st[k];
+    if (stats) {
+      stats[k].status = q.status;
+      stats[k].iters = q.iters;
+      stats[k].reliable_updates = q.updates;
+      stats[k].true_rel_residual = q.relres;
+      stats[k].seconds = secs;
+    }
+    if (q.status != QX_OK && rc == QX_OK) rc = q.status;
+  }
+  if (rc != QX_OK)
+    fail(rc, rc == QX_ENOTCONVERGED ? "solver: max_iter reached before the tolerance"
+                                    : "solver: breakdown (<p,Ap> <= 0 or non-finite values)");
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int qx_cg_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params,
+                                     int nrhs, size_t* bytes) {
+  if (!lat || !bytes || nrhs < 1) return fail(QX_EINVAL, "qx_cg_workspace_bytes: bad argument");
+  int rc = check_params(params);
+  if (rc) return rc;
+  qx_gauge tmp;
+  memcpy(tmp.dims, lat->dims, sizeof tmp.dims);
+  tmp.flags = lat->flags;
+  tmp.geo = lat->geo;
+  tmp.prec = QX_PREC_F64;
+  tmp.recon = 18;
+  tmp.packed = nullptr;
+  std::vector<SysSpec> specs;
+  std::vector<double> m(nrhs, 0.0);
+  add_specs(specs, &tmp, &tmp, params, nrhs, m.data(), nullptr, nullptr);
+  *bytes = plan_layout(specs, lo_prec(params)).total;
+  return QX_OK;
+}
+
+extern "C" int qx_cg_solve(const qx_gauge_t* g64, const qx_gauge_t* glo,
+                           const qx_cg_params_t* params, int nrhs, const double* masses,
+                           const void* b, void* x, void* ws, size_t ws_bytes,
+                           qx_cg_stats_t* stats, hipStream_t stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  rc = check_system(g64, glo, params);
+  if (rc) return rc;
+  if (nrhs < 1 || !masses || !b || !x) return fail(QX_EINVAL, "qx_cg_solve: bad argument");
+  qx_batch B;
+  B.params = *params;
+  add_specs(B.specs, g64, glo, params, nrhs, masses, b, x);
+  rc = build_plan(&B, ws, ws_bytes);
+  if (rc) return rc;
+  rc = upload_plan(&B, stream);
+  if (rc) return rc;
+  return run_plan(&B, stats, stream);
+}
+
+// ----------------------------------------------------------------- batches
+
+extern "C" int qx_batch_workspace_bytes(int nsys, const qx_system_t* systems,
+                                        const qx_cg_params_t* params, size_t* bytes) {
+  if (nsys < 1 || !systems || !bytes) return fail(QX_EINVAL, "qx_batch_workspace_bytes: bad argument");
+  int rc = check_params(params);
+  if (rc) return rc;
+  std::vector<SysSpec> specs;
+  for (int i = 0; i < nsys; ++i) {
+    const qx_system_t& s = systems[i];
+    if (!s.g64 || s.nrhs < 1 || !s.masses) return fail(QX_EINVAL, "batch: bad system %d", i);
+    add_specs(specs, s.g64, s.glo ? s.glo : s.g64, params, s.nrhs, s.masses, s.b, s.x);
+  }
+  *bytes = plan_layout(specs, lo_prec(params)).total;
+  return QX_OK;
+}
+
+extern "C" int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg_params_t* params,
+                               void* ws, size_t ws_bytes, hipStream_t stream, qx_batch_t** out) {
+  if (nsys < 1 || !systems || !out) return fail(QX_EINVAL, "qx_batch_create: bad argument");
+  int rc = check_params(params);
+  if (rc) return rc;
+  qx_batch* B = new (std::nothrow) qx_batch;
+  if (!B) return fail(QX_ENOMEM, "qx_batch_create: out of host memory");
+  B->params = *params;
+  for (int i = 0; i < nsys; ++i) {
+    const qx_system_t& s = systems[i];
+    rc = check_system(s.g64, s.glo, params);
+    if (!rc && (s.nrhs < 1 || !s.masses || !s.b || !s.x))
+      rc = fail(QX_EINVAL, "qx_batch_create: bad system %d", i);
+    if (rc) {
+      delete B;
+      return rc;
+    }
+    add_specs(B->specs, s.g64, s.glo, params, s.nrhs, s.masses, s.b, s.x);
+  }
+  if ((int)B->specs.size() > kMaxSys) {
+    delete B;
+    return fail(QX_EINVAL, "qx_batch_create: at most %d systems of <= 12 sources", kMaxSys);
+  }
+  const char* env = getenv("QX_GRAPH");
+  B->use_graph = !(env && env[0] == '0');
+  rc = build_plan(B, ws, ws_bytes);
+  if (!rc) rc = upload_plan(B, stream);
+  if (!rc) rc = capture_graph(B, stream);
+  if (rc) {
+    delete B;
+    return rc;
+  }
+  *out = B;
+  return QX_OK;
+}
+
+extern "C" int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream) {
+  if (!batch) return fail(QX_EINVAL, "qx_batch_solve: NULL batch");
+  return run_plan(batch, stats, stream);
+}
+
+extern "C" int qx_batch_destroy(qx_batch_t* batch) {
+  delete batch;
+  return QX_OK;
+}
+
+// ------------------------------------------------------------------- force
+
+extern "C" int qx_force_from_fields(const qx_gauge_t* g64, int nrhs, const void* x_packed,
+                                    const void* lam_packed, void* tmp_odd, void* grad_U,
+                                    hipStream_t stream) {
+  if (!g64 || nrhs < 1 || !x_packed || !lam_packed || !tmp_odd || !grad_U)
+    return fail(QX_EINVAL, "qx_force_from_fields: bad argument");
+  if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "qx_force_from_fields: needs FP64 links");
+  const Geo& g = g64->geo;
+  char* y = (char*)tmp_odd;
+  char* nu = y + field_bytes(g, nrhs, QX_PREC_F64);
+  const LaunchShape sh = shape_for(g64, nrhs);
+  QX_HIP(launch_dslash(g, QX_PREC_F64, g64->recon, g64->packed, 1, x_packed, y, nrhs, 0.5, sh,
+                       stream),
+         "qx_force_from_fields: D_oe x");
+  const void* nup = y;
+  if (lam_packed != x_packed) {
+    QX_HIP(launch_dslash(g, QX_PREC_F64, g64->recon, g64->packed, 1, lam_packed, nu, nrhs, 0.5,
+                         sh, stream),
+           "qx_force_from_fields: D_oe lam");
+    nup = nu;
+  }
+  QX_HIP(launch_force(g, nrhs, x_packed, lam_packed, y, nup, grad_U, stream),
+         "qx_force_from_fields: outer products");
+  return QX_OK;
+}
+
+namespace {
+size_t force_extra_bytes(const Geo& g, int nrhs) {
+  return align_up(field_bytes(g, nrhs, QX_PREC_F64), 256) + 256 * sizeof(double) + 256;
+}
+}  // namespace
+
+extern "C" int qx_force_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params,
+                                        int nrhs, size_t* bytes) {
+  if (nrhs > kMaxSrcPerSys) return fail(QX_EINVAL, "qx_force: at most %d sources", kMaxSrcPerSys);
+  size_t b = 0;
+  int rc = qx_cg_workspace_bytes(lat, params, nrhs, &b);
+  if (rc) return rc;
+  *bytes = align_up(b, 256) + force_extra_bytes(lat->geo, nrhs);
+  return QX_OK;
+}
+
+extern "C" int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_cg_params_t* params,
+                        int nrhs, double mass, const void* phi, void* grad_U, double* S_out,
+                        void* x_out, void* ws, size_t ws_bytes, qx_cg_stats_t* stats,
+                        hipStream_t stream) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  rc = check_system(g64, glo, params);
+  if (rc) return rc;
+  if (nrhs < 1 || nrhs > kMaxSrcPerSys || !phi || !grad_U || !ws)
+    return fail(QX_EINVAL, "qx_force: bad argument");
+  const Geo& g = g64->geo;
+  qx_batch B;
+  B.params = *params;
+  B.params.use_x0 = 0;
+  std::vector<double> masses(nrhs, mass);
+  // the solution goes to x_out when given, else it stays packed in the workspace
+  void* xdst = x_out;
+  std::vector<SysSpec> probe;
+  add_specs(probe, g64, glo, params, nrhs, masses.data(), phi, x_out);
+  const size_t solver_bytes = align_up(plan_layout(probe, lo_prec(params)).total, 256);
+  if (ws_bytes < solver_bytes + force_extra_bytes(g, nrhs))
+    return fail(QX_ENOMEM, "qx_force: workspace too small");
+  char* extra = (char*)ws + solver_bytes;
+  char* y = extra;
+  double* partials = (double*)(extra + align_up(field_bytes(g, nrhs, QX_PREC_F64), 256));
+  double* d_S = partials + 255;
+  if (!xdst) xdst = y;  // scratch for the canonical x (same size as one packed odd field)
+  add_specs(B.specs, g64, glo, params, nrhs, masses.data(), phi, xdst);
+  rc = build_plan(&B, ws, solver_bytes);
+  if (!rc) rc = upload_plan(&B, stream);
+  if (!rc) rc = run_plan(&B, stats, stream);
+  if (rc && rc != QX_ENOTCONVERGED) return rc;
+  const int solve_rc = rc;
+  const SysDesc& d = B.sys[0];
+  const size_t vs = field_bytes(g, nrhs, QX_PREC_F64);
+  const char* xhi = (const char*)d.vhi;
+  const char* bhi = xhi + 2 * vs;
+  // S = sum_s Re <phi_s, x_s> from the packed FP64 b and x
+  QX_HIP(launch_redot(bhi, xhi, (size_t)nrhs * 3 * g.hv, partials, 255, d_S, stream),
+         "qx_force: action");
+  double S = 0.0;
+  QX_HIP(hipMemcpyAsync(&S, d_S, sizeof S, hipMemcpyDeviceToHost, stream), "qx_force: action copy");
+  // y = D_oe x in the (now free) odd slot of the FP64 vectors, then the outer products
+  char* yodd = (char*)d.vhi + 3 * vs;
+  const LaunchShape sh = shape_for(g64, nrhs);
+  QX_HIP(launch_dslash(g, QX_PREC_F64, g64->recon, g64->packed, 1, xhi, yodd, nrhs, 0.5, sh, stream),
+         "qx_force: D_oe x");
+  QX_HIP(launch_force(g, nrhs, xhi, xhi, yodd, yodd, grad_U, stream), "qx_force: outer products");
+  QX_HIP(hipStreamSynchronize(stream), "qx_force");
+  if (S_out) *S_out = S;
+  return solve_rc;
+}
+
+extern "C" int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_U,
+                            double* F, hipStream_t stream) {
+  if (!lat || !U_canon || !grad_U || !F) return fail(QX_EINVAL, "qx_force_su3: bad argument");
+  QX_HIP(launch_su3_force(lat->geo, U_canon, grad_U, F, stream), "qx_force_su3");
+  return QX_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* block, int* xcd_order) {
+  if (!g || nrhs < 1 || !block || !xcd_order) return fail(QX_EINVAL, "qx_get_launch: bad argument");
+  const LaunchShape s = shape_for(g, nrhs);
+  *block = s.block;
+  *xcd_order = s.xcd;
+  return QX_OK;
+}
+
+extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int block, int xcd_order) {
+  if (!g || nrhs < 1 || !(block == 64 || block == 128 || block == 256 || block == 512))
+    return fail(QX_EINVAL, "qx_set_launch: bad argument");
+  const_cast<qx_gauge*>(g)->shapes[nrhs] = LaunchShape{block, xcd_order ? 1 : 0};
+  return QX_OK;
+}
+
+extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream) {
+  if (!g || nrhs < 1 || !scratch) return fail(QX_EINVAL, "qx_tune_dslash: bad argument");
+  const Geo& geo = g->geo;
+  const size_t fb = field_bytes(geo, nrhs, g->prec);
+  char* in = (char*)scratch;
+  char* out = in + fb;
+  QX_HIP(hipMemsetAsync(in, 0, fb, stream), "qx_tune_dslash: clear");
+  hipEvent_t e0, e1;
+  QX_HIP(hipEventCreate(&e0), "qx_tune_dslash: event");
+  QX_HIP(hipEventCreate(&e1), "qx_tune_dslash: event");
+  LaunchShape best{};
+  float best_ms = 1e30f;
+  const int blocks[4] = {64, 128, 256, 512};
+  int rc = QX_OK;
+  for (int bi = 0; bi < 4 && rc == QX_OK; ++bi) {
+    for (int x = 0; x < 2 && rc == QX_OK; ++x) {
+      const LaunchShape sh{blocks[bi], x};
+      hipError_t e = hipSuccess;
+      for (int w = 0; w < 3 && e == hipSuccess; ++w)
+        e = launch_dslash(geo, g->prec, g->recon, g->packed, w & 1, in, out, nrhs, 0.5, sh, stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, stream);
+      const int reps = 20;
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_dslash(geo, g->prec, g->recon, g->packed, r & 1, in, out, nrhs, 0.5, sh, stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = hip_fail(e, "qx_tune_dslash: timing");
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = sh;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  const_cast<qx_gauge*>(g)->shapes[nrhs] = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tune[tune_key(g, nrhs)] = best;
+  tune_save_locked();
+  return QX_OK;
+}

@@ -1,0 +1,258 @@
+// Device-side building blocks of the gfx950 kernels: even-odd geometry computed
+// on the fly, link loads with optional 12-real reconstruction, the per-site
+// staggered stencil for several sources, and deterministic wave/block
+// reductions.
+#pragma once
+
+#include "qx_internal.h"
+
+namespace qx {
+
+// ------------------------------------------------------------ complex math
+
+// c += a * b
+template <typename R>
+__device__ __forceinline__ void cfma(cplx<R>& c, const cplx<R>& a, const cplx<R>& b) {
+  c.re = fma(a.re, b.re, c.re);
+  c.re = fma(-a.im, b.im, c.re);
+  c.im = fma(a.re, b.im, c.im);
+  c.im = fma(a.im, b.re, c.im);
+}
+
+// c -= conj(a) * b
+template <typename R>
+__device__ __forceinline__ void cfms_conj(cplx<R>& c, const cplx<R>& a, const cplx<R>& b) {
+  c.re = fma(-a.re, b.re, c.re);
+  c.re = fma(-a.im, b.im, c.re);
+  c.im = fma(-a.re, b.im, c.im);
+  c.im = fma(a.im, b.re, c.im);
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(const cplx<R>& a, const cplx<R>& b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// ----------------------------------------------------------------- geometry
+
+// Coordinates of the site (parity p, checkerboard index cb) and the
+// checkerboard indices of its eight neighbours (which have parity 1 - p).
+// In lexicographic order with x fastest and L0 even, cb = lex >> 1, so the
+// x neighbours stay in the same row of L0/2 entries (shift 0 or +-1 by the
+// parity of x) and the y, z, t neighbours are cb +- s1, s2, s3 with wrap.
+struct Site {
+  int x0, x1, x2, x3;
+  int fwd[4];
+  int bwd[4];
+};
+
+__host__ __device__ __forceinline__ void site_geometry(const Geo& g, int p, int cb, Site& s) {
+  const int r = cb / g.Lh;
+  const int x0h = cb - r * g.Lh;
+  const int r2 = r / g.L1;
+  const int x1 = r - r2 * g.L1;
+  const int x3 = r2 / g.L2;
+  const int x2 = r2 - x3 * g.L2;
+  const int x0 = 2 * x0h + ((p + x1 + x2 + x3) & 1);
+  s.x0 = x0;
+  s.x1 = x1;
+  s.x2 = x2;
+  s.x3 = x3;
+  const int row = r * g.Lh;
+  const int x0p = (x0 + 1 == g.L0) ? 0 : x0 + 1;
+  const int x0m = (x0 == 0) ? g.L0 - 1 : x0 - 1;
+  s.fwd[0] = row + (x0p >> 1);
+  s.bwd[0] = row + (x0m >> 1);
+  s.fwd[1] = (x1 + 1 == g.L1) ? cb - (g.L1 - 1) * g.s1 : cb + g.s1;
+  s.bwd[1] = (x1 == 0) ? cb + (g.L1 - 1) * g.s1 : cb - g.s1;
+  s.fwd[2] = (x2 + 1 == g.L2) ? cb - (g.L2 - 1) * g.s2 : cb + g.s2;
+  s.bwd[2] = (x2 == 0) ? cb + (g.L2 - 1) * g.s2 : cb - g.s2;
+  s.fwd[3] = (x3 + 1 == g.L3) ? cb - (g.L3 - 1) * g.s3 : cb + g.s3;
+  s.bwd[3] = (x3 == 0) ? cb + (g.L3 - 1) * g.s3 : cb - g.s3;
+}
+
+// Staggered phase eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}).
+__host__ __device__ __forceinline__ int eta_sign(int mu, int x0, int x1, int x2) {
+  int e = 0;
+  if (mu >= 1) e += x0;
+  if (mu >= 2) e += x1;
+  if (mu >= 3) e += x2;
+  return (e & 1) ? -1 : 1;
+}
+
+// eta_mu(x) times the boundary sign of the link U_mu(x): the factor folded
+// into the packed links.
+__host__ __device__ __forceinline__ int link_sign(const Geo& g, int mu, int x0, int x1, int x2, int x3) {
+  const int s = eta_sign(mu, x0, x1, x2);
+  return (mu == 3 && g.anti_t && x3 == g.L3 - 1) ? -s : s;
+}
+
+// Block index in the order that gives each XCD a contiguous range of tiles.
+// Workgroups are dealt round-robin to the eight XCDs (blockIdx % 8), each with
+// its own L2; with this remapping XCD k works on the k-th eighth of the
+// checkerboard range, so the t and z neighbours of its sites mostly live in
+// the same L2.
+__device__ __forceinline__ int logical_block(int xcd_order) {
+  const int b = blockIdx.x;
+  if (!xcd_order) return b;
+  const int G = gridDim.x;
+  const int q = G >> 3, r = G & 7;
+  const int x = b & 7, j = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
+}
+
+// ------------------------------------------------------------------- links
+
+// Packed links: [parity][mu][element][cb], element e = 3 * row + column, E = 9
+// (18 reals) or 6 (12 reals: rows 0 and 1).  p points at element 0 of one link.
+template <typename R, int RECON>
+__device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<R>* __restrict__ p, size_t hv,
+                                          int sign) {
+  constexpr int E = RECON == 12 ? 6 : 9;
+#pragma unroll
+  for (int e = 0; e < E; ++e) u[e] = p[e * hv];
+  if constexpr (RECON == 12) {
+    // For W = s U with U in SU(3), s = +-1: row2(W) = s * conj(row0(W) x row1(W)).
+    const R s = (R)sign;
+    const cplx<R> c0 = cmul(u[1], u[5]), c0b = cmul(u[2], u[4]);
+    const cplx<R> c1 = cmul(u[2], u[3]), c1b = cmul(u[0], u[5]);
+    const cplx<R> c2 = cmul(u[0], u[4]), c2b = cmul(u[1], u[3]);
+    u[6] = {s * (c0.re - c0b.re), -s * (c0.im - c0b.im)};
+    u[7] = {s * (c1.re - c1b.re), -s * (c1.im - c1b.im)};
+    u[8] = {s * (c2.re - c2b.re), -s * (c2.im - c2b.im)};
+  }
+}
+
+// ---------------------------------------------------------------- stencil
+
+// acc[k] = sum_mu [ W_mu(x) in_k(x+mu) - W_mu(x-mu)^dag in_k(x-mu) ] for the
+// output site (pout, cb), with W = eta * bc * U the packed links (so this is
+// 2 D).  Every link is loaded once and applied to all active sources k < NB
+// (bit k of `act`); in_k is at in + k * sstride, colour c at + c * hv.
+template <typename R, int RECON, int NB>
+__device__ __forceinline__ void stencil(const Geo& g, const cplx<R>* __restrict__ links, int pout,
+                                        int cb, const cplx<R>* __restrict__ in, size_t sstride,
+                                        unsigned act, cplx<R> (&acc)[NB][3]) {
+  constexpr int E = RECON == 12 ? 6 : 9;
+  const size_t hv = (size_t)g.hv;
+  Site s;
+  site_geometry(g, pout, cb, s);
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[k][a] = {(R)0, (R)0};
+
+  const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
+  const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    int sf = 1, sb = 1;
+    if constexpr (RECON == 12) {
+      // Forward link U_mu(x); backward link U_mu(x - mu), which has the same
+      // eta (eta_mu does not depend on x_mu) and the antiperiodic sign when
+      // (x - mu)_3 = L3 - 1, i.e. x3 = 0 for mu = t.
+      const int e = eta_sign(mu, s.x0, s.x1, s.x2);
+      sf = (mu == 3 && g.anti_t && s.x3 == g.L3 - 1) ? -e : e;
+      sb = (mu == 3 && g.anti_t && s.x3 == 0) ? -e : e;
+    }
+    cplx<R> u[9];
+    load_link<R, RECON>(u, lf + (size_t)mu * E * hv + cb, hv, sf);
+    const int nf = s.fwd[mu];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (!(act >> k & 1u)) continue;
+      const cplx<R>* v = in + k * sstride + nf;
+      const cplx<R> c0 = v[0], c1 = v[hv], c2 = v[2 * hv];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cfma(acc[k][a], u[3 * a + 0], c0);
+        cfma(acc[k][a], u[3 * a + 1], c1);
+        cfma(acc[k][a], u[3 * a + 2], c2);
+      }
+    }
+    const int nb = s.bwd[mu];
+    load_link<R, RECON>(u, lb + (size_t)mu * E * hv + nb, hv, sb);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      if (!(act >> k & 1u)) continue;
+      const cplx<R>* v = in + k * sstride + nb;
+      const cplx<R> c0 = v[0], c1 = v[hv], c2 = v[2 * hv];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cfms_conj(acc[k][a], u[0 + a], c0);
+        cfms_conj(acc[k][a], u[3 + a], c1);
+        cfms_conj(acc[k][a], u[6 + a], c2);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of v over the block for NB independent values, fixed order (wave
+// butterflies, then waves in index order), result valid in thread 0.
+// `sh` must hold NB * 16 doubles.
+template <int NB>
+__device__ __forceinline__ void block_sum(double (&v)[NB], double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const double t = wave_sum(v[k]);
+    if (lane == 0) sh[k * 16 + w] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double t = 0;
+      for (int i = 0; i < nw; ++i) t += sh[k * 16 + i];
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+// Publish per-block partial sums (thread 0 holds them) and report whether
+// this block is the last of its system to do so.  The partials are written,
+// released at agent scope, and counted with an agent-scope atomic; the last
+// block acquires before reading them back.  The counter is reset by the last
+// block so that it is zero again at the next launch.
+template <int NB>
+__device__ __forceinline__ bool publish_partials(const double (&v)[NB], int nsrc, double* partials,
+                                                 int nblk, int bl, unsigned* counter, int* flag_sh) {
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NB && k < nsrc; ++k) partials[(size_t)k * nblk + bl] = v[k];
+    __threadfence();
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    *flag_sh = (prev == (unsigned)(nblk - 1));
+  }
+  __syncthreads();
+  const bool last = *flag_sh != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// In the last block: total over the nblk partials of every source, fixed
+// order; result valid in thread 0.  Resets the counter.
+template <int NB>
+__device__ __forceinline__ void total_partials(double (&tot)[NB], int nsrc, const double* partials,
+                                               int nblk, unsigned* counter, double* sh) {
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    double t = 0;
+    if (k < nsrc)
+      for (int i = threadIdx.x; i < nblk; i += blockDim.x) t += partials[(size_t)k * nblk + i];
+    tot[k] = t;
+  }
+  block_sum<NB>(tot, sh);
+  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace qx
