@@ -1,0 +1,259 @@
+"""Benchmark: staggered Dslash + even-odd CG on one MI355X.
+
+Workload (one step): a full mixed-precision solve of (m^2 - D_eo D_oe) x = b to
+a true FP64 relative residual of 1e-10 on a 16^4 lattice with weak-field links
+U = exp(0.3 i H) (seed 0), one Gaussian source (seed 1), m = 0.05, FP32 inner
+iteration on 12-real links, FP64 reliable updates when |r| drops below
+0.1 max|r|.  Inputs are resident in HBM before the timed region; the step
+includes packing b, every inner iteration and reliable update, and unpacking x.
+
+Reported beside it (same run):
+  * the same solve in plain FP64 (time-to-solution, mixed vs FP64);
+  * the dominant kernel (the FP32 half-Dslash) timed alone with HIP events on
+    its stream, against the HBM roofline;
+  * the half-Dslash on 32^4 (the size where links no longer fit the 256 MB
+    Infinity Cache) in FP32-12 and FP64-18, one and twelve sources;
+  * the measured bandwidth of a plain copy kernel;
+  * the CPU oracle (FP64 CG on the host cores) on the same system.
+
+Flop convention: 570 flops per output site per half-Dslash; one CG iteration
+costs 606 V (two half-Dslash + BLAS-1), one reliable update 570 V + 12 V.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FLOPS_SITE = 570
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the dominant-kernel timing and the copy probe (for counter runs)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_kernel(torch, fn, reps):
+    """Average duration of fn() (one launch) from HIP events on the current stream."""
+    s = torch.cuda.current_stream()
+    for _ in range(5):
+        fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
+
+
+BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colour vector
+
+
+def dominant_kernel(torch, qx, lat, g32, bd, reps):
+    """The FP32 12-real half-Dslash on the workload lattice, timed alone."""
+    p32 = qx.pack(lat, bd, "f32")
+    o32 = qx.dslash(g32, p32, 0, 1)
+    t_k = time_kernel(torch, lambda: qx.dslash(g32, p32, 0, 1, out=o32), reps)
+    achieved = BYTES_SITE_F32_12 * lat.hv / t_k / 1e9
+    log(f"dominant kernel (FP32-12 half-Dslash, {lat.dims}): {t_k * 1e6:.2f} us, "
+        f"{achieved:.0f} GB/s algorithmic, {FLOPS_SITE * lat.hv / t_k / 1e9:.0f} GFLOP/s")
+    return t_k, achieved
+
+
+def copy_probe(torch, qx, nb=1 << 30):
+    """Plain copy of nb bytes: measured bandwidth (read + write) and counter calibration."""
+    a = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    c = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    t_copy = time_kernel(torch, lambda: qx.probe_copy(c, a, nb), 20)
+    copy_gbs = 2 * nb / t_copy / 1e9
+    log(f"copy probe: {nb} bytes, {t_copy * 1e6:.1f} us, {copy_gbs:.0f} GB/s (read + write)")
+    return copy_gbs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1612_02750_amd as qx
+    from paper_1612_02750_amd import synth
+
+    qx.load()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+
+    # ------------------------------------------------------------- workload
+    dims = (16, 16, 16, 16)
+    m, eps, tol, delta = 0.05, 0.3, 1e-10, 0.1
+    lat = qx.Lattice(dims)
+    V, hv = lat.V, lat.hv
+    U = synth.weak_gauge(dims, eps, 0)
+    b = synth.gauss_source(1, hv, 1)
+    Ud = torch.from_numpy(U).cuda()
+    bd = torch.from_numpy(b).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", 18)
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    shape32 = g32.tune(1)
+    shape64 = g64.tune(1)
+    log(f"tuned launch shapes: f32-12 {shape32}, f64-18 {shape64}")
+    if args.kernels_only:
+        t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
+        copy_gbs = copy_probe(torch, qx)
+        print(json.dumps({"kernels_only": True, "dominant_us": round(t_k * 1e6, 3),
+                          "achieved_gbs": round(achieved, 1), "copy_probe_gbs": round(copy_gbs, 1)}))
+        return
+    x_mx = torch.empty_like(bd)
+    x_64 = torch.empty_like(bd)
+    mixed = qx.Batch([(g64, g32, bd, [m], x_mx)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
+    plain = qx.Batch([(g64, None, bd, [m], x_64)], tol=tol, mode=qx.CG_FP64)
+
+    for _ in range(args.warmup):
+        mixed.solve()
+    plain.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = mixed.solve()
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.steps
+    s_mx = st[0]
+    log(f"mixed: {t_mixed * 1e3:.3f} ms/solve, iters {s_mx.iters}, updates {s_mx.reliable_updates}, "
+        f"residual {s_mx.true_rel_residual:.2e}")
+
+    reps64 = max(3, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps64):
+        st64 = plain.solve()
+    torch.cuda.synchronize()
+    t_fp64 = (time.perf_counter() - t0) / reps64
+    s_64 = st64[0]
+    log(f"fp64:  {t_fp64 * 1e3:.3f} ms/solve, iters {s_64.iters}, residual {s_64.true_rel_residual:.2e}")
+
+    flops_mixed = (s_mx.iters * 606 + s_mx.reliable_updates * 582) * V
+    value = flops_mixed / t_mixed / 1e9
+
+    # ---------------------------------------------- dominant kernel vs roofline
+    t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
+
+    # --------------------------------------------------- 32^4 Dslash (HBM size)
+    d32 = {}
+    dims32 = (32, 32, 32, 32)
+    lat32 = qx.Lattice(dims32)
+    U32 = torch.from_numpy(synth.haar_gauge(dims32, 0)).cuda()
+    # compulsory bytes per output site: 8 links + one input and one output colour vector per source
+    for prec, recon, link_b, vec_b in (("f32", 12, 384, 24), ("f64", 18, 1152, 48)):
+        g = qx.Gauge(lat32, U32, prec, recon)
+        for nrhs in (1, 12):
+            g.tune(nrhs)
+            src = torch.from_numpy(synth.gauss_source(nrhs, lat32.hv, 2)).cuda()
+            pin = qx.pack(lat32, src, prec)
+            pout = qx.dslash(g, pin, 0, nrhs)
+            t = time_kernel(torch, lambda: qx.dslash(g, pin, 0, nrhs, out=pout), 50)
+            by = (link_b + 2 * vec_b * nrhs) * lat32.hv
+            d32[f"{prec}-{recon}-nrhs{nrhs}"] = {
+                "us": round(t * 1e6, 2),
+                "gflops": round(FLOPS_SITE * nrhs * lat32.hv / t / 1e9, 1),
+                "gbs_algorithmic": round(by / t / 1e9, 1),
+                "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
+            }
+            log(f"32^4 {prec}-{recon} nrhs {nrhs}: {d32[f'{prec}-{recon}-nrhs{nrhs}']}")
+            del src, pin, pout
+        del g
+    del U32
+
+    copy_gbs = copy_probe(torch, qx)
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        xo, sto, it_o, rr_o = oracle.cg(dims, U, m, b[0], tol=tol)
+        t_cpu = time.perf_counter() - t0
+        cpu = {
+            "value": round(it_o * 606 * V / t_cpu / 1e9, 3),
+            "unit": "GFLOP/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"one full FP64 CG solve of the same 16^4 system to 1e-10 "
+                      f"({it_o} iterations, {t_cpu:.2f} s, true residual {rr_o:.1e})",
+        }
+        # parity of the benchmarked solution against the oracle
+        rr_gpu = oracle.true_residual(dims, U, m, b[0], x_mx.cpu().numpy()[0])
+        log(f"cpu oracle: {cpu}; oracle residual of the GPU solution {rr_gpu:.2e}")
+
+    out = {
+        "metric": "Dslash GFLOP/s + % HBM roofline; CG time-to-solution @1e-10, mixed vs FP64",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_mixed * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 inner / f64 reliable updates",
+        "data": "synthetic",
+        "config": {
+            "workload": "mixed-precision even-odd CG, 16^4 weak-field links eps=0.3, m=0.05, "
+                        "1 Gaussian source, FP32 12-real inner, FP64 reliable updates delta=0.1, "
+                        "tol 1e-10",
+            "lattice": list(dims),
+            "nrhs": 1,
+        },
+        "cg_time_to_solution_ms": {"mixed_f32_12": round(t_mixed * 1e3, 3),
+                                   "fp64": round(t_fp64 * 1e3, 3),
+                                   "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3)},
+        "cg_iterations": {"mixed": s_mx.iters, "mixed_reliable_updates": s_mx.reliable_updates,
+                          "fp64": s_64.iters},
+        "true_rel_residual": {"mixed": s_mx.true_rel_residual, "fp64": s_64.true_rel_residual},
+        "roofline": {
+            "kernel": "k_dslash<float,12,1> (FP32 12-real half-Dslash, 16^4)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(t_k * 1e6, 3),
+            "bytes_per_site": BYTES_SITE_F32_12,
+            "sites_per_launch": hv,
+        },
+        "dslash_32^4": d32,
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

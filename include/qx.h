@@ -278,6 +278,13 @@ int qx_get_launch(const qx_gauge_t* g, int nrhs, int* block, int* xcd_order);
 /* Force a launch shape (block in {64,128,256,512}); the next solves use it. */
 int qx_set_launch(const qx_gauge_t* g, int nrhs, int block, int xcd_order);
 
+/* ------------------------------------------------------------- probe */
+
+/* dst = src (device buffers, bytes a multiple of 16) with a plain streaming
+   kernel: the measured-bandwidth reference for the roofline figures and the
+   calibration kernel for hardware memory counters.  Asynchronous. */
+int qx_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,6 +100,7 @@ def load():
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
         "qx_get_launch": ([_P, _I, _P, _P], _I),
         "qx_set_launch": ([_P, _I, _I, _I], _I),
+        "qx_probe_copy": ([_P, _P, _SZ, _P], _I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -389,6 +390,11 @@ def force_from_fields(g64: Gauge, x, lam, stream=None):
     _check(load().qx_force_from_fields(g64._h, nrhs, _ptr(xp), _ptr(lp), _ptr(tmp), _ptr(G),
                                        _stream(stream)))
     return G
+
+
+def probe_copy(dst, src, nbytes: int, stream=None):
+    """dst = src with the library's streaming copy kernel (bandwidth reference)."""
+    _check(load().qx_probe_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
 
 
 def force_su3(lat: Lattice, U, G, stream=None):

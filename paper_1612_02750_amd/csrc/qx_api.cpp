@@ -828,6 +828,14 @@ extern "C" int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const 
   return QX_OK;
 }
 
+// ------------------------------------------------------------------- probe
+
+extern "C" int qx_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  if (!dst || !src || bytes % 16) return fail(QX_EINVAL, "qx_probe_copy: bad argument");
+  QX_HIP(launch_copy(dst, src, bytes, stream), "qx_probe_copy");
+  return QX_OK;
+}
+
 // ------------------------------------------------------------------ tuning
 
 extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* block, int* xcd_order) {

@@ -10,6 +10,8 @@
 // epilogue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qx_device.h"
 #include "qx_launch.h"
 
@@ -943,6 +945,25 @@ hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials
   hipLaunchKernelGGL(k_redot_partial, dim3(nblk), dim3(256), 0, s, (const cplx<double>*)a,
                      (const cplx<double>*)b, n, partials);
   hipLaunchKernelGGL(k_redot_final, dim3(1), dim3(256), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}
+
+// ================================================================ probe
+
+// Plain copy with 16-byte accesses: the measured-bandwidth reference and the
+// calibration kernel for the memory counters.
+__global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_copy16, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, (const uint4*)src,
+                     (uint4*)dst, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,57 @@
+"""The C ABI library loads on a machine without a GPU and exports every symbol
+that include/qx.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1612_02750_amd", "libqx.so")
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "qx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qx_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1612_02750_amd import build
+
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("qx_dslash", "qx_cg_solve", "qx_gauge_load", "qx_lattice_create", "qx_force",
+              "qx_batch_create", "qx_apply_A"):
+        assert n in names
+
+
+def test_every_declared_symbol_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls(lib):
+    lib.qx_version.restype = ctypes.c_int
+    assert lib.qx_version() == 1
+    lib.qx_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int32 * 4)(4, 4, 3, 4)
+    assert lib.qx_lattice_create(bad, 0, ctypes.byref(h)) == 1  # QX_EINVAL
+    assert b"even" in lib.qx_last_error()
+    ok = (ctypes.c_int32 * 4)(4, 4, 4, 8)
+    assert lib.qx_lattice_create(ok, 0, ctypes.byref(h)) == 0
+    lib.qx_lattice_volume.restype = ctypes.c_int64
+    assert lib.qx_lattice_volume(h) == 512
+    n = ctypes.c_size_t()
+    assert lib.qx_gauge_bytes(h, 1, 12, ctypes.byref(n)) == 0
+    assert n.value == 8 * 256 * 6 * 8
+    assert lib.qx_field_bytes(h, 3, 0, ctypes.byref(n)) == 0
+    assert n.value == 3 * 3 * 256 * 16
+    lib.qx_lattice_destroy(h)
