@@ -13,7 +13,7 @@ LIB = os.path.join(ROOT, "paper_1612_02750_amd", "libqx.so")
 def declared():
     src = open(os.path.join(ROOT, "include", "qx.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(qx_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(qx_[A-Za-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
