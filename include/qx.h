@@ -264,19 +264,25 @@ int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_
 
 /* ------------------------------------------------------------- tuning */
 
-/* Pick the launch shape (threads per block, XCD-aware block order) of the
-   Dslash kernels for this gauge handle and nrhs by timing the candidates on
-   the stream (scratch: two packed fields of nrhs sources of the handle's
-   precision, 2 * qx_field_bytes).  The result is cached per
-   (lattice, precision, link storage, nrhs) in the process and in the JSON
-   file named by QX_TUNE_CACHE if set.  Synchronises the stream. */
+/* Pick the launch shape of the stencil kernels for this gauge handle and nrhs
+   sources by timing every candidate on the stream.  A stencil block covers 64
+   sites with lps * groups wavefronts: lps (1, 2, 4, 8) wavefronts share the
+   eight hops of each site (more loads in flight on small lattices), and each
+   of the groups = ceil(nrhs / nbt) takes nbt (1, 2, 4) sources, every link
+   loaded once per wavefront and applied to all of its sources; xcd_order
+   gives each of the eight XCDs a contiguous range of sites.  scratch: two
+   packed fields of nrhs sources of the handle's precision
+   (2 * qx_field_bytes).  The result is used by every later call with this
+   handle and nrhs (Dslash, A and the solvers) and cached per (lattice,
+   precision, link storage, nrhs) in the process and in the JSON file named by
+   QX_TUNE_CACHE if set.  Synchronises the stream. */
 int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream);
 
-/* Launch shape currently used for (handle, nrhs): threads per block and the
-   XCD-aware ordering flag. */
-int qx_get_launch(const qx_gauge_t* g, int nrhs, int* block, int* xcd_order);
-/* Force a launch shape (block in {64,128,256,512}); the next solves use it. */
-int qx_set_launch(const qx_gauge_t* g, int nrhs, int block, int xcd_order);
+/* Launch shape currently used for (handle, nrhs). */
+int qx_get_launch(const qx_gauge_t* g, int nrhs, int* nbt, int* lps, int* xcd_order);
+/* Force a launch shape; QX_EINVAL if it is not one of the compiled shapes or
+   does not fit one block. */
+int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, int xcd_order);
 
 /* ------------------------------------------------------------- probe */
 

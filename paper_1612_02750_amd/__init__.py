@@ -98,8 +98,8 @@ def load():
         "qx_force": ([_P, _P, _P, _I, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P, _P], _I),
         "qx_force_su3": ([_P, _P, _P, _P, _P], _I),
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
-        "qx_get_launch": ([_P, _I, _P, _P], _I),
-        "qx_set_launch": ([_P, _I, _I, _I], _I),
+        "qx_get_launch": ([_P, _I, _P, _P, _P], _I),
+        "qx_set_launch": ([_P, _I, _I, _I, _I], _I),
         "qx_probe_copy": ([_P, _P, _SZ, _P], _I),
     }
     for name, (args, res) in sig.items():
@@ -219,12 +219,13 @@ class Gauge:
         return self.launch(nrhs)
 
     def launch(self, nrhs: int = 1):
-        b, x = ctypes.c_int(), ctypes.c_int()
-        _check(load().qx_get_launch(self._h, nrhs, ctypes.byref(b), ctypes.byref(x)))
-        return b.value, x.value
+        """(sources per thread, wavefronts per site, XCD order) of the stencil kernels."""
+        n, l, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().qx_get_launch(self._h, nrhs, ctypes.byref(n), ctypes.byref(l), ctypes.byref(x)))
+        return n.value, l.value, x.value
 
-    def set_launch(self, nrhs: int, block: int, xcd_order: int):
-        _check(load().qx_set_launch(self._h, nrhs, block, xcd_order))
+    def set_launch(self, nrhs: int, nbt: int, lps: int, xcd_order: int):
+        _check(load().qx_set_launch(self._h, nrhs, nbt, lps, xcd_order))
 
 
 # ------------------------------------------------------------------ fields

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqx.so")
-SOURCES = ["qx_kernels.hip", "qx_api.cpp"]
+SOURCES = ["qx_engine.hip", "qx_dslash.hip", "qx_kernels.hip", "qx_api.cpp"]
 ARCH = "gfx950"
 
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/qx.h"
+#include "qx_dispatch.h"
 #include "qx_internal.h"
 #include "qx_launch.h"
 
@@ -104,7 +105,7 @@ std::string tune_key(const qx_gauge* g, int nrhs) {
   return buf;
 }
 
-// The cache file is a flat JSON object {"key": [block, xcd], ...}.
+// The cache file is a flat JSON object {"key": [nbt, lps, xcd], ...}.
 void tune_load_locked() {
   if (g_tune_loaded) return;
   g_tune_loaded = true;
@@ -122,10 +123,10 @@ void tune_load_locked() {
     const size_t j = s.find('"', i + 1);
     if (j == std::string::npos) break;
     const std::string key = s.substr(i + 1, j - i - 1);
-    int b = 0, x = 0;
-    if (sscanf(s.c_str() + j + 1, " : [ %d , %d ]", &b, &x) == 2 &&
-        (b == 64 || b == 128 || b == 256 || b == 512))
-      g_tune[key] = LaunchShape{b, x ? 1 : 0};
+    int nbt = 0, lps = 0, x = 0;
+    if (sscanf(s.c_str() + j + 1, " : [ %d , %d , %d ]", &nbt, &lps, &x) == 3 &&
+        nbt_lps_instantiated(nbt, lps))
+      g_tune[key] = LaunchShape{nbt, lps, x ? 1 : 0};
     i = j + 1;
   }
 }
@@ -138,8 +139,8 @@ void tune_save_locked() {
   fprintf(f, "{\n");
   size_t k = 0;
   for (const auto& kv : g_tune)
-    fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.block, kv.second.xcd,
-            ++k < g_tune.size() ? "," : "");
+    fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.nbt, kv.second.lps,
+            kv.second.xcd, ++k < g_tune.size() ? "," : "");
   fprintf(f, "}\n");
   fclose(f);
 }
@@ -356,12 +357,13 @@ Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
   off = align_up(off + sizeof(SrcState) * nsrc, 256);
   for (const auto& s : specs) {
     const Geo& g = s.g64->geo;
-    const int nblk = (g.hv + 63) / 64;
-    L.nblk_max.push_back(nblk);
+    const int nblk = (g.hv + kTile - 1) / kTile;
+    const int vtiles = (3 * g.hv + kVTile - 1) / kVTile;
+    L.nblk_max.push_back(std::max(nblk, vtiles));
     L.counter_off.push_back(off);
     off = align_up(off + 256, 256);
     L.partial_off.push_back(off);
-    off = align_up(off + sizeof(double) * s.nrhs * nblk, 256);
+    off = align_up(off + sizeof(double) * s.nrhs * std::max(nblk, vtiles), 256);
     L.vlo_off.push_back(off);
     off = align_up(off + 5 * field_bytes(g, s.nrhs, prec_lo), 256);
     L.vhi_off.push_back(off);
@@ -447,9 +449,11 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
 
   // launch shape: the tuned (or default) shape of the first system's inner links
   const SysSpec& s0 = B->specs[0];
-  LaunchShape sh = shape_for(s0.glo, s0.nrhs);
   int nb = 1;
   for (const auto& s : B->specs) nb = std::max(nb, s.nrhs);
+  LaunchShape sh = shape_for(s0.glo, nb);
+  if (!shape_ok(sh, nb, cplx_bytes(prec_lo)) || !nbt_lps_instantiated(sh.nbt, sh.lps))
+    sh = LaunchShape{};
 
   B->cfg = EngineCfg{};
   B->cfg.prec_lo = prec_lo;
@@ -459,7 +463,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     if (s.glo->recon != B->cfg.recon_lo || s.g64->recon != B->cfg.recon_hi)
       return fail(QX_EINVAL, "batch: all systems must use the same link storage");
   }
-  B->cfg.nb = nb;
+  B->cfg.nsrc_max = nb;
   B->cfg.shape = sh;
   B->cfg.nsys = (int)B->specs.size();
   B->cfg.d_sys = (const SysDesc*)(B->ws + B->layout.sys_off);
@@ -467,7 +471,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
 
   B->sys.clear();
   B->st0.clear();
-  int blk = 0, src = 0;
+  int blk = 0, vblk = 0, src = 0;
   const double stop = kStopFactor * p.tol;
   for (size_t i = 0; i < B->specs.size(); ++i) {
     const SysSpec& s = B->specs[i];
@@ -476,7 +480,9 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     d.nsrc = s.nrhs;
     d.src0 = src;
     d.blk0 = blk;
-    d.nblk = (d.g.hv + sh.block - 1) / sh.block;
+    d.nblk = (d.g.hv + kTile - 1) / kTile;
+    d.vblk0 = vblk;
+    d.vtiles = (3 * d.g.hv + kVTile - 1) / kVTile;
     d.links_lo = s.glo->packed;
     d.links_hi = s.g64->packed;
     d.vlo = B->ws + B->layout.vlo_off[i];
@@ -484,6 +490,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     d.partials = (double*)(B->ws + B->layout.partial_off[i]);
     d.counter = (unsigned*)(B->ws + B->layout.counter_off[i]);
     blk += d.nblk;
+    vblk += d.nsrc * d.vtiles;
     src += d.nsrc;
     B->sys.push_back(d);
     for (int k = 0; k < s.nrhs; ++k) {
@@ -499,6 +506,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     }
   }
   B->cfg.nblk_total = blk;
+  B->cfg.nvblk_total = vblk;
   B->cfg.nsrc_total = src;
   if (!engine_supported(B->cfg)) return fail(QX_EINVAL, "solver: unsupported configuration");
   if (!B->h_st) QX_HIP(hipHostMalloc((void**)&B->h_st, sizeof(SrcState) * src), "solver: hipHostMalloc");
@@ -838,18 +846,25 @@ extern "C" int qx_probe_copy(void* dst, const void* src, size_t bytes, hipStream
 
 // ------------------------------------------------------------------ tuning
 
-extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* block, int* xcd_order) {
-  if (!g || nrhs < 1 || !block || !xcd_order) return fail(QX_EINVAL, "qx_get_launch: bad argument");
+extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* nbt, int* lps, int* xcd_order) {
+  if (!g || nrhs < 1 || !nbt || !lps || !xcd_order)
+    return fail(QX_EINVAL, "qx_get_launch: bad argument");
   const LaunchShape s = shape_for(g, nrhs);
-  *block = s.block;
+  *nbt = s.nbt;
+  *lps = s.lps;
   *xcd_order = s.xcd;
   return QX_OK;
 }
 
-extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int block, int xcd_order) {
-  if (!g || nrhs < 1 || !(block == 64 || block == 128 || block == 256 || block == 512))
-    return fail(QX_EINVAL, "qx_set_launch: bad argument");
-  const_cast<qx_gauge*>(g)->shapes[nrhs] = LaunchShape{block, xcd_order ? 1 : 0};
+extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, int xcd_order) {
+  if (!g || nrhs < 1 || !nbt_lps_instantiated(nbt, lps))
+    return fail(QX_EINVAL, "qx_set_launch: unsupported shape (nbt %d, lps %d)", nbt, lps);
+  const LaunchShape sh{nbt, lps, xcd_order ? 1 : 0};
+  // the standalone operators split the sources into passes that fit a block;
+  // a solver whose sources do not fit falls back to the default shape
+  if (!shape_ok(sh, 1, cplx_bytes(g->prec)))
+    return fail(QX_EINVAL, "qx_set_launch: shape does not fit one block");
+  const_cast<qx_gauge*>(g)->shapes[nrhs] = sh;
   return QX_OK;
 }
 
@@ -865,29 +880,33 @@ extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipS
   QX_HIP(hipEventCreate(&e1), "qx_tune_dslash: event");
   LaunchShape best{};
   float best_ms = 1e30f;
-  const int blocks[4] = {64, 128, 256, 512};
+  const int nbts[3] = {1, 2, 4}, lpss[4] = {1, 2, 4, 8};
   int rc = QX_OK;
-  for (int bi = 0; bi < 4 && rc == QX_OK; ++bi) {
-    for (int x = 0; x < 2 && rc == QX_OK; ++x) {
-      const LaunchShape sh{blocks[bi], x};
-      hipError_t e = hipSuccess;
-      for (int w = 0; w < 3 && e == hipSuccess; ++w)
-        e = launch_dslash(geo, g->prec, g->recon, g->packed, w & 1, in, out, nrhs, 0.5, sh, stream);
-      if (e == hipSuccess) e = hipEventRecord(e0, stream);
-      const int reps = 20;
-      for (int r = 0; r < reps && e == hipSuccess; ++r)
-        e = launch_dslash(geo, g->prec, g->recon, g->packed, r & 1, in, out, nrhs, 0.5, sh, stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        rc = hip_fail(e, "qx_tune_dslash: timing");
-        break;
-      }
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = sh;
+  for (int nbt : nbts) {
+    if (nbt > 1 && nbt > nrhs) continue;
+    for (int lps : lpss) {
+      for (int x = 0; x < 2 && rc == QX_OK; ++x) {
+        const LaunchShape sh{nbt, lps, x};
+        if (!nbt_lps_instantiated(nbt, lps) || !shape_ok(sh, nrhs, cplx_bytes(g->prec))) continue;
+        hipError_t e = hipSuccess;
+        for (int w = 0; w < 3 && e == hipSuccess; ++w)
+          e = launch_dslash(geo, g->prec, g->recon, g->packed, w & 1, in, out, nrhs, 0.5, sh, stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, stream);
+        const int reps = 20;
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+          e = launch_dslash(geo, g->prec, g->recon, g->packed, r & 1, in, out, nrhs, 0.5, sh, stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          rc = hip_fail(e, "qx_tune_dslash: timing");
+          break;
+        }
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = sh;
+        }
       }
     }
   }

@@ -6,6 +6,9 @@
 
 #include "qx_internal.h"
 
+// Dynamic LDS of the stencil kernels (16-byte aligned).
+extern __shared__ double2 qx_lds[];
+
 namespace qx {
 
 // ------------------------------------------------------------ complex math
@@ -124,67 +127,126 @@ __device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<R>* __rest
 }
 
 // ---------------------------------------------------------------- stencil
+//
+// The eight hops of an output site x are h = 0..3 (forward, mu = h) and
+// h = 4..7 (backward, mu = h - 4):
+//   forward  mu: + W_mu(x)        in(x + mu)
+//   backward mu: - W_mu(x - mu)^dag in(x - mu)
+// with W = eta * bc * U the packed links, so the full sum is 2 D in.  A
+// stencil kernel may split the hops of a site over LPS wavefronts (wave part
+// dp takes the hops h with h % LPS == dp) and the sources over groups of NBT;
+// every link a wavefront loads is applied to all of its active sources.
 
-// acc[k] = sum_mu [ W_mu(x) in_k(x+mu) - W_mu(x-mu)^dag in_k(x-mu) ] for the
-// output site (pout, cb), with W = eta * bc * U the packed links (so this is
-// 2 D).  Every link is loaded once and applied to all active sources k < NB
-// (bit k of `act`); in_k is at in + k * sstride, colour c at + c * hv.
-template <typename R, int RECON, int NB>
-__device__ __forceinline__ void stencil(const Geo& g, const cplx<R>* __restrict__ links, int pout,
-                                        int cb, const cplx<R>* __restrict__ in, size_t sstride,
-                                        unsigned act, cplx<R> (&acc)[NB][3]) {
+// Loader of the input vectors of a stencil: in_j(site, colour) for the
+// sources j of the calling thread, from one packed field.
+template <typename R>
+struct FieldIn {
+  const cplx<R>* __restrict__ p;  // first source of the thread
+  size_t ss, hv;                  // source stride (3 hv), colour stride (hv)
+  __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
+    return p[j * ss + c * hv + site];
+  }
+};
+
+// acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT (bit j of act).
+template <typename R, int RECON, int NBT, int LPS, typename In>
+__device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __restrict__ links,
+                                             int pout, int cb, const Site& s, int dp, const In& in,
+                                             unsigned act, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   const size_t hv = (size_t)g.hv;
-  Site s;
-  site_geometry(g, pout, cb, s);
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) acc[k][a] = {(R)0, (R)0};
-
   const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
   const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    int sf = 1, sb = 1;
+  for (int h = 0; h < 8; ++h) {
+    if (LPS > 1 && (h % LPS) != dp) continue;  // uniform across the wavefront
+    const int mu = h & 3;
+    const bool fwd = h < 4;
+    int sign = 1;
     if constexpr (RECON == 12) {
       // Forward link U_mu(x); backward link U_mu(x - mu), which has the same
       // eta (eta_mu does not depend on x_mu) and the antiperiodic sign when
       // (x - mu)_3 = L3 - 1, i.e. x3 = 0 for mu = t.
       const int e = eta_sign(mu, s.x0, s.x1, s.x2);
-      sf = (mu == 3 && g.anti_t && s.x3 == g.L3 - 1) ? -e : e;
-      sb = (mu == 3 && g.anti_t && s.x3 == 0) ? -e : e;
+      const bool flip = mu == 3 && g.anti_t && (fwd ? s.x3 == g.L3 - 1 : s.x3 == 0);
+      sign = flip ? -e : e;
     }
+    const int nb = fwd ? s.fwd[mu] : s.bwd[mu];
     cplx<R> u[9];
-    load_link<R, RECON>(u, lf + (size_t)mu * E * hv + cb, hv, sf);
-    const int nf = s.fwd[mu];
+    load_link<R, RECON>(u, (fwd ? lf + (size_t)mu * E * hv + cb : lb + (size_t)mu * E * hv + nb),
+                        hv, sign);
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      if (!(act >> k & 1u)) continue;
-      const cplx<R>* v = in + k * sstride + nf;
-      const cplx<R> c0 = v[0], c1 = v[hv], c2 = v[2 * hv];
+    for (int j = 0; j < NBT; ++j) {
+      if (!(act >> j & 1u)) continue;
+      const cplx<R> c0 = in(j, 0, nb), c1 = in(j, 1, nb), c2 = in(j, 2, nb);
+      if (fwd) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cfma(acc[k][a], u[3 * a + 0], c0);
-        cfma(acc[k][a], u[3 * a + 1], c1);
-        cfma(acc[k][a], u[3 * a + 2], c2);
-      }
-    }
-    const int nb = s.bwd[mu];
-    load_link<R, RECON>(u, lb + (size_t)mu * E * hv + nb, hv, sb);
+        for (int a = 0; a < 3; ++a) {
+          cfma(acc[j][a], u[3 * a + 0], c0);
+          cfma(acc[j][a], u[3 * a + 1], c1);
+          cfma(acc[j][a], u[3 * a + 2], c2);
+        }
+      } else {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      if (!(act >> k & 1u)) continue;
-      const cplx<R>* v = in + k * sstride + nb;
-      const cplx<R> c0 = v[0], c1 = v[hv], c2 = v[2 * hv];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        cfms_conj(acc[k][a], u[0 + a], c0);
-        cfms_conj(acc[k][a], u[3 + a], c1);
-        cfms_conj(acc[k][a], u[6 + a], c2);
+        for (int a = 0; a < 3; ++a) {
+          cfms_conj(acc[j][a], u[0 + a], c0);
+          cfms_conj(acc[j][a], u[3 + a], c1);
+          cfms_conj(acc[j][a], u[6 + a], c2);
+        }
       }
     }
   }
+}
+
+template <typename R, int NBT>
+__device__ __forceinline__ void zero_acc(cplx<R> (&acc)[NBT][3]) {
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[j][a] = {(R)0, (R)0};
+}
+
+// Sum the LPS hop parts of a block through LDS.  Wave w of the block is
+// (part dp = w % LPS, group grp = w / LPS); after the call, item i = 3 j + c
+// (source j of the group, colour c) is complete in the wave whose part is
+// i % LPS, in acc[j][c].  The sources are reduced one slot j at a time, so
+// red holds G * LPS * 3 * 64 complex numbers.
+template <typename R, int NBT, int LPS>
+__device__ __forceinline__ void reduce_parts(cplx<R> (&acc)[NBT][3], cplx<R>* red, int dp, int grp,
+                                             int lane) {
+  if constexpr (LPS > 1) {
+    cplx<R>* mine = red + (size_t)(grp * LPS + dp) * 3 * 64;
+    const cplx<R>* base = red + (size_t)grp * LPS * 3 * 64;
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (j > 0) __syncthreads();  // the previous slot has been read
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mine[c * 64 + lane] = acc[j][c];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if ((j * 3 + c) % LPS != dp) continue;
+        cplx<R> t = {(R)0, (R)0};
+#pragma unroll
+        for (int q = 0; q < LPS; ++q) {
+          const cplx<R> v = base[((size_t)q * 3 + c) * 64 + lane];
+          t.re += v.re;
+          t.im += v.im;
+        }
+        acc[j][c] = t;
+      }
+    }
+  }
+}
+
+// Threads per stencil block allowed by the register budget (see max_waves).
+template <typename R, int NBT>
+constexpr int kMaxThreads = sizeof(R) * NBT > 8 ? 512 : 1024;
+
+// Does the wave of part dp own item i = 3 j + c after reduce_parts?
+template <int LPS>
+__device__ __forceinline__ bool owns_item(int i, int dp) {
+  return LPS == 1 || i % LPS == dp;
 }
 
 // ------------------------------------------------------------- reductions
@@ -218,20 +280,43 @@ __device__ __forceinline__ void block_sum(double (&v)[NB], double* sh) {
   __syncthreads();
 }
 
-// Publish per-block partial sums (thread 0 holds them) and report whether
-// this block is the last of its system to do so.  The partials are written,
-// released at agent scope, and counted with an agent-scope atomic; the last
-// block acquires before reading them back.  The counter is reset by the last
-// block so that it is zero again at the next launch.
-template <int NB>
-__device__ __forceinline__ bool publish_partials(const double (&v)[NB], int nsrc, double* partials,
-                                                 int nblk, int bl, unsigned* counter, int* flag_sh) {
+// Per-source sums over a stencil block: thread (wave w, lane) holds v[j] for
+// source grp * NBT + j of its group (grp = w / LPS).  The totals for the G*NBT
+// sources of the block land in tot_sh[k], fixed summation order.  sh must hold
+// 16 * NBT * 16 doubles.
+template <int NBT>
+__device__ __forceinline__ void group_sum(const double (&v)[NBT], int nwaves_per_group, int grp,
+                                          int wig, int ngroups, double* sh, double* tot_sh) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    const double t = wave_sum(v[j]);
+    if (lane == 0) sh[(grp * NBT + j) * 16 + wig] = t;
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < ngroups * NBT) {
+    double t = 0;
+    for (int i = 0; i < nwaves_per_group; ++i) t += sh[k * 16 + i];
+    tot_sh[k] = t;
+  }
+  __syncthreads();
+}
+
+// Publish per-block partial sums (thread 0 holds them in part[0..nsrc)) and
+// report whether this block is the last of its system to do so.  The partials
+// are written, released at agent scope, and counted with an agent-scope
+// atomic; the last block acquires before reading them back.  `expected` is
+// the number of blocks that publish for this system in this launch; the last
+// one resets the counter so that it is zero again at the next launch.
+__device__ __forceinline__ bool publish(const double* part, int nsrc, double* partials, int stride,
+                                        int bl, unsigned* counter, unsigned expected, int* flag_sh) {
   if (threadIdx.x == 0) {
-    for (int k = 0; k < NB && k < nsrc; ++k) partials[(size_t)k * nblk + bl] = v[k];
+    for (int k = 0; k < nsrc; ++k) partials[(size_t)k * stride + bl] = part[k];
     __threadfence();
     const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-    *flag_sh = (prev == (unsigned)(nblk - 1));
+    *flag_sh = (prev == expected - 1u);
   }
   __syncthreads();
   const bool last = *flag_sh != 0;
@@ -239,19 +324,17 @@ __device__ __forceinline__ bool publish_partials(const double (&v)[NB], int nsrc
   return last;
 }
 
-// In the last block: total over the nblk partials of every source, fixed
-// order; result valid in thread 0.  Resets the counter.
-template <int NB>
-__device__ __forceinline__ void total_partials(double (&tot)[NB], int nsrc, const double* partials,
-                                               int nblk, unsigned* counter, double* sh) {
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    double t = 0;
-    if (k < nsrc)
-      for (int i = threadIdx.x; i < nblk; i += blockDim.x) t += partials[(size_t)k * nblk + i];
-    tot[k] = t;
-  }
-  block_sum<NB>(tot, sh);
+// In the last block: total of source k over its n partials (fixed order),
+// result valid in thread 0.  Uses sh[0..16).
+__device__ __forceinline__ double total_of(const double* partials, int stride, int k, int n,
+                                           double* sh) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += partials[(size_t)k * stride + i];
+  block_sum<1>(v, sh);
+  return v[0];
+}
+
+__device__ __forceinline__ void reset_counter(unsigned* counter) {
   if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -1,0 +1,56 @@
+// Compile-time dispatch of the kernel templates from runtime parameters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace qx {
+
+inline unsigned grid_for(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+template <typename F>
+hipError_t with_prec_recon(int prec, int recon, F&& f) {
+  if (prec == 0 && recon == 18) return f.template operator()<double, 18>();
+  if (prec == 0 && recon == 12) return f.template operator()<double, 12>();
+  if (prec == 1 && recon == 18) return f.template operator()<float, 18>();
+  if (prec == 1 && recon == 12) return f.template operator()<float, 12>();
+  return hipErrorInvalidValue;
+}
+
+template <typename F>
+hipError_t with_prec(int prec, F&& f) {
+  if (prec == 0) return f.template operator()<double>();
+  if (prec == 1) return f.template operator()<float>();
+  return hipErrorInvalidValue;
+}
+
+// (sources per thread, wavefronts per site) pairs that are instantiated.
+template <typename F>
+hipError_t with_nbt_lps(int nbt, int lps, F&& f) {
+  switch (nbt * 16 + lps) {
+    case 1 * 16 + 1: return f.template operator()<1, 1>();
+    case 1 * 16 + 2: return f.template operator()<1, 2>();
+    case 1 * 16 + 4: return f.template operator()<1, 4>();
+    case 1 * 16 + 8: return f.template operator()<1, 8>();
+    case 2 * 16 + 1: return f.template operator()<2, 1>();
+    case 2 * 16 + 2: return f.template operator()<2, 2>();
+    case 2 * 16 + 4: return f.template operator()<2, 4>();
+    case 4 * 16 + 1: return f.template operator()<4, 1>();
+    case 4 * 16 + 2: return f.template operator()<4, 2>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline bool nbt_lps_instantiated(int nbt, int lps) {
+  return (nbt == 1 && (lps == 1 || lps == 2 || lps == 4 || lps == 8)) ||
+         (nbt == 2 && (lps == 1 || lps == 2 || lps == 4)) || (nbt == 4 && (lps == 1 || lps == 2));
+}
+
+template <typename F>
+hipError_t with_nbt(int nbt, F&& f) {
+  if (nbt == 1) return f.template operator()<1>();
+  if (nbt == 2) return f.template operator()<2>();
+  if (nbt == 4) return f.template operator()<4>();
+  return hipErrorInvalidValue;
+}
+
+}  // namespace qx

@@ -1,0 +1,151 @@
+// Standalone staggered operators: the half-Dslash D_{p, 1-p} and the
+// even-site operator A = m^2 - D_eo D_oe, for any number of sources.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "qx_device.h"
+#include "qx_dispatch.h"
+#include "qx_launch.h"
+
+namespace qx {
+
+// out_k = scale * (2D in_k) at the sites of parity pout.  Block: 64 sites and
+// LPS * G wavefronts; wavefront w takes hop part w % LPS of the sources
+// (w / LPS) * NBT ... + NBT - 1.
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const cplx<R>* __restrict__ links, int pout,
+                                                 const cplx<R>* __restrict__ in,
+                                                 cplx<R>* __restrict__ out, int nsrc, R scale,
+                                                 int xcd) {
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int dp = w % LPS, grp = w / LPS;
+  const int cb = logical_block(xcd) * kTile + lane;
+  const size_t hv = g.hv, ss = 3 * hv;
+  const int k0 = grp * NBT;
+  unsigned act = 0;
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(g, pout, cb, s);
+    stencil_part<R, RECON, NBT, LPS>(g, links, pout, cb, s, dp, FieldIn<R>{in + k0 * ss, ss, hv},
+                                     act, acc);
+  }
+  reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (owns_item<LPS>(3 * j + c, dp))
+        out[(k0 + j) * ss + c * hv + cb] = {scale * acc[j][c].re, scale * acc[j][c].im};
+  }
+}
+
+struct Masses16 {
+  double m2[16];
+};
+
+// out_k = m2_k p_k - 1/4 (2D_eo) t_k at even sites, t = 2 D_oe p (odd sites).
+template <typename R, int RECON, int NBT>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_deo_axpy(Geo g, const cplx<R>* __restrict__ links,
+                                                   const cplx<R>* __restrict__ t,
+                                                   const cplx<R>* __restrict__ p,
+                                                   cplx<R>* __restrict__ out, int nsrc, Masses16 m,
+                                                   int xcd) {
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int cb = logical_block(xcd) * kTile + lane;
+  const size_t hv = g.hv, ss = 3 * hv;
+  const int k0 = grp * NBT;
+  unsigned act = 0;
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
+  if (!act) return;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  Site s;
+  site_geometry(g, 0, cb, s);
+  stencil_part<R, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldIn<R>{t + k0 * ss, ss, hv}, act, acc);
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+    const R m2 = (R)m.m2[k0 + j];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t i = (k0 + j) * ss + c * hv + cb;
+      const cplx<R> pv = p[i];
+      out[i] = {m2 * pv.re - (R)0.25 * acc[j][c].re, m2 * pv.im - (R)0.25 * acc[j][c].im};
+    }
+  }
+}
+
+namespace {
+// Most sources one launch of this shape can take.
+int sources_per_pass(const LaunchShape& sh, size_t csz) {
+  int n = (16 / sh.lps) * sh.nbt;
+  while (n > 1 && !shape_ok(sh, n, csz)) --n;
+  return n;
+}
+}  // namespace
+
+hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, int pout,
+                         const void* in, void* out, int nsrc, double scale, LaunchShape sh,
+                         hipStream_t s) {
+  const size_t csz = cplx_bytes(prec);
+  if (!nbt_lps_instantiated(sh.nbt, sh.lps) || !shape_ok(sh, 1, csz)) return hipErrorInvalidValue;
+  const size_t field = (size_t)3 * g.hv * csz;
+  const int per = sources_per_pass(sh, csz);
+  const unsigned grid = grid_for(g.hv, kTile);
+  for (int k0 = 0; k0 < nsrc; k0 += per) {
+    const int n = std::min(per, nsrc - k0);
+    const int threads = 64 * sh.lps * shape_groups(sh, n);
+    const size_t lds = shape_lds(sh, n, csz);
+    const char* pin = (const char*)in + k0 * field;
+    char* po = (char*)out + k0 * field;
+    hipError_t e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
+      return with_nbt_lps(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
+        hipLaunchKernelGGL((k_dslash<R, RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, g,
+                           (const cplx<R>*)links, pout, (const cplx<R>*)pin, (cplx<R>*)po, n,
+                           (R)scale, sh.xcd);
+        return hipGetLastError();
+      });
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, int nrhs,
+                          const double* m2, const void* in, void* out, void* tmp, LaunchShape sh,
+                          hipStream_t s) {
+  hipError_t e = launch_dslash(g, prec, recon, links, 1, in, tmp, nrhs, 1.0, sh, s);
+  if (e != hipSuccess) return e;
+  const size_t field = (size_t)3 * g.hv * cplx_bytes(prec);
+  const int per = 16;  // Masses16 holds one pass
+  const unsigned grid = grid_for(g.hv, kTile);
+  for (int k0 = 0; k0 < nrhs; k0 += per) {
+    const int n = std::min(per, nrhs - k0);
+    Masses16 m{};
+    for (int k = 0; k < n; ++k) m.m2[k] = m2[k0 + k];
+    const int threads = 64 * ((n + sh.nbt - 1) / sh.nbt);
+    e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
+      return with_nbt(sh.nbt, [&]<int NBT>() {
+        hipLaunchKernelGGL((k_deo_axpy<R, RECON, NBT>), dim3(grid), dim3(threads), 0, s, g,
+                           (const cplx<R>*)links, (const cplx<R>*)((const char*)tmp + k0 * field),
+                           (const cplx<R>*)((const char*)in + k0 * field),
+                           (cplx<R>*)((char*)out + k0 * field), n, m, sh.xcd);
+        return hipGetLastError();
+      });
+    });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace qx

@@ -1,0 +1,564 @@
+// Conjugate-gradient engine on gfx950: the kernels of one CG iteration, of a
+// reliable update and of the initialisation, for a batch of systems.
+//
+// Every engine launch covers all systems of a batch.  Stencil launches give a
+// system blocks of 64 sites; vector launches give each of its sources blocks
+// of 256 complex elements.  A source takes part in a launch only in the phase
+// the kernel serves (PH_RUN for the iteration, PH_RU / PH_RU2 for the update),
+// so converged sources cost nothing but the link loads they share with the
+// others.  Reductions are deterministic: fixed-order wave and block sums into
+// per-block partials, then the last block of the system (agent-scope counter)
+// adds the partials in index order and updates the per-source state.
+//
+// Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd)}, FP64
+// vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv].
+#include <hip/hip_runtime.h>
+
+#include "qx_device.h"
+#include "qx_dispatch.h"
+#include "qx_launch.h"
+
+namespace qx {
+
+namespace {
+
+constexpr int kStatusOk = 0;
+constexpr int kStatusNotConverged = 5;
+constexpr int kStatusBreakdown = 6;
+
+__device__ __forceinline__ const SysDesc& sys_of_block(const SysDesc* __restrict__ sys, int nsys,
+                                                       int b) {
+  int i = 0;
+  while (i + 1 < nsys && b >= sys[i + 1].blk0) ++i;
+  return sys[i];
+}
+
+__device__ __forceinline__ const SysDesc& sys_of_vblock(const SysDesc* __restrict__ sys, int nsys,
+                                                        int b) {
+  int i = 0;
+  while (i + 1 < nsys && b >= sys[i + 1].vblk0) ++i;
+  return sys[i];
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R>* slot(void* base, int i, size_t vs) {
+  return (cplx<R>*)base + i * vs;
+}
+
+// Sources of a system in the given phase, as a bit mask (at most 64 sources).
+__device__ __forceinline__ unsigned long long phase_bits(const SrcState* st, int nsrc, int phase) {
+  unsigned long long m = 0;
+  for (int k = 0; k < nsrc; ++k)
+    if (st[k].phase == phase) m |= 1ull << k;
+  return m;
+}
+
+template <int NBT>
+__device__ __forceinline__ unsigned group_bits(unsigned long long m, int k0) {
+  return (unsigned)(m >> k0) & ((1u << NBT) - 1u);
+}
+
+// Input of the FP64 residual stencil: x_hi + x_lo, the solution after the
+// pending accumulation.
+template <typename Rlo>
+struct SumIn {
+  const cplx<double>* __restrict__ hi;
+  const cplx<Rlo>* __restrict__ lo;
+  size_t ss, hv;
+  __device__ __forceinline__ cplx<double> operator()(int j, int c, int site) const {
+    const cplx<double> a = hi[j * ss + c * hv + site];
+    const cplx<Rlo> b = lo[j * ss + c * hv + site];
+    return {a.re + (double)b.re, a.im + (double)b.im};
+  }
+};
+
+// Vector-launch prologue: the system, source and tile of this block.
+struct VBlock {
+  int k, tile;
+  size_t n, e;  // elements per source vector (3 hv), element of this thread
+};
+
+__device__ __forceinline__ VBlock vblock(const SysDesc& d, int b) {
+  VBlock v;
+  const int rel = b - d.vblk0;
+  v.k = rel / d.vtiles;
+  v.tile = rel - v.k * d.vtiles;
+  v.n = (size_t)3 * d.g.hv;
+  v.e = (size_t)v.tile * kVTile + threadIdx.x;
+  return v;
+}
+
+// Thread 0 of a vector block publishes its partial (valid in thread 0) and
+// learns whether it is the last of `expected` blocks of its system.
+__device__ __forceinline__ bool vpublish(double v, double* dst, unsigned* counter,
+                                         unsigned expected, int* flag_sh) {
+  if (threadIdx.x == 0) {
+    *dst = v;
+    __threadfence();
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    *flag_sh = (prev == expected - 1u);
+  }
+  __syncthreads();
+  const bool last = *flag_sh != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+}  // namespace
+
+// =================================================================== init
+
+// x_lo = 0, p = 0 (and x_hi = 0 without an initial guess); |b|^2 -> bnorm2,
+// stop2 *= bnorm2; a zero source is done at once (x = 0), a non-finite one is
+// a breakdown.
+template <typename R>
+__global__ void __launch_bounds__(256) k_init(const SysDesc* __restrict__ sys, int nsys,
+                                              SrcState* st, int zero_xhi, int xcd) {
+  __shared__ double sh[16];
+  __shared__ int flag;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const VBlock v = vblock(d, b);
+  const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
+  double acc[1] = {0.0};
+  if (v.e < v.n) {
+    slot<R>(d.vlo, 0, vs)[i] = {(R)0, (R)0};
+    slot<R>(d.vlo, 2, vs)[i] = {(R)0, (R)0};
+    if (zero_xhi) slot<double>(d.vhi, 0, vs)[i] = {0.0, 0.0};
+    const cplx<double> bv = slot<double>(d.vhi, 2, vs)[i];
+    acc[0] = bv.re * bv.re + bv.im * bv.im;
+  }
+  block_sum<1>(acc, sh);
+  if (vpublish(acc[0], d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter,
+               (unsigned)(d.nsrc * d.vtiles), &flag)) {
+    for (int k = 0; k < d.nsrc; ++k) {
+      const double t = total_of(d.partials, d.vtiles, k, d.vtiles, sh);
+      if (threadIdx.x == 0) {
+        SrcState& q = st[d.src0 + k];
+        q.bnorm2 = t;
+        q.stop2 *= t;
+        if (t == 0.0) {
+          q.phase = PH_DONE;
+          q.status = kStatusOk;
+          q.relres = 0.0;
+        } else if (!isfinite(t)) {
+          q.phase = PH_DONE;
+          q.status = kStatusBreakdown;
+          q.relres = t;
+        }
+      }
+    }
+    reset_counter(d.counter);
+  }
+}
+
+// x_hi = 0 for zero sources (the solution of A x = 0).
+__global__ void __launch_bounds__(256) k_zero_done(const SysDesc* __restrict__ sys, int nsys,
+                                                   const SrcState* st, int xcd) {
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const VBlock v = vblock(d, b);
+  const SrcState& q = st[d.src0 + v.k];
+  if (!(q.phase == PH_DONE && q.bnorm2 == 0.0) || v.e >= v.n) return;
+  slot<double>(d.vhi, 0, v.n * d.nsrc)[v.k * v.n + v.e] = {0.0, 0.0};
+}
+
+// ============================================================== iteration
+
+// E1: t = 2 D_oe p for running sources.
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDesc* __restrict__ sys, int nsys,
+                                                   const SrcState* st, int xcd) {
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  const unsigned long long run = phase_bits(st + d.src0, d.nsrc, PH_RUN);
+  if (!run) return;
+  const int cb = (b - d.blk0) * kTile + lane;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  const int k0 = grp * NBT;
+  const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(d.g, 1, cb, s);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp,
+                                     FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv}, act, acc);
+  }
+  reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
+  cplx<R>* t = slot<R>(d.vlo, 4, vs);
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (owns_item<LPS>(3 * j + c, dp)) t[(k0 + j) * ss + c * hv + cb] = acc[j][c];
+  }
+}
+
+// E2: Ap = m^2 p - 1/4 (2D_eo) t and Re<p, Ap>; the last block forms alpha
+// (or flags a breakdown when <p, Ap> <= 0 or is not finite).
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDesc* __restrict__ sys, int nsys,
+                                                   SrcState* st, int xcd) {
+  __shared__ double sh[16 * 64];
+  __shared__ double tot[64];
+  __shared__ int flag;
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  SrcState* q0 = st + d.src0;
+  const unsigned long long run = phase_bits(q0, d.nsrc, PH_RUN);
+  if (!run) return;
+  const int bl = b - d.blk0, cb = bl * kTile + lane;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  const int k0 = grp * NBT;
+  const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(d.g, 0, cb, s);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 0, cb, s, dp,
+                                     FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
+  }
+  reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
+  double dot[NBT];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) dot[j] = 0.0;
+  const cplx<R>* p = slot<R>(d.vlo, 2, vs);
+  cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+    const R m2 = (R)q0[k0 + j].m2;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (!owns_item<LPS>(3 * j + c, dp)) continue;
+      const size_t i = (k0 + j) * ss + c * hv + cb;
+      const cplx<R> pv = p[i];
+      const cplx<R> r = {m2 * pv.re - (R)0.25 * acc[j][c].re, m2 * pv.im - (R)0.25 * acc[j][c].im};
+      Ap[i] = r;
+      dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
+    }
+  }
+  const int G = (int)(blockDim.x >> 6) / LPS;
+  group_sum<NBT>(dot, LPS, grp, dp, G, sh, tot);
+  if (publish(tot, d.nsrc, d.partials, d.nblk, bl, d.counter, (unsigned)d.nblk, &flag)) {
+    for (int k = 0; k < d.nsrc; ++k) {
+      if (!(run >> k & 1ull)) continue;
+      const double t = total_of(d.partials, d.nblk, k, d.nblk, sh);
+      if (threadIdx.x == 0) {
+        SrcState& q = q0[k];
+        q.pAp = t;
+        if (!(t > 0.0) || !isfinite(t)) {
+          q.phase = PH_RU;
+          q.reason = RU_FINAL;
+          q.status = kStatusBreakdown;
+        } else {
+          q.alpha = q.rho / t;
+        }
+      }
+    }
+    reset_counter(d.counter);
+  }
+}
+
+// E3: x_lo += alpha p, r -= alpha Ap, |r|^2; the last block decides between
+// continuing (beta), a reliable update, or the end of the iteration budget.
+template <typename R>
+__global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
+                                                 SrcState* st, int xcd) {
+  __shared__ double sh[16];
+  __shared__ int flag;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  SrcState* q0 = st + d.src0;
+  const VBlock v = vblock(d, b);
+  const unsigned long long run = phase_bits(q0, d.nsrc, PH_RUN);
+  if (!(run >> v.k & 1ull)) return;
+  const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
+  double acc[1] = {0.0};
+  if (v.e < v.n) {
+    const R al = (R)q0[v.k].alpha;
+    cplx<R>* x = slot<R>(d.vlo, 0, vs);
+    cplx<R>* r = slot<R>(d.vlo, 1, vs);
+    const cplx<R> pv = slot<R>(d.vlo, 2, vs)[i], av = slot<R>(d.vlo, 3, vs)[i];
+    cplx<R> xv = x[i], rv = r[i];
+    xv.re = fma(al, pv.re, xv.re);
+    xv.im = fma(al, pv.im, xv.im);
+    rv.re = fma(-al, av.re, rv.re);
+    rv.im = fma(-al, av.im, rv.im);
+    x[i] = xv;
+    r[i] = rv;
+    acc[0] = (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+  }
+  block_sum<1>(acc, sh);
+  const unsigned expected = (unsigned)(__popcll(run) * d.vtiles);
+  if (vpublish(acc[0], d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter, expected, &flag)) {
+    for (int k = 0; k < d.nsrc; ++k) {
+      if (!(run >> k & 1ull)) continue;
+      const double rn2 = total_of(d.partials, d.vtiles, k, d.vtiles, sh);
+      if (threadIdx.x == 0) {
+        SrcState& q = q0[k];
+        q.iters += 1;
+        if (!isfinite(rn2)) {
+          q.phase = PH_RU;
+          q.reason = RU_FINAL;
+          q.status = kStatusBreakdown;
+          continue;
+        }
+        const double rn = sqrt(rn2);
+        if (rn > q.rmax) q.rmax = rn;
+        if (q.iters >= q.max_iter) {
+          q.phase = PH_RU;
+          q.reason = RU_FINAL;
+          q.status = kStatusNotConverged;
+        } else if (rn2 <= q.stop2 || rn < q.delta * q.rmax) {
+          q.phase = PH_RU;
+          q.reason = RU_DROP;
+        } else {
+          q.beta = rn2 / q.rho;
+          q.rho = rn2;
+        }
+      }
+    }
+    reset_counter(d.counter);
+  }
+}
+
+// E4: p = r + beta p for running sources.
+template <typename R>
+__global__ void __launch_bounds__(256) k_iter_p(const SysDesc* __restrict__ sys, int nsys,
+                                                const SrcState* st, int xcd) {
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const VBlock v = vblock(d, b);
+  const SrcState& q = st[d.src0 + v.k];
+  if (q.phase != PH_RUN || v.e >= v.n) return;
+  const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
+  const R be = (R)q.beta;
+  const cplx<R> rv = slot<R>(d.vlo, 1, vs)[i];
+  cplx<R>* p = slot<R>(d.vlo, 2, vs);
+  const cplx<R> pv = p[i];
+  p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+}
+
+// ========================================================= reliable update
+
+// R1: t_hi = 2 D_oe (x_hi + x_lo) in FP64 for sources waiting for an update.
+template <typename Rlo, int RECON, int NBT>
+__global__ void __launch_bounds__((kMaxThreads<double, NBT>)) k_ru_doe(const SysDesc* __restrict__ sys, int nsys,
+                                                 const SrcState* st, int xcd) {
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  const unsigned long long ru = phase_bits(st + d.src0, d.nsrc, PH_RU);
+  const int cb = (b - d.blk0) * kTile + lane;
+  const int k0 = grp * NBT;
+  const unsigned act = cb < d.g.hv ? group_bits<NBT>(ru, k0) : 0u;
+  if (!act) return;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  cplx<double> acc[NBT][3];
+  zero_acc<double, NBT>(acc);
+  Site s;
+  site_geometry(d.g, 1, cb, s);
+  stencil_part<double, RECON, NBT, 1>(
+      d.g, (const cplx<double>*)d.links_hi, 1, cb, s, 0,
+      SumIn<Rlo>{slot<double>(d.vhi, 0, vs) + k0 * ss, slot<Rlo>(d.vlo, 0, vs) + k0 * ss, ss, hv},
+      act, acc);
+  cplx<double>* t = slot<double>(d.vhi, 3, vs);
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[(k0 + j) * ss + c * hv + cb] = acc[j][c];
+  }
+}
+
+// R2: x_hi += x_lo, x_lo = 0, r_hi = b - (m^2 x_hi - 1/4 (2D_eo) t_hi) and
+// |r_hi|^2 in FP64; the last block declares convergence on this true residual
+// or prepares the restart of the recurrence (beta, rho, rmax).
+template <typename Rlo, int RECON, int NBT>
+__global__ void __launch_bounds__((kMaxThreads<double, NBT>)) k_ru_residual(const SysDesc* __restrict__ sys, int nsys,
+                                                      SrcState* st, int xcd) {
+  __shared__ double sh[16 * 64];
+  __shared__ double tot[64];
+  __shared__ int flag;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  SrcState* q0 = st + d.src0;
+  const unsigned long long ru = phase_bits(q0, d.nsrc, PH_RU);
+  if (!ru) return;
+  const int bl = b - d.blk0, cb = bl * kTile + lane;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  const int k0 = grp * NBT;
+  const unsigned act = cb < d.g.hv ? group_bits<NBT>(ru, k0) : 0u;
+  double rr[NBT];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) rr[j] = 0.0;
+  if (act) {
+    cplx<double> acc[NBT][3];
+    zero_acc<double, NBT>(acc);
+    Site s;
+    site_geometry(d.g, 0, cb, s);
+    stencil_part<double, RECON, NBT, 1>(d.g, (const cplx<double>*)d.links_hi, 0, cb, s, 0,
+                                        FieldIn<double>{slot<double>(d.vhi, 3, vs) + k0 * ss, ss, hv},
+                                        act, acc);
+    cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
+    cplx<double>* rhi = slot<double>(d.vhi, 1, vs);
+    const cplx<double>* bb = slot<double>(d.vhi, 2, vs);
+    cplx<Rlo>* xlo = slot<Rlo>(d.vlo, 0, vs);
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (!(act >> j & 1u)) continue;
+      const double m2 = q0[k0 + j].m2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const size_t i = (k0 + j) * ss + c * hv + cb;
+        const cplx<Rlo> xl = xlo[i];
+        cplx<double> xv = xhi[i];
+        xv.re += (double)xl.re;
+        xv.im += (double)xl.im;
+        xhi[i] = xv;
+        xlo[i] = {(Rlo)0, (Rlo)0};
+        const cplx<double> bv = bb[i];
+        const cplx<double> r = {bv.re - (m2 * xv.re - 0.25 * acc[j][c].re),
+                                bv.im - (m2 * xv.im - 0.25 * acc[j][c].im)};
+        rhi[i] = r;
+        rr[j] += r.re * r.re + r.im * r.im;
+      }
+    }
+  }
+  const int G = (int)(blockDim.x >> 6);
+  group_sum<NBT>(rr, 1, grp, 0, G, sh, tot);
+  if (publish(tot, d.nsrc, d.partials, d.nblk, bl, d.counter, (unsigned)d.nblk, &flag)) {
+    for (int k = 0; k < d.nsrc; ++k) {
+      if (!(ru >> k & 1ull)) continue;
+      const double r2 = total_of(d.partials, d.nblk, k, d.nblk, sh);
+      if (threadIdx.x == 0) {
+        SrcState& q = q0[k];
+        q.updates += 1;
+        q.relres = sqrt(r2 / q.bnorm2);
+        if (r2 <= q.stop2) {
+          q.phase = PH_DONE;
+          q.status = kStatusOk;
+        } else if (!isfinite(r2)) {
+          q.phase = PH_DONE;
+          q.status = kStatusBreakdown;
+        } else if (q.reason == RU_FINAL) {
+          q.phase = PH_DONE;
+        } else {
+          q.beta = q.reason == RU_INIT ? 0.0 : r2 / q.rho;
+          q.rho = r2;
+          q.rmax = sqrt(r2);
+          q.phase = PH_RU2;
+        }
+      }
+    }
+    reset_counter(d.counter);
+  }
+}
+
+// R3: r = lo(r_hi), p = r + beta p; the last block of the system lets the
+// updated sources iterate again.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ru_finish(const SysDesc* __restrict__ sys, int nsys,
+                                                   SrcState* st, int xcd) {
+  __shared__ int flag;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  SrcState* q0 = st + d.src0;
+  const VBlock v = vblock(d, b);
+  const unsigned long long ru2 = phase_bits(q0, d.nsrc, PH_RU2);
+  if (!(ru2 >> v.k & 1ull)) return;
+  if (v.e < v.n) {
+    const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
+    const R be = (R)q0[v.k].beta;
+    const cplx<double> h = slot<double>(d.vhi, 1, vs)[i];
+    const cplx<R> rv = {(R)h.re, (R)h.im};
+    cplx<R>* p = slot<R>(d.vlo, 2, vs);
+    const cplx<R> pv = p[i];
+    slot<R>(d.vlo, 1, vs)[i] = rv;
+    p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+  }
+  __syncthreads();
+  const unsigned expected = (unsigned)(__popcll(ru2) * d.vtiles);
+  if (vpublish(0.0, d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter, expected, &flag)) {
+    if (threadIdx.x == 0)
+      for (int k = 0; k < d.nsrc; ++k)
+        if (ru2 >> k & 1ull) q0[k].phase = PH_RUN;
+    reset_counter(d.counter);
+  }
+}
+
+// ================================================================ launchers
+
+bool engine_supported(const EngineCfg& c) {
+  const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) && (c.recon_lo == 18 || c.recon_lo == 12);
+  const bool ok_hi = c.recon_hi == 18 || c.recon_hi == 12;
+  const bool ok_shape = nbt_lps_instantiated(c.shape.nbt, c.shape.lps) &&
+                        shape_ok(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo)) &&
+                        shape_groups(c.shape, c.nsrc_max) <= max_waves(c.shape.nbt, 16);
+  return ok_lo && ok_hi && ok_shape && c.nsrc_max >= 1 && c.nsrc_max <= 64 && c.nsys >= 1 &&
+         c.nblk_total >= 1 && c.nvblk_total >= 1;
+}
+
+hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s) {
+  const dim3 grid(c.nvblk_total), block(kVTile);
+  return with_prec(c.prec_lo, [&]<typename R>() {
+    hipLaunchKernelGGL(k_init<R>, grid, block, 0, s, c.d_sys, c.nsys, c.d_st, zero_xhi,
+                       c.shape.xcd);
+    hipLaunchKernelGGL(k_zero_done, grid, block, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+    return hipGetLastError();
+  });
+}
+
+hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
+  const int G = shape_groups(c.shape, c.nsrc_max);
+  const dim3 sgrid(c.nblk_total), sblock(64 * c.shape.lps * G);
+  const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
+  const dim3 vgrid(c.nvblk_total), vblock_(kVTile);
+  return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
+    return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+      hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+                         c.d_st, c.shape.xcd);
+      hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+                         c.d_st, c.shape.xcd);
+      hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+      hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
+  const int G = shape_groups(c.shape, c.nsrc_max);
+  const dim3 sgrid(c.nblk_total), sblock(64 * G);
+  const dim3 vgrid(c.nvblk_total), vblock_(kVTile);
+  return with_prec(c.prec_lo, [&]<typename Rlo>() {
+    return with_nbt(c.shape.nbt, [&]<int NBT>() {
+      if (c.recon_hi == 12) {
+        hipLaunchKernelGGL((k_ru_doe<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                           c.shape.xcd);
+        hipLaunchKernelGGL((k_ru_residual<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
+                           c.d_st, c.shape.xcd);
+      } else {
+        hipLaunchKernelGGL((k_ru_doe<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                           c.shape.xcd);
+        hipLaunchKernelGGL((k_ru_residual<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
+                           c.d_st, c.shape.xcd);
+      }
+      hipLaunchKernelGGL(k_ru_finish<Rlo>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st,
+                         c.shape.xcd);
+      return hipGetLastError();
+    });
+  });
+}
+
+}  // namespace qx

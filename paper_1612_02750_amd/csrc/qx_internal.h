@@ -58,19 +58,25 @@ struct SrcState {
 
 // One system of a solver launch: a lattice, its links in the inner precision
 // and in FP64, and the bases of its vectors inside the workspace.
+// Stencil launches give each system nblk blocks of 64 sites (blocks
+// [blk0, blk0 + nblk)); vector (BLAS) launches give each of its sources
+// vtiles blocks of 256 complex elements (blocks [vblk0, vblk0 + nsrc*vtiles)).
 struct SysDesc {
   Geo g;
   int nsrc;    // sources of this system
   int src0;    // index of its first source in the SrcState array
-  int blk0;    // first block of this system in every engine launch
-  int nblk;    // blocks of this system
+  int blk0, nblk;
+  int vblk0, vtiles;
   const void* links_lo;
   const void* links_hi;
   void* vlo;        // inner precision: x_lo, r, p, Ap (even), t (odd); each [nsrc][3][hv]
   void* vhi;        // FP64: x_hi, r_hi, b (even), t_hi (odd); each [nsrc][3][hv]
-  double* partials; // [nsrc][nblk]
+  double* partials; // [nsrc][nblk] (stencil) or [nsrc][vtiles] (vector)
   unsigned* counter;  // last-block counter of this system (kept at zero between launches)
 };
+
+constexpr int kTile = 64;     // sites per stencil block
+constexpr int kVTile = 256;   // complex elements per vector block
 
 constexpr int kMaxSys = 64;
 

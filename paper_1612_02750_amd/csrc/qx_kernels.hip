@@ -1,51 +1,22 @@
-// gfx950 kernels of libqx.so: packing, index maps, the staggered Dslash, the
-// even-site operator A = m^2 - D_eo D_oe, the conjugate-gradient engine with
-// reliable updates, and the fermion force.
+// gfx950 kernels of libqx.so outside the stencil: packing of gauge fields and
+// colour vectors, the device index maps, the fermion force and its su(3)
+// projection, a deterministic dot product and the bandwidth probe.
 //
 // Operator (textbook Kogut-Susskind form of the staggered operator the paper
 // names in Sec. 4):
 //   (D chi)(x) = 1/2 sum_mu eta_mu(x) [bc U_mu(x) chi(x+mu) - bc U_mu(x-mu)^dag chi(x-mu)]
-// Inside the kernels the links carry eta * bc (folded at pack time) and the
-// stencil computes 2D; the factor 1/2 (or 1/4 for D_eo D_oe) is applied in the
-// epilogue.
+// The packed links carry eta * bc (folded here at pack time); the stencil
+// kernels compute 2D and apply the factor 1/2 (or 1/4 for D_eo D_oe) in
+// their epilogues.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "qx_device.h"
+#include "qx_dispatch.h"
 #include "qx_launch.h"
 
 namespace qx {
-
-namespace {
-
-constexpr int kStatusOk = 0;
-constexpr int kStatusNotConverged = 5;
-constexpr int kStatusBreakdown = 6;
-
-inline unsigned grid_for(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
-
-// Calls f.template operator()<NB>() with the smallest supported NB >= n.
-template <typename F>
-hipError_t with_nb(int n, F&& f) {
-  if (n <= 1) return f.template operator()<1>();
-  if (n <= 2) return f.template operator()<2>();
-  if (n <= 4) return f.template operator()<4>();
-  if (n <= 8) return f.template operator()<8>();
-  if (n <= 12) return f.template operator()<12>();
-  return hipErrorInvalidValue;
-}
-
-template <typename F>
-hipError_t with_prec_recon(int prec, int recon, F&& f) {
-  if (prec == 0 && recon == 18) return f.template operator()<double, 18>();
-  if (prec == 0 && recon == 12) return f.template operator()<double, 12>();
-  if (prec == 1 && recon == 18) return f.template operator()<float, 18>();
-  if (prec == 1 && recon == 12) return f.template operator()<float, 12>();
-  return hipErrorInvalidValue;
-}
-
-}  // namespace
 
 // =================================================================== packing
 
@@ -186,619 +157,6 @@ hipError_t launch_index_maps(const Geo& g, int32_t* lex_of_eo, int32_t* nbr_eo, 
   hipLaunchKernelGGL(k_index_maps, dim3(grid_for(2 * (size_t)g.hv, 256)), dim3(256), 0, s, g,
                      lex_of_eo, nbr_eo);
   return hipGetLastError();
-}
-
-// ============================================================ plain operators
-
-// out_k = scale * (2D in_k) at the sites of parity pout, k < nsrc <= NB.
-template <typename R, int RECON, int NB>
-__global__ void __launch_bounds__(512) k_dslash(Geo g, const cplx<R>* __restrict__ links, int pout,
-                                                const cplx<R>* __restrict__ in,
-                                                cplx<R>* __restrict__ out, int nsrc, R scale,
-                                                int xcd) {
-  const int cb = logical_block(xcd) * blockDim.x + threadIdx.x;
-  if (cb >= g.hv) return;
-  const size_t hv = (size_t)g.hv;
-  const unsigned act = (1u << nsrc) - 1u;
-  cplx<R> acc[NB][3];
-  stencil<R, RECON, NB>(g, links, pout, cb, in, 3 * hv, act, acc);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (k >= nsrc) break;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-      out[(k * 3 + a) * hv + cb] = {scale * acc[k][a].re, scale * acc[k][a].im};
-  }
-}
-
-struct Masses12 {
-  double m2[12];
-};
-
-// out_k = m2_k p_k - 1/4 (2D_eo) t_k at even sites (t = 2 D_oe p on odd sites).
-template <typename R, int RECON, int NB>
-__global__ void __launch_bounds__(512) k_deo_axpy(Geo g, const cplx<R>* __restrict__ links,
-                                                  const cplx<R>* __restrict__ t,
-                                                  const cplx<R>* __restrict__ p,
-                                                  cplx<R>* __restrict__ out, int nsrc, Masses12 m,
-                                                  int xcd) {
-  const int cb = logical_block(xcd) * blockDim.x + threadIdx.x;
-  if (cb >= g.hv) return;
-  const size_t hv = (size_t)g.hv;
-  const unsigned act = (1u << nsrc) - 1u;
-  cplx<R> acc[NB][3];
-  stencil<R, RECON, NB>(g, links, 0, cb, t, 3 * hv, act, acc);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (k >= nsrc) break;
-    const R m2 = (R)m.m2[k];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t j = (k * 3 + a) * hv + cb;
-      const cplx<R> pv = p[j];
-      out[j] = {m2 * pv.re - (R)0.25 * acc[k][a].re, m2 * pv.im - (R)0.25 * acc[k][a].im};
-    }
-  }
-}
-
-hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, int pout,
-                         const void* in, void* out, int nsrc, double scale, LaunchShape sh,
-                         hipStream_t s) {
-  const size_t csz = cplx_bytes(prec);
-  const size_t field = (size_t)3 * g.hv * csz;
-  for (int k0 = 0; k0 < nsrc; k0 += 12) {
-    const int n = nsrc - k0 < 12 ? nsrc - k0 : 12;
-    const char* pin = (const char*)in + k0 * field;
-    char* pout_ = (char*)out + k0 * field;
-    hipError_t e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
-      return with_nb(n, [&]<int NB>() {
-        hipLaunchKernelGGL((k_dslash<R, RECON, NB>), dim3(grid_for(g.hv, sh.block)),
-                           dim3(sh.block), 0, s, g, (const cplx<R>*)links, pout,
-                           (const cplx<R>*)pin, (cplx<R>*)pout_, n, (R)scale, sh.xcd);
-        return hipGetLastError();
-      });
-    });
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, int nrhs,
-                          const double* m2, const void* in, void* out, void* tmp, LaunchShape sh,
-                          hipStream_t s) {
-  hipError_t e = launch_dslash(g, prec, recon, links, 1, in, tmp, nrhs, 1.0, sh, s);
-  if (e != hipSuccess) return e;
-  const size_t field = (size_t)3 * g.hv * cplx_bytes(prec);
-  for (int k0 = 0; k0 < nrhs; k0 += 12) {
-    const int n = nrhs - k0 < 12 ? nrhs - k0 : 12;
-    Masses12 m{};
-    for (int k = 0; k < n; ++k) m.m2[k] = m2[k0 + k];
-    e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
-      return with_nb(n, [&]<int NB>() {
-        hipLaunchKernelGGL((k_deo_axpy<R, RECON, NB>), dim3(grid_for(g.hv, sh.block)),
-                           dim3(sh.block), 0, s, g, (const cplx<R>*)links,
-                           (const cplx<R>*)((const char*)tmp + k0 * field),
-                           (const cplx<R>*)((const char*)in + k0 * field),
-                           (cplx<R>*)((char*)out + k0 * field), n, m, sh.xcd);
-        return hipGetLastError();
-      });
-    });
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-// ==================================================================== engine
-//
-// Every engine launch covers all systems of a batch: block b belongs to the
-// system whose [blk0, blk0 + nblk) range holds it, and each thread handles one
-// checkerboard site for all NB sources of its system.  Sources whose phase
-// does not match the kernel's are skipped, so converged sources cost nothing
-// but the link loads they share with the others.
-//
-// Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd)}, FP64
-// vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv].
-
-namespace {
-
-__device__ __forceinline__ const SysDesc& find_sys(const SysDesc* __restrict__ sys, int nsys,
-                                                   int b) {
-  int i = 0;
-  while (i + 1 < nsys && b >= sys[i + 1].blk0) ++i;
-  return sys[i];
-}
-
-template <int NB>
-__device__ __forceinline__ unsigned phase_mask(const SrcState* st, int nsrc, int phase) {
-  unsigned m = 0;
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k < nsrc && st[k].phase == phase) m |= 1u << k;
-  return m;
-}
-
-template <typename R>
-__device__ __forceinline__ cplx<R>* slot(void* base, int i, size_t vs) {
-  return (cplx<R>*)base + i * vs;
-}
-
-}  // namespace
-
-// Init: x_lo = 0, p = 0, optionally x_hi = 0; |b|^2 -> bnorm2, stop2 *= bnorm2;
-// a zero source is done at once (x = 0), a non-finite one is a breakdown.
-template <typename R, int NB>
-__global__ void __launch_bounds__(512) k_init(const SysDesc* __restrict__ sys, int nsys,
-                                              SrcState* st, int zero_xhi, int xcd) {
-  __shared__ double sh[NB * 16];
-  __shared__ int flag;
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const int bl = b - d.blk0, cb = bl * blockDim.x + threadIdx.x;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  double nb2[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) nb2[k] = 0.0;
-  if (cb < d.g.hv) {
-    cplx<R>* xlo = slot<R>(d.vlo, 0, vs);
-    cplx<R>* p = slot<R>(d.vlo, 2, vs);
-    cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
-    const cplx<double>* bb = slot<double>(d.vhi, 2, vs);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      if (k >= d.nsrc) break;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const size_t j = (k * 3 + a) * hv + cb;
-        xlo[j] = {(R)0, (R)0};
-        p[j] = {(R)0, (R)0};
-        if (zero_xhi) xhi[j] = {0.0, 0.0};
-        const cplx<double> v = bb[j];
-        nb2[k] += v.re * v.re + v.im * v.im;
-      }
-    }
-  }
-  block_sum<NB>(nb2, sh);
-  if (publish_partials<NB>(nb2, d.nsrc, d.partials, d.nblk, bl, d.counter, &flag)) {
-    double tot[NB];
-    total_partials<NB>(tot, d.nsrc, d.partials, d.nblk, d.counter, sh);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NB && k < d.nsrc; ++k) {
-        SrcState& q = st[d.src0 + k];
-        q.bnorm2 = tot[k];
-        q.stop2 *= tot[k];
-        if (tot[k] == 0.0) {
-          q.phase = PH_DONE;
-          q.status = kStatusOk;
-          q.relres = 0.0;
-        } else if (!isfinite(tot[k])) {
-          q.phase = PH_DONE;
-          q.status = kStatusBreakdown;
-          q.relres = tot[k];
-        }
-      }
-    }
-  }
-}
-
-// x_hi = 0 for zero sources (the solution of A x = 0).
-template <int NB>
-__global__ void __launch_bounds__(512) k_zero_done(const SysDesc* __restrict__ sys, int nsys,
-                                                   const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const int cb = (b - d.blk0) * blockDim.x + threadIdx.x;
-  if (cb >= d.g.hv) return;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
-  for (int k = 0; k < NB && k < d.nsrc; ++k) {
-    const SrcState& q = st[d.src0 + k];
-    if (q.phase == PH_DONE && q.bnorm2 == 0.0)
-      for (int a = 0; a < 3; ++a) xhi[(k * 3 + a) * hv + cb] = {0.0, 0.0};
-  }
-}
-
-// E1: t = 2 D_oe p for running sources.
-template <typename R, int RECON, int NB>
-__global__ void __launch_bounds__(512) k_iter_doe(const SysDesc* __restrict__ sys, int nsys,
-                                                  const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const unsigned act = phase_mask<NB>(st + d.src0, d.nsrc, PH_RUN);
-  const int cb = (b - d.blk0) * blockDim.x + threadIdx.x;
-  if (!act || cb >= d.g.hv) return;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  const cplx<R>* p = slot<R>(d.vlo, 2, vs);
-  cplx<R>* t = slot<R>(d.vlo, 4, vs);
-  cplx<R> acc[NB][3];
-  stencil<R, RECON, NB>(d.g, (const cplx<R>*)d.links_lo, 1, cb, p, 3 * hv, act, acc);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (!(act >> k & 1u)) continue;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) t[(k * 3 + a) * hv + cb] = acc[k][a];
-  }
-}
-
-// E2: Ap = m^2 p - 1/4 (2D_eo) t, Re<p, Ap>; the last block forms alpha.
-template <typename R, int RECON, int NB>
-__global__ void __launch_bounds__(512) k_iter_deo(const SysDesc* __restrict__ sys, int nsys,
-                                                  SrcState* st, int xcd) {
-  __shared__ double sh[NB * 16];
-  __shared__ int flag;
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
-  const unsigned act = phase_mask<NB>(q0, d.nsrc, PH_RUN);
-  if (!act) return;
-  const int bl = b - d.blk0, cb = bl * blockDim.x + threadIdx.x;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  double dot[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) dot[k] = 0.0;
-  if (cb < d.g.hv) {
-    const cplx<R>* p = slot<R>(d.vlo, 2, vs);
-    cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
-    const cplx<R>* t = slot<R>(d.vlo, 4, vs);
-    cplx<R> acc[NB][3];
-    stencil<R, RECON, NB>(d.g, (const cplx<R>*)d.links_lo, 0, cb, t, 3 * hv, act, acc);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      if (!(act >> k & 1u)) continue;
-      const R m2 = (R)q0[k].m2;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const size_t j = (k * 3 + a) * hv + cb;
-        const cplx<R> pv = p[j];
-        const cplx<R> r = {m2 * pv.re - (R)0.25 * acc[k][a].re,
-                           m2 * pv.im - (R)0.25 * acc[k][a].im};
-        Ap[j] = r;
-        dot[k] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
-      }
-    }
-  }
-  block_sum<NB>(dot, sh);
-  if (publish_partials<NB>(dot, d.nsrc, d.partials, d.nblk, bl, d.counter, &flag)) {
-    double tot[NB];
-    total_partials<NB>(tot, d.nsrc, d.partials, d.nblk, d.counter, sh);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NB && k < d.nsrc; ++k) {
-        if (!(act >> k & 1u)) continue;
-        SrcState& q = q0[k];
-        q.pAp = tot[k];
-        if (!(tot[k] > 0.0) || !isfinite(tot[k])) {
-          q.phase = PH_RU;
-          q.reason = RU_FINAL;
-          q.status = kStatusBreakdown;
-        } else {
-          q.alpha = q.rho / tot[k];
-        }
-      }
-    }
-  }
-}
-
-// E3: x_lo += alpha p, r -= alpha Ap, |r|^2; the last block decides between
-// continuing (beta), a reliable update, or the end of the iteration budget.
-template <typename R, int NB>
-__global__ void __launch_bounds__(512) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
-                                                 SrcState* st, int xcd) {
-  __shared__ double sh[NB * 16];
-  __shared__ int flag;
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
-  const unsigned act = phase_mask<NB>(q0, d.nsrc, PH_RUN);
-  if (!act) return;
-  const int bl = b - d.blk0, cb = bl * blockDim.x + threadIdx.x;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  double rr[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) rr[k] = 0.0;
-  if (cb < d.g.hv) {
-    cplx<R>* x = slot<R>(d.vlo, 0, vs);
-    cplx<R>* r = slot<R>(d.vlo, 1, vs);
-    const cplx<R>* p = slot<R>(d.vlo, 2, vs);
-    const cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      if (!(act >> k & 1u)) continue;
-      const R al = (R)q0[k].alpha;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const size_t j = (k * 3 + a) * hv + cb;
-        const cplx<R> pv = p[j], av = Ap[j];
-        cplx<R> xv = x[j], rv = r[j];
-        xv.re = fma(al, pv.re, xv.re);
-        xv.im = fma(al, pv.im, xv.im);
-        rv.re = fma(-al, av.re, rv.re);
-        rv.im = fma(-al, av.im, rv.im);
-        x[j] = xv;
-        r[j] = rv;
-        rr[k] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
-      }
-    }
-  }
-  block_sum<NB>(rr, sh);
-  if (publish_partials<NB>(rr, d.nsrc, d.partials, d.nblk, bl, d.counter, &flag)) {
-    double tot[NB];
-    total_partials<NB>(tot, d.nsrc, d.partials, d.nblk, d.counter, sh);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NB && k < d.nsrc; ++k) {
-        if (!(act >> k & 1u)) continue;
-        SrcState& q = q0[k];
-        const double rn2 = tot[k];
-        q.iters += 1;
-        if (!isfinite(rn2)) {
-          q.phase = PH_RU;
-          q.reason = RU_FINAL;
-          q.status = kStatusBreakdown;
-          continue;
-        }
-        const double rn = sqrt(rn2);
-        if (rn > q.rmax) q.rmax = rn;
-        if (q.iters >= q.max_iter) {
-          q.phase = PH_RU;
-          q.reason = RU_FINAL;
-          q.status = kStatusNotConverged;
-        } else if (rn2 <= q.stop2 || rn < q.delta * q.rmax) {
-          q.phase = PH_RU;
-          q.reason = RU_DROP;
-        } else {
-          q.beta = rn2 / q.rho;
-          q.rho = rn2;
-        }
-      }
-    }
-  }
-}
-
-// E4: p = r + beta p for running sources.
-template <typename R, int NB>
-__global__ void __launch_bounds__(512) k_iter_p(const SysDesc* __restrict__ sys, int nsys,
-                                                const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const SrcState* q0 = st + d.src0;
-  const unsigned act = phase_mask<NB>(q0, d.nsrc, PH_RUN);
-  const int cb = (b - d.blk0) * blockDim.x + threadIdx.x;
-  if (!act || cb >= d.g.hv) return;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  const cplx<R>* r = slot<R>(d.vlo, 1, vs);
-  cplx<R>* p = slot<R>(d.vlo, 2, vs);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (!(act >> k & 1u)) continue;
-    const R be = (R)q0[k].beta;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t j = (k * 3 + a) * hv + cb;
-      const cplx<R> rv = r[j], pv = p[j];
-      p[j] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
-    }
-  }
-}
-
-// R1: x_hi += x_lo, x_lo = 0 for sources waiting for a reliable update.
-template <typename R, int NB>
-__global__ void __launch_bounds__(512) k_ru_accum(const SysDesc* __restrict__ sys, int nsys,
-                                                  const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const unsigned act = phase_mask<NB>(st + d.src0, d.nsrc, PH_RU);
-  const int cb = (b - d.blk0) * blockDim.x + threadIdx.x;
-  if (!act || cb >= d.g.hv) return;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  cplx<R>* xlo = slot<R>(d.vlo, 0, vs);
-  cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (!(act >> k & 1u)) continue;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t j = (k * 3 + a) * hv + cb;
-      const cplx<R> v = xlo[j];
-      cplx<double> h = xhi[j];
-      h.re += (double)v.re;
-      h.im += (double)v.im;
-      xhi[j] = h;
-      xlo[j] = {(R)0, (R)0};
-    }
-  }
-}
-
-// R2: t_hi = 2 D_oe x_hi in FP64.
-template <int RECON, int NB>
-__global__ void __launch_bounds__(512) k_ru_doe(const SysDesc* __restrict__ sys, int nsys,
-                                                const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const unsigned act = phase_mask<NB>(st + d.src0, d.nsrc, PH_RU);
-  const int cb = (b - d.blk0) * blockDim.x + threadIdx.x;
-  if (!act || cb >= d.g.hv) return;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  const cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
-  cplx<double>* t = slot<double>(d.vhi, 3, vs);
-  cplx<double> acc[NB][3];
-  stencil<double, RECON, NB>(d.g, (const cplx<double>*)d.links_hi, 1, cb, xhi, 3 * hv, act, acc);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (!(act >> k & 1u)) continue;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) t[(k * 3 + a) * hv + cb] = acc[k][a];
-  }
-}
-
-// R3: r_hi = b - (m^2 x_hi - 1/4 (2D_eo) t_hi) and |r_hi|^2 in FP64; the last
-// block declares convergence on this true residual or prepares the restart
-// of the recurrence (beta, rho, rmax).
-template <int RECON, int NB>
-__global__ void __launch_bounds__(512) k_ru_residual(const SysDesc* __restrict__ sys, int nsys,
-                                                     SrcState* st, int xcd) {
-  __shared__ double sh[NB * 16];
-  __shared__ int flag;
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
-  const unsigned act = phase_mask<NB>(q0, d.nsrc, PH_RU);
-  if (!act) return;
-  const int bl = b - d.blk0, cb = bl * blockDim.x + threadIdx.x;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  double rr[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) rr[k] = 0.0;
-  if (cb < d.g.hv) {
-    const cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
-    cplx<double>* rhi = slot<double>(d.vhi, 1, vs);
-    const cplx<double>* bb = slot<double>(d.vhi, 2, vs);
-    const cplx<double>* t = slot<double>(d.vhi, 3, vs);
-    cplx<double> acc[NB][3];
-    stencil<double, RECON, NB>(d.g, (const cplx<double>*)d.links_hi, 0, cb, t, 3 * hv, act, acc);
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      if (!(act >> k & 1u)) continue;
-      const double m2 = q0[k].m2;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const size_t j = (k * 3 + a) * hv + cb;
-        const cplx<double> xv = xhi[j], bv = bb[j];
-        const cplx<double> r = {bv.re - (m2 * xv.re - 0.25 * acc[k][a].re),
-                                bv.im - (m2 * xv.im - 0.25 * acc[k][a].im)};
-        rhi[j] = r;
-        rr[k] += r.re * r.re + r.im * r.im;
-      }
-    }
-  }
-  block_sum<NB>(rr, sh);
-  if (publish_partials<NB>(rr, d.nsrc, d.partials, d.nblk, bl, d.counter, &flag)) {
-    double tot[NB];
-    total_partials<NB>(tot, d.nsrc, d.partials, d.nblk, d.counter, sh);
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < NB && k < d.nsrc; ++k) {
-        if (!(act >> k & 1u)) continue;
-        SrcState& q = q0[k];
-        const double r2 = tot[k];
-        q.updates += 1;
-        q.relres = sqrt(r2 / q.bnorm2);
-        if (r2 <= q.stop2) {
-          q.phase = PH_DONE;
-          q.status = kStatusOk;
-        } else if (!isfinite(r2)) {
-          q.phase = PH_DONE;
-          q.status = kStatusBreakdown;
-        } else if (q.reason == RU_FINAL) {
-          q.phase = PH_DONE;
-        } else {
-          q.beta = q.reason == RU_INIT ? 0.0 : r2 / q.rho;
-          q.rho = r2;
-          q.rmax = sqrt(r2);
-          q.phase = PH_RU2;
-        }
-      }
-    }
-  }
-}
-
-// R4: r = lo(r_hi), p = r + beta p.
-template <typename R, int NB>
-__global__ void __launch_bounds__(512) k_ru_finish(const SysDesc* __restrict__ sys, int nsys,
-                                                   const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = find_sys(sys, nsys, b);
-  const SrcState* q0 = st + d.src0;
-  const unsigned act = phase_mask<NB>(q0, d.nsrc, PH_RU2);
-  const int cb = (b - d.blk0) * blockDim.x + threadIdx.x;
-  if (!act || cb >= d.g.hv) return;
-  const size_t hv = d.g.hv, vs = 3 * hv * d.nsrc;
-  cplx<R>* r = slot<R>(d.vlo, 1, vs);
-  cplx<R>* p = slot<R>(d.vlo, 2, vs);
-  const cplx<double>* rhi = slot<double>(d.vhi, 1, vs);
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (!(act >> k & 1u)) continue;
-    const R be = (R)q0[k].beta;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const size_t j = (k * 3 + a) * hv + cb;
-      const cplx<double> h = rhi[j];
-      const cplx<R> rv = {(R)h.re, (R)h.im};
-      const cplx<R> pv = p[j];
-      r[j] = rv;
-      p[j] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
-    }
-  }
-}
-
-// R5: sources whose update is complete resume iterating.
-__global__ void __launch_bounds__(256) k_ru_commit(SrcState* st, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    if (st[i].phase == PH_RU2) st[i].phase = PH_RUN;
-}
-
-bool engine_supported(const EngineCfg& c) {
-  const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) && (c.recon_lo == 18 || c.recon_lo == 12);
-  const bool ok_hi = c.recon_hi == 18 || c.recon_hi == 12;
-  const bool ok_nb = c.nb >= 1 && c.nb <= 12;
-  const bool ok_bs = c.shape.block == 64 || c.shape.block == 128 || c.shape.block == 256 ||
-                     c.shape.block == 512;
-  return ok_lo && ok_hi && ok_nb && ok_bs && c.nsys >= 1 && c.nblk_total >= 1;
-}
-
-namespace {
-template <typename F>
-hipError_t with_lo(const EngineCfg& c, F&& f) {
-  return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
-    return with_nb(c.nb, [&]<int NB>() { return f.template operator()<R, RECON, NB>(); });
-  });
-}
-}  // namespace
-
-hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s) {
-  const dim3 grid(c.nblk_total), block(c.shape.block);
-  return with_lo(c, [&]<typename R, int RECON, int NB>() {
-    hipLaunchKernelGGL((k_init<R, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st, zero_xhi,
-                       c.shape.xcd);
-    hipLaunchKernelGGL((k_zero_done<NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    return hipGetLastError();
-  });
-}
-
-hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
-  const dim3 grid(c.nblk_total), block(c.shape.block);
-  return with_lo(c, [&]<typename R, int RECON, int NB>() {
-    hipLaunchKernelGGL((k_iter_doe<R, RECON, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_deo<R, RECON, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_xr<R, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_p<R, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    return hipGetLastError();
-  });
-}
-
-hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
-  const dim3 grid(c.nblk_total), block(c.shape.block);
-  return with_lo(c, [&]<typename R, int RECON, int NB>() {
-    hipLaunchKernelGGL((k_ru_accum<R, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    if (c.recon_hi == 12) {
-      hipLaunchKernelGGL((k_ru_doe<12, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                         c.shape.xcd);
-      hipLaunchKernelGGL((k_ru_residual<12, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                         c.shape.xcd);
-    } else {
-      hipLaunchKernelGGL((k_ru_doe<18, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                         c.shape.xcd);
-      hipLaunchKernelGGL((k_ru_residual<18, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                         c.shape.xcd);
-    }
-    hipLaunchKernelGGL((k_ru_finish<R, NB>), grid, block, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    hipLaunchKernelGGL(k_ru_commit, dim3(1), dim3(256), 0, s, c.d_st, c.nsrc_total);
-    return hipGetLastError();
-  });
 }
 
 // ===================================================================== force

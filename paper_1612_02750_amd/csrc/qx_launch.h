@@ -5,10 +5,32 @@
 
 namespace qx {
 
+// Launch shape of the stencil kernels: every block covers 64 sites with
+// lps * groups wavefronts; lps wavefronts share the eight hops of a site,
+// each group takes nbt sources (groups = ceil(nsrc / nbt)).
 struct LaunchShape {
-  int block = 256;  // threads per block
-  int xcd = 1;      // XCD-contiguous block order
+  int nbt = 1;  // sources per thread: 1, 2 or 4
+  int lps = 1;  // wavefronts per site: 1, 2, 4 or 8
+  int xcd = 1;  // XCD-contiguous block order
 };
+
+inline int shape_groups(const LaunchShape& s, int nsrc) { return (nsrc + s.nbt - 1) / s.nbt; }
+// LDS bytes of the hop reduction (0 without hop splitting).
+inline size_t shape_lds(const LaunchShape& s, int nsrc, size_t cplx_sz) {
+  return s.lps > 1 ? (size_t)shape_groups(s, nsrc) * s.lps * 3 * 64 * cplx_sz : 0;
+}
+// Most wavefronts per stencil block: 16, or 8 when a thread holds more than
+// 8 bytes of real accumulators per colour (FP64 with 2+ sources, FP32 with 4),
+// which then get up to 256 VGPRs.
+inline int max_waves(int nbt, size_t cplx_sz) { return (cplx_sz / 2) * nbt > 8 ? 8 : 16; }
+// Is the shape launchable for nsrc sources with complex numbers of cplx_sz bytes?
+inline bool shape_ok(const LaunchShape& s, int nsrc, size_t cplx_sz) {
+  const bool nbt_ok = s.nbt == 1 || s.nbt == 2 || s.nbt == 4;
+  const bool lps_ok = s.lps == 1 || s.lps == 2 || s.lps == 4 || s.lps == 8;
+  if (!nbt_ok || !lps_ok || nsrc < 1) return false;
+  const int waves = s.lps * shape_groups(s, nsrc);
+  return waves <= max_waves(s.nbt, cplx_sz) && shape_lds(s, nsrc, cplx_sz) <= 64 * 1024;
+}
 
 // Bytes of one complex number of the given precision (QX_PREC_F64 = 0 -> 16, F32 -> 8).
 inline size_t cplx_bytes(int prec) { return prec == 0 ? 16 : 8; }
@@ -21,7 +43,8 @@ hipError_t launch_unpack_field(const Geo& g, int nrhs, int prec, const void* pac
                                hipStream_t s);
 hipError_t launch_index_maps(const Geo& g, int32_t* lex_of_eo, int32_t* nbr_eo, hipStream_t s);
 
-// out = scale * (2D) in, from parity 1 - pout to pout, nsrc sources (any count).
+// out = scale * (2D) in, from parity 1 - pout to pout, nsrc sources (any count;
+// passes of at most 16 * nbt sources).
 hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, int pout,
                          const void* in, void* out, int nsrc, double scale, LaunchShape sh,
                          hipStream_t s);
@@ -36,9 +59,10 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
 // states, the inner precision and link storage, the FP64 link storage, the
 // number of sources each thread handles (nb), and the launch shape.
 struct EngineCfg {
-  int prec_lo = 0, recon_lo = 18, recon_hi = 18, nb = 1;
+  int prec_lo = 0, recon_lo = 18, recon_hi = 18;
+  int nsrc_max = 1;  // most sources of any system (sets the groups of a block)
   LaunchShape shape;
-  int nsys = 0, nblk_total = 0, nsrc_total = 0;
+  int nsys = 0, nblk_total = 0, nvblk_total = 0, nsrc_total = 0;
   const SysDesc* d_sys = nullptr;
   SrcState* d_st = nullptr;
 };

@@ -99,17 +99,43 @@ def test_dslash_multi_rhs(qx, nrhs, prec, recon, tol):
     assert err <= tol
 
 
-@pytest.mark.parametrize("block,xcd", [(64, 0), (128, 1), (256, 0), (512, 1)])
-def test_dslash_launch_shapes(qx, block, xcd):
-    dims = (6, 4, 2, 8)  # V/2 = 192: ragged against every block size
-    lat = qx.Lattice(dims)
+SHAPES_NL = [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2)]
+
+
+@pytest.mark.parametrize("nbt,lps", SHAPES_NL)
+@pytest.mark.parametrize("prec,recon,tol", [("f64", 18, 1e-13), ("f32", 12, 1e-5)])
+def test_dslash_launch_shapes(qx, nbt, lps, prec, recon, tol):
+    """Every compiled launch shape (sources per thread, wavefronts per site), with
+    V/2 = 192 ragged against the 64-site tiles and a source count that leaves
+    partly filled groups."""
+    dims = (6, 4, 2, 8)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
     U = gauge(dims, seed=4)
-    g = qx.Gauge(lat, to_dev(U), "f64", 18)
-    g.set_launch(2, block, xcd)
-    chi = synth.gauss_source(2, lat.hv, 8)
-    out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi)), 1, 2), 2))
-    for k in range(2):
-        assert rel(out[k], oracle.dslash_eo(dims, U, chi[k], 1)) <= 1e-13
+    g = qx.Gauge(lat, to_dev(U), prec, recon)
+    nrhs = 5
+    g.set_launch(nrhs, nbt, lps, (nbt + lps) % 2)
+    chi = synth.gauss_source(nrhs, lat.hv, 8)
+    out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), 1, nrhs), nrhs, prec))
+    for k in range(nrhs):
+        ref = oracle.dslash_eo(dims, U, chi[k], 1, oracle.BC_T_ANTIPERIODIC)
+        assert rel(out[k], ref) <= tol, (k, nbt, lps)
+
+
+@pytest.mark.parametrize("nbt,lps", SHAPES_NL)
+def test_cg_launch_shapes(qx, nbt, lps):
+    """The CG engine under every launch shape: 3 sources of different masses."""
+    dims = (4, 6, 4, 4)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=5)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    g32.set_launch(3, nbt, lps, 1)
+    masses = [0.1, 0.3, 0.05]
+    b = synth.gauss_source(3, lat.hv, 6)
+    x, st = qx.cg(g64, to_dev(b), masses, glo=g32, tol=1e-10)
+    _check_solution(dims, U, masses, b, to_host(x), st)
+    assert g32.launch(3) == (nbt, lps, 1)
 
 
 def test_dslash_32_4_sampled(qx):
