@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the 32^4 twelve-source comparison")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the dominant-kernel timing and the copy probe (for counter runs)")
     return ap.parse_args()
@@ -91,6 +93,52 @@ def copy_probe(torch, qx, nb=1 << 30):
     copy_gbs = 2 * nb / t_copy / 1e9
     log(f"copy probe: {nb} bytes, {t_copy * 1e6:.1f} us, {copy_gbs:.0f} GB/s (read + write)")
     return copy_gbs
+
+
+def multi_rhs(torch, qx, synth):
+    """32^4 Haar links, 12 Gaussian sources, m = 0.02, tol 1e-10: the twelve
+    sources solved together (FP32 12-real inner iteration, FP64 reliable
+    updates, one batch) against plain FP64 CG solving them one after another."""
+    dims, m, nsrc = (32, 32, 32, 32), 0.02, 12
+    lat = qx.Lattice(dims)
+    Ud = torch.from_numpy(synth.haar_gauge(dims, 0)).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", 18)
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    del Ud
+    shape12 = g32.tune(nsrc)
+    shape1 = g64.tune(1)
+    bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
+    x_mx = torch.empty_like(bd)
+    mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=1e-10, mode=qx.CG_MIXED_F32)
+    mixed.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mixed.solve()
+    torch.cuda.synchronize()
+    t_mx = time.perf_counter() - t0
+    x_64 = torch.empty_like(bd)
+    plains = [qx.Batch([(g64, None, bd[k:k + 1], [m], x_64[k:k + 1])], tol=1e-10, mode=qx.CG_FP64)
+              for k in range(nsrc)]
+    plains[0].solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st64 = [p.solve()[0] for p in plains]
+    torch.cuda.synchronize()
+    t_64 = time.perf_counter() - t0
+    out = {
+        "workload": "32^4 Haar links, 12 Gaussian sources, m=0.02, tol 1e-10",
+        "mixed_batch_12_ms": round(t_mx * 1e3, 2),
+        "fp64_sequential_12_ms": round(t_64 * 1e3, 2),
+        "speedup": round(t_64 / t_mx, 3),
+        "mixed_iters_max": max(s.iters for s in st),
+        "fp64_iters_max": max(s.iters for s in st64),
+        "max_true_rel_residual": max(max(s.true_rel_residual for s in st),
+                                     max(s.true_rel_residual for s in st64)),
+        "launch_shape_f32_12src": list(shape12),
+        "launch_shape_f64_1src": list(shape1),
+    }
+    log(f"32^4 x 12 sources: {out}")
+    return out
 
 
 def main():
@@ -189,6 +237,9 @@ def main():
 
     copy_gbs = copy_probe(torch, qx)
 
+    multi = None if args.no_multi else multi_rhs(torch, qx, synth)
+
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -249,6 +300,7 @@ def main():
             "sites_per_launch": hv,
         },
         "dslash_32^4": d32,
+        "multi_rhs_32^4": multi,
         "copy_probe_gbs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
     }

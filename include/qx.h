@@ -90,12 +90,20 @@ typedef struct qx_lattice qx_lattice_t;
 typedef struct qx_gauge qx_gauge_t;
 typedef struct qx_batch qx_batch_t;
 
+/* engines of the CG iteration */
+enum {
+  QX_ENGINE_AUTO = 0,      /* persistent when every stencil tile gets its own block, else launches */
+  QX_ENGINE_LAUNCH = 1,    /* three kernel launches per iteration (graph-captured in batches) */
+  QX_ENGINE_PERSISTENT = 2 /* one cooperative launch runs many iterations with grid barriers */
+};
+
 /* Solver parameters.  tol: relative residual |b - A x| / |b| to reach, measured
    in FP64 on the returned x.  max_iter: cap on inner iterations per source.
    delta: reliable-update trigger, an update happens when |r| < delta * max|r|
    since the last update (ignored by QX_CG_FP64, which updates only to confirm
    convergence).  use_x0: x holds an initial guess on entry.  chunk: inner
-   iterations enqueued between host convergence checks (0 = default). */
+   iterations enqueued between host convergence checks (0 = default).
+   engine: QX_ENGINE_*. */
 typedef struct {
   double tol;
   int max_iter;
@@ -103,6 +111,7 @@ typedef struct {
   double delta;
   int use_x0;
   int chunk;
+  int engine;
 } qx_cg_params_t;
 
 /* Per-source solver statistics. */

@@ -24,6 +24,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTUNITARY, ENOTCONVERGED, EBREAKDOWN, ENOLIB = range
 BC_T_ANTIPERIODIC = 1
 PREC_F64, PREC_F32 = 0, 1
 CG_FP64, CG_MIXED_F32 = 0, 1
+ENGINE_AUTO, ENGINE_LAUNCH, ENGINE_PERSISTENT = 0, 1, 2
 
 _PREC = {"f64": PREC_F64, "f32": PREC_F32, PREC_F64: PREC_F64, PREC_F32: PREC_F32}
 
@@ -36,7 +37,8 @@ class QXError(RuntimeError):
 
 class _Params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("mode", ctypes.c_int),
-                ("delta", ctypes.c_double), ("use_x0", ctypes.c_int), ("chunk", ctypes.c_int)]
+                ("delta", ctypes.c_double), ("use_x0", ctypes.c_int), ("chunk", ctypes.c_int),
+                ("engine", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -271,8 +273,9 @@ def apply_A(g: Gauge, packed_in, masses: Sequence[float], out=None, tmp=None, st
 
 # ------------------------------------------------------------------ solver
 
-def _params(tol, max_iter, mode, delta, use_x0, chunk):
-    return _Params(float(tol), int(max_iter), int(mode), float(delta), int(use_x0), int(chunk))
+def _params(tol, max_iter, mode, delta, use_x0, chunk, engine=ENGINE_AUTO):
+    return _Params(float(tol), int(max_iter), int(mode), float(delta), int(use_x0), int(chunk),
+                   int(engine))
 
 
 def _stats(arr, n):
@@ -281,7 +284,8 @@ def _stats(arr, n):
 
 
 def cg(g64: Gauge, b, masses, glo: Optional[Gauge] = None, tol=1e-10, max_iter=100000,
-       mode=None, delta=0.1, x0=None, chunk=0, ws=None, stream=None, raise_on_fail=True):
+       mode=None, delta=0.1, x0=None, chunk=0, ws=None, stream=None, raise_on_fail=True,
+       engine=ENGINE_AUTO):
     """Solve (m_s^2 - D_eo D_oe) x_s = b_s; b (nrhs, V/2, 3) complex128.  Returns (x, stats).
     mode defaults to mixed FP32/FP64 when glo is given, else FP64."""
     torch = _torch()
@@ -293,7 +297,7 @@ def cg(g64: Gauge, b, masses, glo: Optional[Gauge] = None, tol=1e-10, max_iter=1
         masses = [float(masses)] * nrhs
     if mode is None:
         mode = CG_MIXED_F32 if glo is not None else CG_FP64
-    p = _params(tol, max_iter, mode, delta, x0 is not None, chunk)
+    p = _params(tol, max_iter, mode, delta, x0 is not None, chunk, engine)
     n = ctypes.c_size_t()
     _check(L.qx_cg_workspace_bytes(lat._h, ctypes.byref(p), nrhs, ctypes.byref(n)))
     if ws is None:
@@ -313,11 +317,11 @@ class Batch:
     one launch per CG step for all of them, replayed from a captured HIP graph."""
 
     def __init__(self, systems, tol=1e-10, max_iter=100000, mode=CG_MIXED_F32, delta=0.1,
-                 chunk=0, stream=None):
+                 chunk=0, stream=None, engine=ENGINE_AUTO):
         """systems: list of (g64, glo_or_None, b (nrhs,V/2,3), masses, x_out)."""
         L = load()
         self.systems = systems
-        self.p = _params(tol, max_iter, mode, delta, 0, chunk)
+        self.p = _params(tol, max_iter, mode, delta, 0, chunk, engine)
         arr = (_System * len(systems))()
         self._masses = []
         self.nsrc = 0

@@ -339,7 +339,7 @@ struct SysSpec {
 };
 
 struct Layout {
-  size_t sys_off = 0, st_off = 0, total = 0;
+  size_t sys_off = 0, st_off = 0, gs_off = 0, total = 0;
   std::vector<size_t> counter_off, partial_off, vlo_off, vhi_off;
   std::vector<int> nblk_max;
 };
@@ -355,6 +355,8 @@ Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
   size_t nsrc = 0;
   for (const auto& s : specs) nsrc += s.nrhs;
   off = align_up(off + sizeof(SrcState) * nsrc, 256);
+  L.gs_off = off;
+  off = align_up(off + sizeof(GridSync), 256);
   for (const auto& s : specs) {
     const Geo& g = s.g64->geo;
     const int nblk = (g.hv + kTile - 1) / kTile;
@@ -381,6 +383,8 @@ int check_params(const qx_cg_params_t* p) {
   if (p->mode == QX_CG_MIXED_F32 && !(p->delta > 0.0 && p->delta < 1.0))
     return fail(QX_EINVAL, "solver: delta must be in (0, 1) for the mixed mode");
   if (p->chunk < 0) return fail(QX_EINVAL, "solver: chunk must be >= 0");
+  if (p->engine < QX_ENGINE_AUTO || p->engine > QX_ENGINE_PERSISTENT)
+    return fail(QX_EINVAL, "solver: unknown engine %d", p->engine);
   return QX_OK;
 }
 
@@ -423,10 +427,13 @@ struct qx_batch {
   EngineCfg cfg;
   std::vector<SysDesc> sys;
   std::vector<SrcState> st0;
-  SrcState* h_st = nullptr;  // pinned
+  SrcState* h_st = nullptr;  // pinned mirror of the workspace from the states to the barrier word
+  GridSync* h_gs = nullptr;  // inside h_st's buffer
   char* ws = nullptr;
   int chunk = 16, ru_every = 4;
   bool use_graph = false;
+  bool persistent = false;
+  int pgrid = 0;
   hipGraphExec_t graph = nullptr;
   hipStream_t graph_stream = nullptr;
 
@@ -509,9 +516,28 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   B->cfg.nvblk_total = vblk;
   B->cfg.nsrc_total = src;
   if (!engine_supported(B->cfg)) return fail(QX_EINVAL, "solver: unsupported configuration");
-  if (!B->h_st) QX_HIP(hipHostMalloc((void**)&B->h_st, sizeof(SrcState) * src), "solver: hipHostMalloc");
-  B->chunk = p.chunk > 0 ? p.chunk : 16;
-  B->ru_every = std::min(B->chunk, 4);
+  const size_t mirror = B->layout.gs_off - B->layout.st_off + sizeof(GridSync);
+  if (!B->h_st) QX_HIP(hipHostMalloc((void**)&B->h_st, mirror), "solver: hipHostMalloc");
+  B->h_gs = (GridSync*)((char*)B->h_st + (B->layout.gs_off - B->layout.st_off));
+  // engine: persistent when every stencil tile gets a co-resident block (or when asked)
+  B->persistent = false;
+  if (p.engine != QX_ENGINE_LAUNCH) {
+    const int cap = engine_persistent_capacity(B->cfg);
+    if (p.engine == QX_ENGINE_PERSISTENT && cap < 1)
+      return fail(QX_EINVAL, "solver: the persistent engine cannot be launched on this device");
+    if (p.engine == QX_ENGINE_PERSISTENT || (cap >= B->cfg.nblk_total && cap > 0)) {
+      B->persistent = true;
+      B->pgrid = std::min(cap, B->cfg.nblk_total);
+    }
+  }
+  if (B->persistent) {
+    B->chunk = p.chunk > 0 ? p.chunk : 512;
+    B->ru_every = B->chunk;
+    B->use_graph = false;
+  } else {
+    B->chunk = p.chunk > 0 ? p.chunk : 16;
+    B->ru_every = std::min(B->chunk, 4);
+  }
   return QX_OK;
 }
 
@@ -522,6 +548,7 @@ int upload_plan(qx_batch* B, hipStream_t s) {
          "solver: descriptor upload");
   for (size_t i = 0; i < B->sys.size(); ++i)
     QX_HIP(hipMemsetAsync(B->ws + B->layout.counter_off[i], 0, 256, s), "solver: counter reset");
+  QX_HIP(hipMemsetAsync(B->ws + B->layout.gs_off, 0, sizeof(GridSync), s), "solver: barrier reset");
   QX_HIP(hipStreamSynchronize(s), "solver: upload");
   return QX_OK;
 }
@@ -530,14 +557,20 @@ int upload_plan(qx_batch* B, hipStream_t s) {
 // sequence after every `ru_every` of them and at the end, then a copy of the
 // source states to the pinned host mirror.
 int enqueue_chunk(qx_batch* B, hipStream_t s) {
-  for (int i = 0; i < B->chunk; ++i) {
-    QX_HIP(engine_iteration(B->cfg, s), "solver: iteration");
-    if ((i + 1) % B->ru_every == 0 || i + 1 == B->chunk)
-      QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
+  if (B->persistent) {
+    QX_HIP(engine_persistent(B->cfg, B->chunk, (GridSync*)(B->ws + B->layout.gs_off), B->pgrid, s),
+           "solver: persistent iterations");
+    QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
+  } else {
+    for (int i = 0; i < B->chunk; ++i) {
+      QX_HIP(engine_iteration(B->cfg, s), "solver: iteration");
+      if ((i + 1) % B->ru_every == 0 || i + 1 == B->chunk)
+        QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
+    }
   }
-  QX_HIP(hipMemcpyAsync(B->h_st, B->cfg.d_st, sizeof(SrcState) * B->cfg.nsrc_total,
-                        hipMemcpyDeviceToHost, s),
-         "solver: state readback");
+  const size_t n = B->persistent ? B->layout.gs_off - B->layout.st_off + sizeof(GridSync)
+                                  : sizeof(SrcState) * B->cfg.nsrc_total;
+  QX_HIP(hipMemcpyAsync(B->h_st, B->cfg.d_st, n, hipMemcpyDeviceToHost, s), "solver: state readback");
   return QX_OK;
 }
 
@@ -583,6 +616,8 @@ int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
     if (p.use_x0)
       QX_HIP(launch_pack_field(d.g, d.nsrc, QX_PREC_F64, sp.x, d.vhi, s), "solver: pack x0");
   }
+  if (B->persistent)
+    QX_HIP(hipMemsetAsync(B->ws + B->layout.gs_off, 0, sizeof(GridSync), s), "solver: barrier reset");
   QX_HIP(engine_init(B->cfg, p.use_x0 ? 0 : 1, s), "solver: init");
   QX_HIP(engine_reliable_update(B->cfg, s), "solver: initial residual");
   if (B->use_graph && B->graph && B->graph_stream != s) {
@@ -599,6 +634,8 @@ int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
       if (rc != QX_OK) return rc;
     }
     QX_HIP(hipStreamSynchronize(s), "solver: chunk");
+    if (B->persistent && B->h_gs->error)
+      return fail(QX_EHIP, "solver: a grid barrier of the persistent kernel timed out");
     done = true;
     for (int k = 0; k < B->cfg.nsrc_total; ++k)
       if (B->h_st[k].phase != PH_DONE) done = false;

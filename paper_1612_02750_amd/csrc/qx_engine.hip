@@ -10,9 +10,15 @@
 // per-block partials, then the last block of the system (agent-scope counter)
 // adds the partials in index order and updates the per-source state.
 //
+// One iteration is three launches: D_oe (applying the pending p update on the
+// fly), D_eo fused with the A epilogue, the p update store and <p, Ap>, and the
+// x/r update with |r|^2.
+//
 // Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd)}, FP64
 // vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv].
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "qx_device.h"
 #include "qx_dispatch.h"
@@ -69,6 +75,24 @@ struct SumIn {
     const cplx<double> a = hi[j * ss + c * hv + site];
     const cplx<Rlo> b = lo[j * ss + c * hv + site];
     return {a.re + (double)b.re, a.im + (double)b.im};
+  }
+};
+
+// Input of the D_oe pass of an iteration: p, or r + beta p for sources whose
+// search direction is still to be updated (bit j of pend).
+template <typename R, int NBT>
+struct PendIn {
+  const cplx<R>* __restrict__ p;
+  const cplx<R>* __restrict__ r;
+  size_t ss, hv;
+  unsigned pend;
+  R beta[NBT];
+  __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
+    const size_t i = j * ss + c * hv + site;
+    const cplx<R> pv = p[i];
+    if (!(pend >> j & 1u)) return pv;
+    const cplx<R> rv = r[i];
+    return {fma(beta[j], pv.re, rv.re), fma(beta[j], pv.im, rv.im)};
   }
 };
 
@@ -165,16 +189,40 @@ __global__ void __launch_bounds__(256) k_zero_done(const SysDesc* __restrict__ s
 }
 
 // ============================================================== iteration
+//
+// The three passes of an iteration are written per tile (a 64-site stencil
+// tile or a 256-element vector tile) so that the same code serves the
+// launch-per-pass kernels and the persistent kernel.  FRESH selects state
+// reads that bypass the scalar cache, needed when the state was written by
+// another block of the same (persistent) launch.
 
-// E1: t = 2 D_oe p for running sources.
-template <typename R, int RECON, int NBT, int LPS>
-__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDesc* __restrict__ sys, int nsys,
-                                                   const SrcState* st, int xcd) {
+template <bool FRESH, typename T>
+__device__ __forceinline__ T rd(const T& x) {
+  if constexpr (FRESH) return *(const volatile T*)&x;
+  return x;
+}
+
+template <bool FRESH>
+__device__ __forceinline__ unsigned long long phase_bits_f(const SrcState* st, int nsrc, int phase) {
+  unsigned long long m = 0;
+  for (int k = 0; k < nsrc; ++k)
+    if (rd<FRESH>(st[k].phase) == phase) m |= 1ull << k;
+  return m;
+}
+
+template <bool FRESH>
+using StateRef = typename std::conditional<FRESH, volatile SrcState&, SrcState&>::type;
+
+// E1: t = 2 D_oe p for running sources, with p = r + beta p applied on the fly
+// where the previous iteration left it pending.
+template <typename R, int RECON, int NBT, int LPS, bool FRESH>
+__device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int nsys,
+                                         const SrcState* st, int b) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
-  const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
-  const unsigned long long run = phase_bits(st + d.src0, d.nsrc, PH_RUN);
+  const SrcState* q0 = st + d.src0;
+  const unsigned long long run = phase_bits_f<FRESH>(q0, d.nsrc, PH_RUN);
   if (!run) return;
   const int cb = (b - d.blk0) * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
@@ -183,10 +231,18 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDes
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
   if (act) {
+    PendIn<R, NBT> in{slot<R>(d.vlo, 2, vs) + k0 * ss, slot<R>(d.vlo, 1, vs) + k0 * ss, ss, hv, 0u, {}};
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      in.beta[j] = (R)0;
+      if (act >> j & 1u) {
+        in.beta[j] = (R)rd<FRESH>(q0[k0 + j].beta);
+        if (rd<FRESH>(q0[k0 + j].pend)) in.pend |= 1u << j;
+      }
+    }
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp,
-                                     FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv}, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp, in, act, acc);
   }
   reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
@@ -197,22 +253,20 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDes
     for (int c = 0; c < 3; ++c)
       if (owns_item<LPS>(3 * j + c, dp)) t[(k0 + j) * ss + c * hv + cb] = acc[j][c];
   }
+  if constexpr (LPS > 1) __syncthreads();  // the LDS buffer is reused by the next tile
 }
 
-// E2: Ap = m^2 p - 1/4 (2D_eo) t and Re<p, Ap>; the last block forms alpha
-// (or flags a breakdown when <p, Ap> <= 0 or is not finite).
-template <typename R, int RECON, int NBT, int LPS>
-__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDesc* __restrict__ sys, int nsys,
-                                                   SrcState* st, int xcd) {
-  __shared__ double sh[16 * 64];
-  __shared__ double tot[64];
-  __shared__ int flag;
+// E2: p = r + beta p where pending (stored), Ap = m^2 p - 1/4 (2D_eo) t and
+// Re<p, Ap>; the last block forms alpha (or flags a breakdown when <p, Ap> <= 0
+// or is not finite) and clears the pending flags.
+template <typename R, int RECON, int NBT, int LPS, bool FRESH>
+__device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys, SrcState* st,
+                                         int b, double* sh, double* tot, int* flag) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
-  const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   SrcState* q0 = st + d.src0;
-  const unsigned long long run = phase_bits(q0, d.nsrc, PH_RUN);
+  const unsigned long long run = phase_bits_f<FRESH>(q0, d.nsrc, PH_RUN);
   if (!run) return;
   const int bl = b - d.blk0, cb = bl * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
@@ -230,17 +284,26 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDes
   double dot[NBT];
 #pragma unroll
   for (int j = 0; j < NBT; ++j) dot[j] = 0.0;
-  const cplx<R>* p = slot<R>(d.vlo, 2, vs);
+  cplx<R>* p = slot<R>(d.vlo, 2, vs);
+  const cplx<R>* rr = slot<R>(d.vlo, 1, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     if (!(act >> j & 1u)) continue;
-    const R m2 = (R)q0[k0 + j].m2;
+    const SrcState& q = q0[k0 + j];
+    const R m2 = (R)rd<FRESH>(q.m2);
+    const bool pend = rd<FRESH>(q.pend) != 0;
+    const R be = (R)rd<FRESH>(q.beta);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (!owns_item<LPS>(3 * j + c, dp)) continue;
       const size_t i = (k0 + j) * ss + c * hv + cb;
-      const cplx<R> pv = p[i];
+      cplx<R> pv = p[i];
+      if (pend) {
+        const cplx<R> rv = rr[i];
+        pv = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+        p[i] = pv;
+      }
       const cplx<R> r = {m2 * pv.re - (R)0.25 * acc[j][c].re, m2 * pv.im - (R)0.25 * acc[j][c].im};
       Ap[i] = r;
       dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
@@ -248,13 +311,14 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDes
   }
   const int G = (int)(blockDim.x >> 6) / LPS;
   group_sum<NBT>(dot, LPS, grp, dp, G, sh, tot);
-  if (publish(tot, d.nsrc, d.partials, d.nblk, bl, d.counter, (unsigned)d.nblk, &flag)) {
+  if (publish(tot, d.nsrc, d.partials, d.nblk, bl, d.counter, (unsigned)d.nblk, flag)) {
     for (int k = 0; k < d.nsrc; ++k) {
       if (!(run >> k & 1ull)) continue;
       const double t = total_of(d.partials, d.nblk, k, d.nblk, sh);
       if (threadIdx.x == 0) {
-        SrcState& q = q0[k];
+        StateRef<FRESH> q = q0[k];
         q.pAp = t;
+        q.pend = 0;
         if (!(t > 0.0) || !isfinite(t)) {
           q.phase = PH_RU;
           q.reason = RU_FINAL;
@@ -266,46 +330,49 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDes
     }
     reset_counter(d.counter);
   }
+  __syncthreads();  // the shared scratch is reused by the next tile
 }
 
-// E3: x_lo += alpha p, r -= alpha Ap, |r|^2; the last block decides between
-// continuing (beta), a reliable update, or the end of the iteration budget.
-template <typename R>
-__global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
-                                                 SrcState* st, int xcd) {
-  __shared__ double sh[16];
-  __shared__ int flag;
-  const int b = logical_block(xcd);
+// E3: x_lo += alpha p, r -= alpha Ap, |r|^2 over one vector tile; the last
+// block decides between continuing (beta), a reliable update, or the end of
+// the iteration budget.  Works for any block size.
+template <typename R, bool FRESH>
+__device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsys, SrcState* st,
+                                        int b, double* sh, int* flag) {
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
   SrcState* q0 = st + d.src0;
-  const VBlock v = vblock(d, b);
-  const unsigned long long run = phase_bits(q0, d.nsrc, PH_RUN);
-  if (!(run >> v.k & 1ull)) return;
-  const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const unsigned long long run = phase_bits_f<FRESH>(q0, d.nsrc, PH_RUN);
+  if (!(run >> k & 1ull)) return;
+  const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
+  const R al = (R)rd<FRESH>(q0[k].alpha);
+  cplx<R>* x = slot<R>(d.vlo, 0, vs) + k * n;
+  cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
+  const cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  const cplx<R>* Ap = slot<R>(d.vlo, 3, vs) + k * n;
   double acc[1] = {0.0};
-  if (v.e < v.n) {
-    const R al = (R)q0[v.k].alpha;
-    cplx<R>* x = slot<R>(d.vlo, 0, vs);
-    cplx<R>* r = slot<R>(d.vlo, 1, vs);
-    const cplx<R> pv = slot<R>(d.vlo, 2, vs)[i], av = slot<R>(d.vlo, 3, vs)[i];
-    cplx<R> xv = x[i], rv = r[i];
+  for (int t = threadIdx.x; t < kVTile; t += blockDim.x) {
+    const size_t e = (size_t)tile * kVTile + t;
+    if (e >= n) break;
+    const cplx<R> pv = p[e], av = Ap[e];
+    cplx<R> xv = x[e], rv = r[e];
     xv.re = fma(al, pv.re, xv.re);
     xv.im = fma(al, pv.im, xv.im);
     rv.re = fma(-al, av.re, rv.re);
     rv.im = fma(-al, av.im, rv.im);
-    x[i] = xv;
-    r[i] = rv;
-    acc[0] = (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+    x[e] = xv;
+    r[e] = rv;
+    acc[0] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
   }
   block_sum<1>(acc, sh);
   const unsigned expected = (unsigned)(__popcll(run) * d.vtiles);
-  if (vpublish(acc[0], d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter, expected, &flag)) {
-    for (int k = 0; k < d.nsrc; ++k) {
-      if (!(run >> k & 1ull)) continue;
-      const double rn2 = total_of(d.partials, d.vtiles, k, d.vtiles, sh);
+  if (vpublish(acc[0], d.partials + (size_t)k * d.vtiles + tile, d.counter, expected, flag)) {
+    for (int kk = 0; kk < d.nsrc; ++kk) {
+      if (!(run >> kk & 1ull)) continue;
+      const double rn2 = total_of(d.partials, d.vtiles, kk, d.vtiles, sh);
       if (threadIdx.x == 0) {
-        SrcState& q = q0[k];
-        q.iters += 1;
+        StateRef<FRESH> q = q0[kk];
+        q.iters = q.iters + 1;
         if (!isfinite(rn2)) {
           q.phase = PH_RU;
           q.reason = RU_FINAL;
@@ -324,28 +391,112 @@ __global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys
         } else {
           q.beta = rn2 / q.rho;
           q.rho = rn2;
+          q.pend = 1;
         }
       }
     }
     reset_counter(d.counter);
   }
+  __syncthreads();  // the shared scratch is reused by the next tile
 }
 
-// E4: p = r + beta p for running sources.
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDesc* __restrict__ sys,
+                                                                    int nsys, const SrcState* st,
+                                                                    int xcd) {
+  doe_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd));
+}
+
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDesc* __restrict__ sys,
+                                                                    int nsys, SrcState* st,
+                                                                    int xcd) {
+  __shared__ double sh[16 * 64];
+  __shared__ double tot[64];
+  __shared__ int flag;
+  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), sh, tot, &flag);
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_iter_p(const SysDesc* __restrict__ sys, int nsys,
-                                                const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const VBlock v = vblock(d, b);
-  const SrcState& q = st[d.src0 + v.k];
-  if (q.phase != PH_RUN || v.e >= v.n) return;
-  const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
-  const R be = (R)q.beta;
-  const cplx<R> rv = slot<R>(d.vlo, 1, vs)[i];
-  cplx<R>* p = slot<R>(d.vlo, 2, vs);
-  const cplx<R> pv = p[i];
-  p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+__global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
+                                                 SrcState* st, int xcd) {
+  __shared__ double sh[16];
+  __shared__ int flag;
+  xr_tile<R, false>(sys, nsys, st, logical_block(xcd), sh, &flag);
+}
+
+// ------------------------------------------------------- persistent kernel
+//
+// One cooperative launch runs up to `iters` iterations of every system:
+// each pass is a grid-stride loop over tiles followed by a grid barrier.  The
+// barrier is a sense (generation) counter at agent scope; a wait gives up
+// after `timeout` ticks of the constant-rate device clock and raises the error
+// word, so that every block leaves the kernel.
+// The loop ends when no source is running or one waits for a reliable update
+// (the host then runs the update), a decision every block takes from the same
+// state after a barrier.
+
+__device__ __forceinline__ bool grid_sync(GridSync* gs, unsigned nblocks, long long timeout,
+                                          int* ok_sh) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1u) {
+      __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gs->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const long long t0 = wall_clock64();
+      while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&gs->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > timeout) {
+          __hip_atomic_store(&gs->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  return *ok_sh != 0;
+}
+
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>))
+    k_cg_persistent(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int nsrc_total,
+                    int nblk_total, int nvblk_total, int iters, GridSync* gs,
+                    long long timeout) {
+  __shared__ double sh[16 * 64];
+  __shared__ double tot[64];
+  __shared__ int flag, ok;
+  for (int it = 0; it < iters; ++it) {
+    // leave when nothing runs or some source waits for a reliable update
+    bool run = false, ru = false;
+    for (int k = 0; k < nsrc_total; ++k) {
+      const int ph = rd<true>(st[k].phase);
+      run |= ph == PH_RUN;
+      ru |= ph == PH_RU;
+    }
+    if (!run || ru) break;
+    for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
+      doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b);
+    if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
+    for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
+      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, sh, tot, &flag);
+    if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
+    for (int b = blockIdx.x; b < nvblk_total; b += gridDim.x)
+      xr_tile<R, true>(sys, nsys, st, b, sh, &flag);
+    if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
+  }
 }
 
 // ========================================================= reliable update
@@ -492,7 +643,10 @@ __global__ void __launch_bounds__(256) k_ru_finish(const SysDesc* __restrict__ s
   if (vpublish(0.0, d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter, expected, &flag)) {
     if (threadIdx.x == 0)
       for (int k = 0; k < d.nsrc; ++k)
-        if (ru2 >> k & 1ull) q0[k].phase = PH_RUN;
+        if (ru2 >> k & 1ull) {
+          q0[k].phase = PH_RUN;
+          q0[k].pend = 0;
+        }
     reset_counter(d.counter);
   }
 }
@@ -531,8 +685,63 @@ hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
       hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st, c.shape.xcd);
       hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
-      hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
       return hipGetLastError();
+    });
+  });
+}
+
+namespace {
+int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      n = 0;
+  }
+  return n;
+}
+}  // namespace
+
+int engine_persistent_capacity(const EngineCfg& c) {
+  const int G = shape_groups(c.shape, c.nsrc_max);
+  const int threads = 64 * c.shape.lps * G;
+  const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
+  int per_cu = 0;
+  hipError_t e = with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
+    return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS>), threads,
+          lds);
+    });
+  });
+  if (e != hipSuccess) return 0;
+  return per_cu * cu_count();
+}
+
+hipError_t engine_persistent(const EngineCfg& c, int iters, GridSync* gs, int grid,
+                             hipStream_t s) {
+  const int G = shape_groups(c.shape, c.nsrc_max);
+  const int threads = 64 * c.shape.lps * G;
+  const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
+  const SysDesc* sys = c.d_sys;
+  int nsys = c.nsys, nsrc = c.nsrc_total, nblk = c.nblk_total, nvblk = c.nvblk_total;
+  SrcState* st = c.d_st;
+  // barrier waits give up after 2 s of the constant-rate device clock
+  static long long timeout = 0;
+  if (!timeout) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;
+    timeout = 2000LL * khz;
+  }
+  void* args[] = {&sys, &nsys, &st, &nsrc, &nblk, &nvblk, &iters, &gs, &timeout};
+  return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
+    return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+      return hipLaunchCooperativeKernel(
+          reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS>), dim3(grid),
+          dim3(threads), args, (unsigned)lds, s);
     });
   });
 }

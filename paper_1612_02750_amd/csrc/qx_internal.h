@@ -53,7 +53,8 @@ struct SrcState {
   int reason;       // RuReason of a pending update
   int status;       // QX_* status
   int iters, updates, max_iter;
-  int pad[2];
+  int pend;         // p is still to be replaced by r + beta p (done inside the next stencil passes)
+  int pad;
 };
 
 // One system of a solver launch: a lattice, its links in the inner precision
@@ -73,6 +74,14 @@ struct SysDesc {
   void* vhi;        // FP64: x_hi, r_hi, b (even), t_hi (odd); each [nsrc][3][hv]
   double* partials; // [nsrc][nblk] (stencil) or [nsrc][vtiles] (vector)
   unsigned* counter;  // last-block counter of this system (kept at zero between launches)
+};
+
+// Grid barrier of the persistent solver kernel (zeroed before first use).
+struct GridSync {
+  unsigned count;   // blocks arrived at the current barrier
+  unsigned gen;     // barrier generation
+  unsigned error;   // set when a barrier wait timed out
+  unsigned pad[61];
 };
 
 constexpr int kTile = 64;     // sites per stencil block

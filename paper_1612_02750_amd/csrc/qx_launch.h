@@ -71,6 +71,10 @@ bool engine_supported(const EngineCfg& c);
 hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s);
 hipError_t engine_iteration(const EngineCfg& c, hipStream_t s);
 hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s);
+// Co-resident blocks of the persistent solver kernel on this device (0 if it
+// cannot be launched), and one cooperative launch of up to `iters` iterations.
+int engine_persistent_capacity(const EngineCfg& c);
+hipError_t engine_persistent(const EngineCfg& c, int iters, GridSync* gs, int grid, hipStream_t s);
 
 // ------------------------------------------------------------------ force
 

@@ -305,9 +305,13 @@ def test_uneven_batch_config4(qx):
         xd = torch.empty_like(bd)
         systems.append((g64, g32, bd, masses, xd))
         keep.append((dims, U, b, masses, xd, lat))
-    batch = qx.Batch(systems, tol=1e-10)
-    for rep in range(2):
-        stats = batch.solve()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):  # a non-default stream: the chunk is captured in a HIP graph
+        batch = qx.Batch(systems, tol=1e-10, engine=qx.ENGINE_LAUNCH)
+        all_stats = [batch.solve() for rep in range(2)]
+    torch.cuda.synchronize()
+    for stats in all_stats:
         j = 0
         for dims, U, b, masses, xd, lat in keep:
             x = to_host(xd)
@@ -452,3 +456,80 @@ def test_autograd_action(qx):
     So, Go, *_ = oracle.force(dims, U, m, phi[0], tol=1e-13)
     assert abs(S.item() - So) <= 1e-10 * abs(So)
     assert rel(to_host(Ut.grad), Go) <= 1e-9
+
+
+# ------------------------------------------------------- persistent engine
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_engines_agree_bitwise(qx, mixed):
+    """The persistent kernel (grid barriers) and the launch-per-pass engine run the
+    same reductions in the same order and update at the same iterations."""
+    dims = (8, 4, 6, 8)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    U = gauge(dims, seed=9)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    glo = qx.Gauge(lat, Ud, "f32", 12) if mixed else None
+    masses = [0.05, 0.2, 0.1]
+    b = synth.gauss_source(3, lat.hv, 11)
+    xa, sa = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_LAUNCH)
+    xb, sb = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_PERSISTENT)
+    assert np.array_equal(to_host(xa), to_host(xb))
+    assert [s.iters for s in sa] == [s.iters for s in sb]
+    assert [s.reliable_updates for s in sa] == [s.reliable_updates for s in sb]
+    _check_solution(dims, U, masses, b, to_host(xb), sb, flags=oracle.BC_T_ANTIPERIODIC)
+
+
+def test_persistent_edge_cases(qx):
+    import torch
+
+    dims = (4, 4, 4, 4)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=0)
+    g64 = qx.Gauge(lat, to_dev(U), "f64")
+    g32 = qx.Gauge(lat, to_dev(U), "f32")
+    b = synth.gauss_source(1, lat.hv, 1)
+    P = qx.ENGINE_PERSISTENT
+    x, st = qx.cg(g64, torch.zeros((1, lat.hv, 3), dtype=torch.complex128, device="cuda"), 0.1,
+                  engine=P)
+    assert st[0].status == 0 and st[0].iters == 0 and not to_host(x).any()
+    x, st = qx.cg(g64, to_dev(b), 0.1, max_iter=3, engine=P, raise_on_fail=False)
+    assert st[0].status == qx.ENOTCONVERGED and st[0].iters == 3
+    bn = b.copy()
+    bn[0, 5, 2] = np.inf
+    x, st = qx.cg(g64, to_dev(bn), 0.1, glo=g32, engine=P, raise_on_fail=False)
+    assert st[0].status == qx.EBREAKDOWN
+    gf = qx.Gauge(lat, to_dev(synth.unit_gauge(dims)), "f64")
+    x, st = qx.cg(gf, to_dev(b), 0.0, max_iter=300, engine=P, raise_on_fail=False)
+    assert st[0].status in (qx.ENOTCONVERGED, qx.EBREAKDOWN)
+    x, st = qx.cg(g64, to_dev(b), 0.1, glo=g32, engine=P)
+    _check_solution(dims, U, [0.1], b, to_host(x), st)
+
+
+def test_persistent_uneven_batch(qx):
+    import torch
+
+    shapes = [(4, 4, 4, 4), (8, 4, 4, 6), (6, 6, 6, 6), (8, 8, 8, 8)]
+    systems, keep = [], []
+    for k, dims in enumerate(shapes):
+        U = synth.weak_gauge(dims, 0.3, 20 + k)
+        lat = qx.Lattice(dims)
+        Ud = to_dev(U)
+        g64 = qx.Gauge(lat, Ud, "f64")
+        g32 = qx.Gauge(lat, Ud, "f32", 12)
+        nrhs = 1 + k % 3
+        b = synth.gauss_source(nrhs, lat.hv, 40 + k)
+        masses = [0.02 + 0.03 * j for j in range(nrhs)]
+        bd = to_dev(b)
+        xd = torch.empty_like(bd)
+        systems.append((g64, g32, bd, masses, xd))
+        keep.append((dims, U, b, masses, xd))
+    for engine in (qx.ENGINE_PERSISTENT, qx.ENGINE_LAUNCH):
+        stats = qx.Batch(systems, tol=1e-10, engine=engine).solve()
+        j = 0
+        for dims, U, b, masses, xd in keep:
+            x = to_host(xd)
+            for s in range(b.shape[0]):
+                rr = oracle.true_residual(dims, U, masses[s], b[s], x[s])
+                assert rr <= 1e-10 and stats[j].status == 0, (engine, dims, s, rr)
+                j += 1
