@@ -203,6 +203,22 @@ def main():
     s_64 = st64[0]
     log(f"fp64:  {t_fp64 * 1e3:.3f} ms/solve, iters {s_64.iters}, residual {s_64.true_rel_residual:.2e}")
 
+    # the same mixed solve under each CG engine
+    engines = {}
+    for name, eng in (("launch", qx.ENGINE_LAUNCH), ("persistent", qx.ENGINE_PERSISTENT)):
+        xe = torch.empty_like(bd)
+        be = qx.Batch([(g64, g32, bd, [m], xe)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta,
+                      engine=eng)
+        be.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            se = be.solve()
+        torch.cuda.synchronize()
+        engines[name] = {"ms": round((time.perf_counter() - t0) / 3 * 1e3, 3), "iters": se[0].iters}
+        del be
+    log(f"engines (mixed 16^4): {engines}")
+
     flops_mixed = (s_mx.iters * 606 + s_mx.reliable_updates * 582) * V
     value = flops_mixed / t_mixed / 1e9
 
@@ -284,6 +300,7 @@ def main():
         "cg_time_to_solution_ms": {"mixed_f32_12": round(t_mixed * 1e3, 3),
                                    "fp64": round(t_fp64 * 1e3, 3),
                                    "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3)},
+        "cg_engines_mixed_ms": engines,
         "cg_iterations": {"mixed": s_mx.iters, "mixed_reliable_updates": s_mx.reliable_updates,
                           "fp64": s_64.iters},
         "true_rel_residual": {"mixed": s_mx.true_rel_residual, "fp64": s_64.true_rel_residual},

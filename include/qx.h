@@ -92,9 +92,11 @@ typedef struct qx_batch qx_batch_t;
 
 /* engines of the CG iteration */
 enum {
-  QX_ENGINE_AUTO = 0,      /* persistent when every stencil tile gets its own block, else launches */
-  QX_ENGINE_LAUNCH = 1,    /* three kernel launches per iteration (graph-captured in batches) */
-  QX_ENGINE_PERSISTENT = 2 /* one cooperative launch runs many iterations with grid barriers */
+  QX_ENGINE_AUTO = 0,      /* the default engine (currently QX_ENGINE_LAUNCH) */
+  QX_ENGINE_LAUNCH = 1,    /* five kernel launches per iteration (graph-captured in batches) */
+  QX_ENGINE_PERSISTENT = 2 /* one cooperative launch runs many iterations with grid barriers;
+                              same results bit for bit, but slower on MI355X, where every
+                              barrier costs each block an agent-scope release (L2 writeback) */
 };
 
 /* Solver parameters.  tol: relative residual |b - A x| / |b| to reach, measured

@@ -340,8 +340,7 @@ struct SysSpec {
 
 struct Layout {
   size_t sys_off = 0, st_off = 0, gs_off = 0, total = 0;
-  std::vector<size_t> counter_off, partial_off, vlo_off, vhi_off;
-  std::vector<int> nblk_max;
+  std::vector<size_t> partial_off, vlo_off, vhi_off;
 };
 
 int lo_prec(const qx_cg_params_t* p) { return p->mode == QX_CG_FP64 ? QX_PREC_F64 : QX_PREC_F32; }
@@ -361,11 +360,9 @@ Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
     const Geo& g = s.g64->geo;
     const int nblk = (g.hv + kTile - 1) / kTile;
     const int vtiles = (3 * g.hv + kVTile - 1) / kVTile;
-    L.nblk_max.push_back(std::max(nblk, vtiles));
-    L.counter_off.push_back(off);
-    off = align_up(off + 256, 256);
+    const size_t n1 = std::max(nblk, vtiles);
     L.partial_off.push_back(off);
-    off = align_up(off + sizeof(double) * s.nrhs * std::max(nblk, vtiles), 256);
+    off = align_up(off + sizeof(double) * s.nrhs * n1, 256);
     L.vlo_off.push_back(off);
     off = align_up(off + 5 * field_bytes(g, s.nrhs, prec_lo), 256);
     L.vhi_off.push_back(off);
@@ -495,7 +492,6 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     d.vlo = B->ws + B->layout.vlo_off[i];
     d.vhi = B->ws + B->layout.vhi_off[i];
     d.partials = (double*)(B->ws + B->layout.partial_off[i]);
-    d.counter = (unsigned*)(B->ws + B->layout.counter_off[i]);
     blk += d.nblk;
     vblk += d.nsrc * d.vtiles;
     src += d.nsrc;
@@ -519,16 +515,14 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   const size_t mirror = B->layout.gs_off - B->layout.st_off + sizeof(GridSync);
   if (!B->h_st) QX_HIP(hipHostMalloc((void**)&B->h_st, mirror), "solver: hipHostMalloc");
   B->h_gs = (GridSync*)((char*)B->h_st + (B->layout.gs_off - B->layout.st_off));
-  // engine: persistent when every stencil tile gets a co-resident block (or when asked)
+  // engine: launch per pass unless the persistent kernel is asked for
   B->persistent = false;
-  if (p.engine != QX_ENGINE_LAUNCH) {
+  if (p.engine == QX_ENGINE_PERSISTENT) {
     const int cap = engine_persistent_capacity(B->cfg);
-    if (p.engine == QX_ENGINE_PERSISTENT && cap < 1)
+    if (cap < 1)
       return fail(QX_EINVAL, "solver: the persistent engine cannot be launched on this device");
-    if (p.engine == QX_ENGINE_PERSISTENT || (cap >= B->cfg.nblk_total && cap > 0)) {
-      B->persistent = true;
-      B->pgrid = std::min(cap, B->cfg.nblk_total);
-    }
+    B->persistent = true;
+    B->pgrid = std::min(cap, B->cfg.nblk_total);
   }
   if (B->persistent) {
     B->chunk = p.chunk > 0 ? p.chunk : 512;
@@ -541,13 +535,11 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   return QX_OK;
 }
 
-// Upload the descriptor table and clear the last-block counters.
+// Upload the descriptor table and clear the grid barrier word.
 int upload_plan(qx_batch* B, hipStream_t s) {
   QX_HIP(hipMemcpyAsync(B->ws + B->layout.sys_off, B->sys.data(), sizeof(SysDesc) * B->sys.size(),
                         hipMemcpyHostToDevice, s),
          "solver: descriptor upload");
-  for (size_t i = 0; i < B->sys.size(); ++i)
-    QX_HIP(hipMemsetAsync(B->ws + B->layout.counter_off[i], 0, 256, s), "solver: counter reset");
   QX_HIP(hipMemsetAsync(B->ws + B->layout.gs_off, 0, sizeof(GridSync), s), "solver: barrier reset");
   QX_HIP(hipStreamSynchronize(s), "solver: upload");
   return QX_OK;

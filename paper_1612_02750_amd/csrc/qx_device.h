@@ -303,39 +303,4 @@ __device__ __forceinline__ void group_sum(const double (&v)[NBT], int nwaves_per
   __syncthreads();
 }
 
-// Publish per-block partial sums (thread 0 holds them in part[0..nsrc)) and
-// report whether this block is the last of its system to do so.  The partials
-// are written, released at agent scope, and counted with an agent-scope
-// atomic; the last block acquires before reading them back.  `expected` is
-// the number of blocks that publish for this system in this launch; the last
-// one resets the counter so that it is zero again at the next launch.
-__device__ __forceinline__ bool publish(const double* part, int nsrc, double* partials, int stride,
-                                        int bl, unsigned* counter, unsigned expected, int* flag_sh) {
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < nsrc; ++k) partials[(size_t)k * stride + bl] = part[k];
-    __threadfence();
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    *flag_sh = (prev == expected - 1u);
-  }
-  __syncthreads();
-  const bool last = *flag_sh != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// In the last block: total of source k over its n partials (fixed order),
-// result valid in thread 0.  Uses sh[0..16).
-__device__ __forceinline__ double total_of(const double* partials, int stride, int k, int n,
-                                           double* sh) {
-  double v[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += partials[(size_t)k * stride + i];
-  block_sum<1>(v, sh);
-  return v[0];
-}
-
-__device__ __forceinline__ void reset_counter(unsigned* counter) {
-  if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 }  // namespace qx

@@ -6,13 +6,20 @@
 // of 256 complex elements.  A source takes part in a launch only in the phase
 // the kernel serves (PH_RUN for the iteration, PH_RU / PH_RU2 for the update),
 // so converged sources cost nothing but the link loads they share with the
-// others.  Reductions are deterministic: fixed-order wave and block sums into
-// per-block partials, then the last block of the system (agent-scope counter)
-// adds the partials in index order and updates the per-source state.
+// others.
 //
-// One iteration is three launches: D_oe (applying the pending p update on the
-// fly), D_eo fused with the A epilogue, the p update store and <p, Ap>, and the
-// x/r update with |r|^2.
+// Reductions need no memory fence inside a kernel: every block stores its
+// partial sums (fixed-order wave and block sums) with plain stores, and after
+// the kernel boundary a finalize kernel with one block per source adds the
+// partials in index order and applies the state update (alpha, beta, the
+// reliable-update and convergence decisions).  On MI355X an agent-scope fence
+// writes back the issuing XCD's L2, so a fence per block (last-block
+// reductions, grid barriers) costs far more than the extra launch.
+//
+// One iteration is five launches: D_oe (applying the pending p update on the
+// fly), D_eo fused with the A epilogue, the p update store and the <p, Ap>
+// partials, the alpha finalize, the x/r update with the |r|^2 partials, and
+// the beta finalize.
 //
 // Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd)}, FP64
 // vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv].
@@ -46,16 +53,35 @@ __device__ __forceinline__ const SysDesc& sys_of_vblock(const SysDesc* __restric
   return sys[i];
 }
 
+__device__ __forceinline__ const SysDesc& sys_of_source(const SysDesc* __restrict__ sys, int nsys,
+                                                        int k) {
+  int i = 0;
+  while (i + 1 < nsys && k >= sys[i + 1].src0) ++i;
+  return sys[i];
+}
+
 template <typename R>
 __device__ __forceinline__ cplx<R>* slot(void* base, int i, size_t vs) {
   return (cplx<R>*)base + i * vs;
 }
 
+// State reads: FRESH bypasses the scalar cache, needed when another block of
+// the same (persistent) launch wrote the state.
+template <bool FRESH, typename T>
+__device__ __forceinline__ T rd(const T& x) {
+  if constexpr (FRESH) return *(const volatile T*)&x;
+  return x;
+}
+
+template <bool FRESH>
+using StateRef = typename std::conditional<FRESH, volatile SrcState&, SrcState&>::type;
+
 // Sources of a system in the given phase, as a bit mask (at most 64 sources).
+template <bool FRESH>
 __device__ __forceinline__ unsigned long long phase_bits(const SrcState* st, int nsrc, int phase) {
   unsigned long long m = 0;
   for (int k = 0; k < nsrc; ++k)
-    if (st[k].phase == phase) m |= 1ull << k;
+    if (rd<FRESH>(st[k].phase) == phase) m |= 1ull << k;
   return m;
 }
 
@@ -96,85 +122,53 @@ struct PendIn {
   }
 };
 
-// Vector-launch prologue: the system, source and tile of this block.
-struct VBlock {
-  int k, tile;
-  size_t n, e;  // elements per source vector (3 hv), element of this thread
-};
-
-__device__ __forceinline__ VBlock vblock(const SysDesc& d, int b) {
-  VBlock v;
-  const int rel = b - d.vblk0;
-  v.k = rel / d.vtiles;
-  v.tile = rel - v.k * d.vtiles;
-  v.n = (size_t)3 * d.g.hv;
-  v.e = (size_t)v.tile * kVTile + threadIdx.x;
-  return v;
-}
-
-// Thread 0 of a vector block publishes its partial (valid in thread 0) and
-// learns whether it is the last of `expected` blocks of its system.
-__device__ __forceinline__ bool vpublish(double v, double* dst, unsigned* counter,
-                                         unsigned expected, int* flag_sh) {
-  if (threadIdx.x == 0) {
-    *dst = v;
-    __threadfence();
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    *flag_sh = (prev == expected - 1u);
+// Sum over a 256-element vector tile of a per-element value: four chunks of
+// 64 elements, chunk c taken by wavefront c % (waves of the block) and summed
+// by one butterfly, the chunk sums added in chunk order.  The result (valid in
+// thread 0) does not depend on the block size.  f(e) computes element e's
+// value (and may update vectors); it is called once per element of the tile.
+template <typename F>
+__device__ __forceinline__ double tile_sum(int tile, size_t n, double* sh, F&& f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  for (int c = w; c < kVTile / 64; c += nw) {
+    const size_t e = (size_t)tile * kVTile + c * 64 + lane;
+    double v = e < n ? f(e) : 0.0;
+    v = wave_sum(v);
+    if (lane == 0) sh[c] = v;
   }
   __syncthreads();
-  const bool last = *flag_sh != 0;
-  if (last) __threadfence();
-  return last;
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int c = 0; c < kVTile / 64; ++c) t += sh[c];
+  __syncthreads();
+  return t;
 }
 
 }  // namespace
 
 // =================================================================== init
 
-// x_lo = 0, p = 0 (and x_hi = 0 without an initial guess); |b|^2 -> bnorm2,
-// stop2 *= bnorm2; a zero source is done at once (x = 0), a non-finite one is
-// a breakdown.
+// x_lo = 0, p = 0 (and x_hi = 0 without an initial guess); partials of |b|^2.
 template <typename R>
 __global__ void __launch_bounds__(256) k_init(const SysDesc* __restrict__ sys, int nsys,
-                                              SrcState* st, int zero_xhi, int xcd) {
+                                              int zero_xhi, int xcd) {
   __shared__ double sh[16];
-  __shared__ int flag;
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const VBlock v = vblock(d, b);
-  const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
-  double acc[1] = {0.0};
-  if (v.e < v.n) {
-    slot<R>(d.vlo, 0, vs)[i] = {(R)0, (R)0};
-    slot<R>(d.vlo, 2, vs)[i] = {(R)0, (R)0};
-    if (zero_xhi) slot<double>(d.vhi, 0, vs)[i] = {0.0, 0.0};
-    const cplx<double> bv = slot<double>(d.vhi, 2, vs)[i];
-    acc[0] = bv.re * bv.re + bv.im * bv.im;
-  }
-  block_sum<1>(acc, sh);
-  if (vpublish(acc[0], d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter,
-               (unsigned)(d.nsrc * d.vtiles), &flag)) {
-    for (int k = 0; k < d.nsrc; ++k) {
-      const double t = total_of(d.partials, d.vtiles, k, d.vtiles, sh);
-      if (threadIdx.x == 0) {
-        SrcState& q = st[d.src0 + k];
-        q.bnorm2 = t;
-        q.stop2 *= t;
-        if (t == 0.0) {
-          q.phase = PH_DONE;
-          q.status = kStatusOk;
-          q.relres = 0.0;
-        } else if (!isfinite(t)) {
-          q.phase = PH_DONE;
-          q.status = kStatusBreakdown;
-          q.relres = t;
-        }
-      }
-    }
-    reset_counter(d.counter);
-  }
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
+  cplx<R>* xlo = slot<R>(d.vlo, 0, vs) + k * n;
+  cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  cplx<double>* xhi = slot<double>(d.vhi, 0, vs) + k * n;
+  const cplx<double>* bb = slot<double>(d.vhi, 2, vs) + k * n;
+  const double t = tile_sum(tile, n, sh, [&](size_t e) {
+    xlo[e] = {(R)0, (R)0};
+    p[e] = {(R)0, (R)0};
+    if (zero_xhi) xhi[e] = {0.0, 0.0};
+    const cplx<double> bv = bb[e];
+    return bv.re * bv.re + bv.im * bv.im;
+  });
+  if (threadIdx.x == 0) d.partials[(size_t)k * d.vtiles + tile] = t;
 }
 
 // x_hi = 0 for zero sources (the solution of A x = 0).
@@ -182,36 +176,137 @@ __global__ void __launch_bounds__(256) k_zero_done(const SysDesc* __restrict__ s
                                                    const SrcState* st, int xcd) {
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const VBlock v = vblock(d, b);
-  const SrcState& q = st[d.src0 + v.k];
-  if (!(q.phase == PH_DONE && q.bnorm2 == 0.0) || v.e >= v.n) return;
-  slot<double>(d.vhi, 0, v.n * d.nsrc)[v.k * v.n + v.e] = {0.0, 0.0};
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
+  const SrcState& q = st[d.src0 + k];
+  if (!(q.phase == PH_DONE && q.bnorm2 == 0.0) || e >= n) return;
+  slot<double>(d.vhi, 0, n * d.nsrc)[k * n + e] = {0.0, 0.0};
+}
+
+// ============================================================== finalize
+
+enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RU = 3, FIN_COMMIT = 4 };
+
+// Sum of the n partials of source k in index order (valid in thread 0).
+__device__ __forceinline__ double partial_total(const SysDesc& d, int k, int n, double* sh) {
+  double v[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += d.partials[(size_t)k * n + i];
+  block_sum<1>(v, sh);
+  return v[0];
+}
+
+// The state update of one source after a reduction (thread 0 only).
+template <bool FRESH>
+__device__ __forceinline__ void finalize_source(int kind, StateRef<FRESH> q, double t) {
+  switch (kind) {
+    case FIN_INIT:  // |b|^2: a zero source is done (x = 0), a non-finite one broke down
+      q.bnorm2 = t;
+      q.stop2 = q.stop2 * t;
+      if (t == 0.0) {
+        q.phase = PH_DONE;
+        q.status = kStatusOk;
+        q.relres = 0.0;
+      } else if (!isfinite(t)) {
+        q.phase = PH_DONE;
+        q.status = kStatusBreakdown;
+        q.relres = t;
+      }
+      break;
+    case FIN_ALPHA:  // <p, Ap>: alpha, or a breakdown when <p, Ap> <= 0 or not finite
+      q.pAp = t;
+      q.pend = 0;
+      if (!(t > 0.0) || !isfinite(t)) {
+        q.phase = PH_RU;
+        q.reason = RU_FINAL;
+        q.status = kStatusBreakdown;
+      } else {
+        q.alpha = q.rho / t;
+      }
+      break;
+    case FIN_BETA: {  // |r|^2 of the recurrence: continue, update, or stop
+      q.iters = q.iters + 1;
+      if (!isfinite(t)) {
+        q.phase = PH_RU;
+        q.reason = RU_FINAL;
+        q.status = kStatusBreakdown;
+        break;
+      }
+      const double rn = sqrt(t);
+      if (rn > q.rmax) q.rmax = rn;
+      if (q.iters >= q.max_iter) {
+        q.phase = PH_RU;
+        q.reason = RU_FINAL;
+        q.status = kStatusNotConverged;
+      } else if (t <= q.stop2 || rn < q.delta * q.rmax) {
+        q.phase = PH_RU;
+        q.reason = RU_DROP;
+      } else {
+        q.beta = t / q.rho;
+        q.rho = t;
+        q.pend = 1;
+      }
+      break;
+    }
+    case FIN_RU:  // FP64 |b - A x|^2: converged, or restart the recurrence from it
+      q.updates = q.updates + 1;
+      q.relres = sqrt(t / q.bnorm2);
+      if (t <= q.stop2) {
+        q.phase = PH_DONE;
+        q.status = kStatusOk;
+      } else if (!isfinite(t)) {
+        q.phase = PH_DONE;
+        q.status = kStatusBreakdown;
+      } else if (q.reason == RU_FINAL) {
+        q.phase = PH_DONE;
+      } else {
+        q.beta = q.reason == RU_INIT ? 0.0 : t / q.rho;
+        q.rho = t;
+        q.rmax = sqrt(t);
+        q.phase = PH_RU2;
+      }
+      break;
+    case FIN_COMMIT:  // a finished update lets the source iterate again
+      q.phase = PH_RUN;
+      q.pend = 0;
+      break;
+  }
+}
+
+__device__ __forceinline__ int fin_phase(int kind) {
+  return kind == FIN_ALPHA || kind == FIN_BETA ? PH_RUN
+         : kind == FIN_RU                      ? PH_RU
+         : kind == FIN_COMMIT                  ? PH_RU2
+                                               : -1;
+}
+
+// Finalize source g (global index) of the batch.
+template <bool FRESH>
+__device__ __forceinline__ void finalize_one(const SysDesc* __restrict__ sys, int nsys,
+                                             SrcState* st, int g, int kind, double* sh) {
+  const SysDesc& d = sys_of_source(sys, nsys, g);
+  const int k = g - d.src0;
+  const int ph = fin_phase(kind);
+  if (ph >= 0 && rd<FRESH>(st[g].phase) != ph) return;
+  double t = 0.0;
+  if (kind != FIN_COMMIT) {
+    const int n = (kind == FIN_ALPHA || kind == FIN_RU) ? d.nblk : d.vtiles;
+    t = partial_total(d, k, n, sh);
+  }
+  if (threadIdx.x == 0) finalize_source<FRESH>(kind, st[g], t);
+}
+
+// One block per source of the batch.
+__global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, int nsys,
+                                                  SrcState* st, int kind) {
+  __shared__ double sh[16];
+  finalize_one<false>(sys, nsys, st, blockIdx.x, kind, sh);
 }
 
 // ============================================================== iteration
 //
-// The three passes of an iteration are written per tile (a 64-site stencil
-// tile or a 256-element vector tile) so that the same code serves the
-// launch-per-pass kernels and the persistent kernel.  FRESH selects state
-// reads that bypass the scalar cache, needed when the state was written by
-// another block of the same (persistent) launch.
-
-template <bool FRESH, typename T>
-__device__ __forceinline__ T rd(const T& x) {
-  if constexpr (FRESH) return *(const volatile T*)&x;
-  return x;
-}
-
-template <bool FRESH>
-__device__ __forceinline__ unsigned long long phase_bits_f(const SrcState* st, int nsrc, int phase) {
-  unsigned long long m = 0;
-  for (int k = 0; k < nsrc; ++k)
-    if (rd<FRESH>(st[k].phase) == phase) m |= 1ull << k;
-  return m;
-}
-
-template <bool FRESH>
-using StateRef = typename std::conditional<FRESH, volatile SrcState&, SrcState&>::type;
+// The passes of an iteration are written per tile (a 64-site stencil tile or
+// a 256-element vector tile) so that the same code serves the launch-per-pass
+// kernels and the persistent kernel.
 
 // E1: t = 2 D_oe p for running sources, with p = r + beta p applied on the fly
 // where the previous iteration left it pending.
@@ -222,7 +317,7 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
-  const unsigned long long run = phase_bits_f<FRESH>(q0, d.nsrc, PH_RUN);
+  const unsigned long long run = phase_bits<FRESH>(q0, d.nsrc, PH_RUN);
   if (!run) return;
   const int cb = (b - d.blk0) * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
@@ -256,17 +351,16 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   if constexpr (LPS > 1) __syncthreads();  // the LDS buffer is reused by the next tile
 }
 
-// E2: p = r + beta p where pending (stored), Ap = m^2 p - 1/4 (2D_eo) t and
-// Re<p, Ap>; the last block forms alpha (or flags a breakdown when <p, Ap> <= 0
-// or is not finite) and clears the pending flags.
+// E2: p = r + beta p where pending (stored), Ap = m^2 p - 1/4 (2D_eo) t and the
+// partials of Re<p, Ap>.
 template <typename R, int RECON, int NBT, int LPS, bool FRESH>
-__device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys, SrcState* st,
-                                         int b, double* sh, double* tot, int* flag) {
+__device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
+                                         const SrcState* st, int b, double* sh, double* tot) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
-  const unsigned long long run = phase_bits_f<FRESH>(q0, d.nsrc, PH_RUN);
+  const SrcState* q0 = st + d.src0;
+  const unsigned long long run = phase_bits<FRESH>(q0, d.nsrc, PH_RUN);
   if (!run) return;
   const int bl = b - d.blk0, cb = bl * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
@@ -311,49 +405,26 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   }
   const int G = (int)(blockDim.x >> 6) / LPS;
   group_sum<NBT>(dot, LPS, grp, dp, G, sh, tot);
-  if (publish(tot, d.nsrc, d.partials, d.nblk, bl, d.counter, (unsigned)d.nblk, flag)) {
-    for (int k = 0; k < d.nsrc; ++k) {
-      if (!(run >> k & 1ull)) continue;
-      const double t = total_of(d.partials, d.nblk, k, d.nblk, sh);
-      if (threadIdx.x == 0) {
-        StateRef<FRESH> q = q0[k];
-        q.pAp = t;
-        q.pend = 0;
-        if (!(t > 0.0) || !isfinite(t)) {
-          q.phase = PH_RU;
-          q.reason = RU_FINAL;
-          q.status = kStatusBreakdown;
-        } else {
-          q.alpha = q.rho / t;
-        }
-      }
-    }
-    reset_counter(d.counter);
-  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < d.nsrc; ++k) d.partials[(size_t)k * d.nblk + bl] = tot[k];
   __syncthreads();  // the shared scratch is reused by the next tile
 }
 
-// E3: x_lo += alpha p, r -= alpha Ap, |r|^2 over one vector tile; the last
-// block decides between continuing (beta), a reliable update, or the end of
-// the iteration budget.  Works for any block size.
+// E3: x_lo += alpha p, r -= alpha Ap over one vector tile and the partial of
+// |r|^2.  Works for any block size.
 template <typename R, bool FRESH>
-__device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsys, SrcState* st,
-                                        int b, double* sh, int* flag) {
+__device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsys,
+                                        const SrcState* st, int b, double* sh) {
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
   const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
-  const unsigned long long run = phase_bits_f<FRESH>(q0, d.nsrc, PH_RUN);
-  if (!(run >> k & 1ull)) return;
+  if (rd<FRESH>(st[d.src0 + k].phase) != PH_RUN) return;
   const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
-  const R al = (R)rd<FRESH>(q0[k].alpha);
+  const R al = (R)rd<FRESH>(st[d.src0 + k].alpha);
   cplx<R>* x = slot<R>(d.vlo, 0, vs) + k * n;
   cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
   const cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
   const cplx<R>* Ap = slot<R>(d.vlo, 3, vs) + k * n;
-  double acc[1] = {0.0};
-  for (int t = threadIdx.x; t < kVTile; t += blockDim.x) {
-    const size_t e = (size_t)tile * kVTile + t;
-    if (e >= n) break;
+  const double t = tile_sum(tile, n, sh, [&](size_t e) {
     const cplx<R> pv = p[e], av = Ap[e];
     cplx<R> xv = x[e], rv = r[e];
     xv.re = fma(al, pv.re, xv.re);
@@ -362,42 +433,9 @@ __device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsy
     rv.im = fma(-al, av.im, rv.im);
     x[e] = xv;
     r[e] = rv;
-    acc[0] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
-  }
-  block_sum<1>(acc, sh);
-  const unsigned expected = (unsigned)(__popcll(run) * d.vtiles);
-  if (vpublish(acc[0], d.partials + (size_t)k * d.vtiles + tile, d.counter, expected, flag)) {
-    for (int kk = 0; kk < d.nsrc; ++kk) {
-      if (!(run >> kk & 1ull)) continue;
-      const double rn2 = total_of(d.partials, d.vtiles, kk, d.vtiles, sh);
-      if (threadIdx.x == 0) {
-        StateRef<FRESH> q = q0[kk];
-        q.iters = q.iters + 1;
-        if (!isfinite(rn2)) {
-          q.phase = PH_RU;
-          q.reason = RU_FINAL;
-          q.status = kStatusBreakdown;
-          continue;
-        }
-        const double rn = sqrt(rn2);
-        if (rn > q.rmax) q.rmax = rn;
-        if (q.iters >= q.max_iter) {
-          q.phase = PH_RU;
-          q.reason = RU_FINAL;
-          q.status = kStatusNotConverged;
-        } else if (rn2 <= q.stop2 || rn < q.delta * q.rmax) {
-          q.phase = PH_RU;
-          q.reason = RU_DROP;
-        } else {
-          q.beta = rn2 / q.rho;
-          q.rho = rn2;
-          q.pend = 1;
-        }
-      }
-    }
-    reset_counter(d.counter);
-  }
-  __syncthreads();  // the shared scratch is reused by the next tile
+    return (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+  });
+  if (threadIdx.x == 0) d.partials[(size_t)k * d.vtiles + tile] = t;
 }
 
 template <typename R, int RECON, int NBT, int LPS>
@@ -409,32 +447,31 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDes
 
 template <typename R, int RECON, int NBT, int LPS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDesc* __restrict__ sys,
-                                                                    int nsys, SrcState* st,
+                                                                    int nsys, const SrcState* st,
                                                                     int xcd) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  __shared__ int flag;
-  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), sh, tot, &flag);
+  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), sh, tot);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
-                                                 SrcState* st, int xcd) {
+                                                 const SrcState* st, int xcd) {
   __shared__ double sh[16];
-  __shared__ int flag;
-  xr_tile<R, false>(sys, nsys, st, logical_block(xcd), sh, &flag);
+  xr_tile<R, false>(sys, nsys, st, logical_block(xcd), sh);
 }
 
 // ------------------------------------------------------- persistent kernel
 //
-// One cooperative launch runs up to `iters` iterations of every system:
-// each pass is a grid-stride loop over tiles followed by a grid barrier.  The
-// barrier is a sense (generation) counter at agent scope; a wait gives up
-// after `timeout` ticks of the constant-rate device clock and raises the error
-// word, so that every block leaves the kernel.
+// One cooperative launch runs up to `iters` iterations of every system: each
+// pass is a grid-stride loop over tiles (or sources, for the finalize passes)
+// followed by a grid barrier.  The barrier is a generation counter at agent
+// scope; a wait gives up after `timeout` ticks of the constant-rate device
+// clock and raises the error word, so that every block leaves the kernel.
 // The loop ends when no source is running or one waits for a reliable update
 // (the host then runs the update), a decision every block takes from the same
-// state after a barrier.
+// state after a barrier.  Each barrier costs every block an agent-scope
+// release and acquire; the launch-per-pass engine is the default.
 
 __device__ __forceinline__ bool grid_sync(GridSync* gs, unsigned nblocks, long long timeout,
                                           int* ok_sh) {
@@ -442,15 +479,16 @@ __device__ __forceinline__ bool grid_sync(GridSync* gs, unsigned nblocks, long l
   if (threadIdx.x == 0) {
     int ok = 1;
     const unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    __threadfence();  // release this block's writes
     const unsigned arrived =
-        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&gs->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == nblocks - 1u) {
       __hip_atomic_store(&gs->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&gs->gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
+      // poll with relaxed loads (no cache maintenance per poll), acquire once below
       const long long t0 = wall_clock64();
-      while (__hip_atomic_load(&gs->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (__hip_atomic_load(&gs->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           ok = 0;
           break;
@@ -463,7 +501,7 @@ __device__ __forceinline__ bool grid_sync(GridSync* gs, unsigned nblocks, long l
         __builtin_amdgcn_s_sleep(2);
       }
     }
-    __threadfence();
+    __threadfence();  // acquire the other blocks' writes
     *ok_sh = ok;
   }
   __syncthreads();
@@ -477,7 +515,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
                     long long timeout) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  __shared__ int flag, ok;
+  __shared__ int ok;
   for (int it = 0; it < iters; ++it) {
     // leave when nothing runs or some source waits for a reliable update
     bool run = false, ru = false;
@@ -491,10 +529,16 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
       doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
-      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, sh, tot, &flag);
+      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, sh, tot);
+    if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
+    for (int g = blockIdx.x; g < nsrc_total; g += gridDim.x)
+      finalize_one<true>(sys, nsys, st, g, FIN_ALPHA, sh);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nvblk_total; b += gridDim.x)
-      xr_tile<R, true>(sys, nsys, st, b, sh, &flag);
+      xr_tile<R, true>(sys, nsys, st, b, sh);
+    if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
+    for (int g = blockIdx.x; g < nsrc_total; g += gridDim.x)
+      finalize_one<true>(sys, nsys, st, g, FIN_BETA, sh);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
   }
 }
@@ -503,12 +547,12 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
 
 // R1: t_hi = 2 D_oe (x_hi + x_lo) in FP64 for sources waiting for an update.
 template <typename Rlo, int RECON, int NBT>
-__global__ void __launch_bounds__((kMaxThreads<double, NBT>)) k_ru_doe(const SysDesc* __restrict__ sys, int nsys,
-                                                 const SrcState* st, int xcd) {
+__global__ void __launch_bounds__((kMaxThreads<double, NBT>))
+    k_ru_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd) {
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
-  const unsigned long long ru = phase_bits(st + d.src0, d.nsrc, PH_RU);
+  const unsigned long long ru = phase_bits<false>(st + d.src0, d.nsrc, PH_RU);
   const int cb = (b - d.blk0) * kTile + lane;
   const int k0 = grp * NBT;
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(ru, k0) : 0u;
@@ -531,20 +575,18 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>)) k_ru_doe(const Sys
   }
 }
 
-// R2: x_hi += x_lo, x_lo = 0, r_hi = b - (m^2 x_hi - 1/4 (2D_eo) t_hi) and
-// |r_hi|^2 in FP64; the last block declares convergence on this true residual
-// or prepares the restart of the recurrence (beta, rho, rmax).
+// R2: x_hi += x_lo, x_lo = 0, r_hi = b - (m^2 x_hi - 1/4 (2D_eo) t_hi) and the
+// partials of |r_hi|^2, all in FP64.
 template <typename Rlo, int RECON, int NBT>
-__global__ void __launch_bounds__((kMaxThreads<double, NBT>)) k_ru_residual(const SysDesc* __restrict__ sys, int nsys,
-                                                      SrcState* st, int xcd) {
+__global__ void __launch_bounds__((kMaxThreads<double, NBT>))
+    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  __shared__ int flag;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
-  const unsigned long long ru = phase_bits(q0, d.nsrc, PH_RU);
+  const SrcState* q0 = st + d.src0;
+  const unsigned long long ru = phase_bits<false>(q0, d.nsrc, PH_RU);
   if (!ru) return;
   const int bl = b - d.blk0, cb = bl * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
@@ -588,67 +630,28 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>)) k_ru_residual(cons
   }
   const int G = (int)(blockDim.x >> 6);
   group_sum<NBT>(rr, 1, grp, 0, G, sh, tot);
-  if (publish(tot, d.nsrc, d.partials, d.nblk, bl, d.counter, (unsigned)d.nblk, &flag)) {
-    for (int k = 0; k < d.nsrc; ++k) {
-      if (!(ru >> k & 1ull)) continue;
-      const double r2 = total_of(d.partials, d.nblk, k, d.nblk, sh);
-      if (threadIdx.x == 0) {
-        SrcState& q = q0[k];
-        q.updates += 1;
-        q.relres = sqrt(r2 / q.bnorm2);
-        if (r2 <= q.stop2) {
-          q.phase = PH_DONE;
-          q.status = kStatusOk;
-        } else if (!isfinite(r2)) {
-          q.phase = PH_DONE;
-          q.status = kStatusBreakdown;
-        } else if (q.reason == RU_FINAL) {
-          q.phase = PH_DONE;
-        } else {
-          q.beta = q.reason == RU_INIT ? 0.0 : r2 / q.rho;
-          q.rho = r2;
-          q.rmax = sqrt(r2);
-          q.phase = PH_RU2;
-        }
-      }
-    }
-    reset_counter(d.counter);
-  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < d.nsrc; ++k) d.partials[(size_t)k * d.nblk + bl] = tot[k];
 }
 
-// R3: r = lo(r_hi), p = r + beta p; the last block of the system lets the
-// updated sources iterate again.
+// R3: r = lo(r_hi), p = r + beta p for sources whose update did not converge.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ru_finish(const SysDesc* __restrict__ sys, int nsys,
-                                                   SrcState* st, int xcd) {
-  __shared__ int flag;
+                                                   const SrcState* st, int xcd) {
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  SrcState* q0 = st + d.src0;
-  const VBlock v = vblock(d, b);
-  const unsigned long long ru2 = phase_bits(q0, d.nsrc, PH_RU2);
-  if (!(ru2 >> v.k & 1ull)) return;
-  if (v.e < v.n) {
-    const size_t vs = v.n * d.nsrc, i = v.k * v.n + v.e;
-    const R be = (R)q0[v.k].beta;
-    const cplx<double> h = slot<double>(d.vhi, 1, vs)[i];
-    const cplx<R> rv = {(R)h.re, (R)h.im};
-    cplx<R>* p = slot<R>(d.vlo, 2, vs);
-    const cplx<R> pv = p[i];
-    slot<R>(d.vlo, 1, vs)[i] = rv;
-    p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
-  }
-  __syncthreads();
-  const unsigned expected = (unsigned)(__popcll(ru2) * d.vtiles);
-  if (vpublish(0.0, d.partials + (size_t)v.k * d.vtiles + v.tile, d.counter, expected, &flag)) {
-    if (threadIdx.x == 0)
-      for (int k = 0; k < d.nsrc; ++k)
-        if (ru2 >> k & 1ull) {
-          q0[k].phase = PH_RUN;
-          q0[k].pend = 0;
-        }
-    reset_counter(d.counter);
-  }
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const SrcState& q = st[d.src0 + k];
+  const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
+  if (q.phase != PH_RU2 || e >= n) return;
+  const size_t vs = n * d.nsrc, i = k * n + e;
+  const R be = (R)q.beta;
+  const cplx<double> h = slot<double>(d.vhi, 1, vs)[i];
+  const cplx<R> rv = {(R)h.re, (R)h.im};
+  cplx<R>* p = slot<R>(d.vlo, 2, vs);
+  const cplx<R> pv = p[i];
+  slot<R>(d.vlo, 1, vs)[i] = rv;
+  p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
 }
 
 // ================================================================ launchers
@@ -663,31 +666,50 @@ bool engine_supported(const EngineCfg& c) {
          c.nblk_total >= 1 && c.nvblk_total >= 1;
 }
 
+namespace {
+hipError_t finalize(const EngineCfg& c, int kind, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(256), 0, s, c.d_sys, c.nsys, c.d_st,
+                     kind);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s) {
   const dim3 grid(c.nvblk_total), block(kVTile);
-  return with_prec(c.prec_lo, [&]<typename R>() {
-    hipLaunchKernelGGL(k_init<R>, grid, block, 0, s, c.d_sys, c.nsys, c.d_st, zero_xhi,
-                       c.shape.xcd);
-    hipLaunchKernelGGL(k_zero_done, grid, block, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+  hipError_t e = with_prec(c.prec_lo, [&]<typename R>() {
+    hipLaunchKernelGGL(k_init<R>, grid, block, 0, s, c.d_sys, c.nsys, zero_xhi, c.shape.xcd);
     return hipGetLastError();
   });
+  if (e == hipSuccess) e = finalize(c, FIN_INIT, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_zero_done, grid, block, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * c.shape.lps * G);
   const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
-  const dim3 vgrid(c.nvblk_total), vblock_(kVTile);
-  return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
+  const dim3 vgrid(c.nvblk_total), vblock(kVTile);
+  hipError_t e = with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
       hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st, c.shape.xcd);
-      hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
       return hipGetLastError();
     });
   });
+  if (e == hipSuccess) e = finalize(c, FIN_ALPHA, s);
+  if (e == hipSuccess)
+    e = with_prec(c.prec_lo, [&]<typename R>() {
+      hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+      return hipGetLastError();
+    });
+  if (e == hipSuccess) e = finalize(c, FIN_BETA, s);
+  return e;
 }
 
 namespace {
@@ -749,8 +771,8 @@ hipError_t engine_persistent(const EngineCfg& c, int iters, GridSync* gs, int gr
 hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * G);
-  const dim3 vgrid(c.nvblk_total), vblock_(kVTile);
-  return with_prec(c.prec_lo, [&]<typename Rlo>() {
+  const dim3 vgrid(c.nvblk_total), vblock(kVTile);
+  hipError_t e = with_prec(c.prec_lo, [&]<typename Rlo>() {
     return with_nbt(c.shape.nbt, [&]<int NBT>() {
       if (c.recon_hi == 12) {
         hipLaunchKernelGGL((k_ru_doe<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
@@ -763,11 +785,18 @@ hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
         hipLaunchKernelGGL((k_ru_residual<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
                            c.d_st, c.shape.xcd);
       }
-      hipLaunchKernelGGL(k_ru_finish<Rlo>, vgrid, vblock_, 0, s, c.d_sys, c.nsys, c.d_st,
-                         c.shape.xcd);
       return hipGetLastError();
     });
   });
+  if (e == hipSuccess) e = finalize(c, FIN_RU, s);
+  if (e == hipSuccess)
+    e = with_prec(c.prec_lo, [&]<typename Rlo>() {
+      hipLaunchKernelGGL(k_ru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                         c.shape.xcd);
+      return hipGetLastError();
+    });
+  if (e == hipSuccess) e = finalize(c, FIN_COMMIT, s);
+  return e;
 }
 
 }  // namespace qx

@@ -72,8 +72,7 @@ struct SysDesc {
   const void* links_hi;
   void* vlo;        // inner precision: x_lo, r, p, Ap (even), t (odd); each [nsrc][3][hv]
   void* vhi;        // FP64: x_hi, r_hi, b (even), t_hi (odd); each [nsrc][3][hv]
-  double* partials; // [nsrc][nblk] (stencil) or [nsrc][vtiles] (vector)
-  unsigned* counter;  // last-block counter of this system (kept at zero between launches)
+  double* partials;   // per-block partial sums: [nsrc][nblk] (stencil) or [nsrc][vtiles] (vector)
 };
 
 // Grid barrier of the persistent solver kernel (zeroed before first use).

@@ -308,18 +308,26 @@ hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials
 
 // ================================================================ probe
 
-// Plain copy with 16-byte accesses: the measured-bandwidth reference and the
-// calibration kernel for the memory counters.
+// Plain copy with 16-byte accesses, four independent loads in flight per
+// thread: the measured-bandwidth reference and the calibration kernel for the
+// memory counters.
 __global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src,
                                                 uint4* __restrict__ dst, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
   const size_t n = bytes / 16;
-  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 64);
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 32);
   hipLaunchKernelGGL(k_copy16, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, (const uint4*)src,
                      (uint4*)dst, n);
   return hipGetLastError();

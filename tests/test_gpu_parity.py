@@ -307,10 +307,20 @@ def test_uneven_batch_config4(qx):
         keep.append((dims, U, b, masses, xd, lat))
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
+    xs, all_stats = [], []
     with torch.cuda.stream(side):  # a non-default stream: the chunk is captured in a HIP graph
         batch = qx.Batch(systems, tol=1e-10, engine=qx.ENGINE_LAUNCH)
-        all_stats = [batch.solve() for rep in range(2)]
+        for rep in range(2):
+            all_stats.append(batch.solve())
+            torch.cuda.synchronize()
+            xs.append([to_host(k[4]).copy() for k in keep])
     torch.cuda.synchronize()
+    # the same batch run eagerly on the default stream (no graph) gives the same bits
+    all_stats.append(batch.solve())
+    xs.append([to_host(k[4]).copy() for k in keep])
+    for rep in (0, 1):
+        for a, e in zip(xs[rep], xs[2]):
+            assert np.array_equal(a, e)
     for stats in all_stats:
         j = 0
         for dims, U, b, masses, xd, lat in keep:
