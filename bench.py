@@ -91,8 +91,12 @@ def copy_probe(torch, qx, nb=1 << 30):
     c = torch.empty(nb, dtype=torch.uint8, device="cuda")
     t_copy = time_kernel(torch, lambda: qx.probe_copy(c, a, nb), 20)
     copy_gbs = 2 * nb / t_copy / 1e9
-    log(f"copy probe: {nb} bytes, {t_copy * 1e6:.1f} us, {copy_gbs:.0f} GB/s (read + write)")
-    return copy_gbs
+    scratch = torch.zeros(8192, dtype=torch.int32, device="cuda")
+    t_read = time_kernel(torch, lambda: qx.probe_read(a, nb, scratch), 20)
+    read_gbs = nb / t_read / 1e9
+    log(f"copy probe: {nb} bytes, {t_copy * 1e6:.1f} us, {copy_gbs:.0f} GB/s (read + write); "
+        f"read probe: {t_read * 1e6:.1f} us, {read_gbs:.0f} GB/s")
+    return copy_gbs, read_gbs
 
 
 def multi_rhs(torch, qx, synth):
@@ -172,9 +176,10 @@ def main():
     log(f"tuned launch shapes: f32-12 {shape32}, f64-18 {shape64}")
     if args.kernels_only:
         t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
-        copy_gbs = copy_probe(torch, qx)
+        copy_gbs, read_gbs = copy_probe(torch, qx)
         print(json.dumps({"kernels_only": True, "dominant_us": round(t_k * 1e6, 3),
-                          "achieved_gbs": round(achieved, 1), "copy_probe_gbs": round(copy_gbs, 1)}))
+                          "achieved_gbs": round(achieved, 1), "copy_probe_gbs": round(copy_gbs, 1),
+                          "read_probe_gbs": round(read_gbs, 1)}))
         return
     x_mx = torch.empty_like(bd)
     x_64 = torch.empty_like(bd)
@@ -251,7 +256,32 @@ def main():
         del g
     del U32
 
-    copy_gbs = copy_probe(torch, qx)
+    # 48^4: every operand far beyond the 256 MB Infinity Cache (link values do
+    # not change the traffic, so a unit gauge field built on the device is used)
+    dims48 = (48, 48, 48, 48)
+    lat48 = qx.Lattice(dims48)
+    U48 = torch.zeros((4, lat48.V, 3, 3), dtype=torch.complex128, device="cuda")
+    U48[..., 0, 0] = U48[..., 1, 1] = U48[..., 2, 2] = 1.0
+    for prec, recon, link_b, vec_b in (("f32", 12, 384, 24), ("f64", 18, 1152, 48)):
+        g = qx.Gauge(lat48, U48, prec, recon)
+        g.tune(1)
+        src = torch.from_numpy(synth.gauss_source(1, lat48.hv, 3)).cuda()
+        pin = qx.pack(lat48, src, prec)
+        pout = qx.dslash(g, pin, 0, 1)
+        t = time_kernel(torch, lambda: qx.dslash(g, pin, 0, 1, out=pout), 30)
+        by = (link_b + 2 * vec_b) * lat48.hv
+        d32[f"48^4-{prec}-{recon}-nrhs1"] = {
+            "us": round(t * 1e6, 2),
+            "gflops": round(FLOPS_SITE * lat48.hv / t / 1e9, 1),
+            "gbs_algorithmic": round(by / t / 1e9, 1),
+            "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
+            "shape": list(g.launch(1)),
+        }
+        log(f"48^4 {prec}-{recon}: {d32[f'48^4-{prec}-{recon}-nrhs1']}")
+        del g, src, pin, pout
+    del U48
+
+    copy_gbs, read_gbs = copy_probe(torch, qx)
 
     multi = None if args.no_multi else multi_rhs(torch, qx, synth)
 
@@ -316,9 +346,10 @@ def main():
             "bytes_per_site": BYTES_SITE_F32_12,
             "sites_per_launch": hv,
         },
-        "dslash_32^4": d32,
+        "dslash_sweep": d32,
         "multi_rhs_32^4": multi,
         "copy_probe_gbs": round(copy_gbs, 1),
+        "read_probe_gbs": round(read_gbs, 1),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

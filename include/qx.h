@@ -302,6 +302,11 @@ int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, int xcd_order
    calibration kernel for hardware memory counters.  Asynchronous. */
 int qx_probe_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
+/* Read `bytes` (a multiple of 16) of src once with a plain streaming kernel:
+   the measured read bandwidth, the reference for read-dominated kernels such
+   as the Dslash.  scratch: 32 KiB of device memory.  Asynchronous. */
+int qx_probe_read(const void* src, size_t bytes, void* scratch, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

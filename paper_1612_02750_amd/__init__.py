@@ -103,6 +103,7 @@ def load():
         "qx_get_launch": ([_P, _I, _P, _P, _P], _I),
         "qx_set_launch": ([_P, _I, _I, _I, _I], _I),
         "qx_probe_copy": ([_P, _P, _SZ, _P], _I),
+        "qx_probe_read": ([_P, _SZ, _P, _P], _I),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -400,6 +401,11 @@ def force_from_fields(g64: Gauge, x, lam, stream=None):
 def probe_copy(dst, src, nbytes: int, stream=None):
     """dst = src with the library's streaming copy kernel (bandwidth reference)."""
     _check(load().qx_probe_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
+
+
+def probe_read(src, nbytes: int, scratch, stream=None):
+    """Read nbytes of src once with the library's streaming read kernel."""
+    _check(load().qx_probe_read(_ptr(src), int(nbytes), _ptr(scratch), _stream(stream)))
 
 
 def force_su3(lat: Lattice, U, G, stream=None):

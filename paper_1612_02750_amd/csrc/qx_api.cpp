@@ -873,6 +873,12 @@ extern "C" int qx_probe_copy(void* dst, const void* src, size_t bytes, hipStream
   return QX_OK;
 }
 
+extern "C" int qx_probe_read(const void* src, size_t bytes, void* scratch, hipStream_t stream) {
+  if (!src || !scratch || bytes % 16) return fail(QX_EINVAL, "qx_probe_read: bad argument");
+  QX_HIP(launch_read(src, bytes, (unsigned*)scratch, stream), "qx_probe_read");
+  return QX_OK;
+}
+
 // ------------------------------------------------------------------ tuning
 
 extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* nbt, int* lps, int* xcd_order) {

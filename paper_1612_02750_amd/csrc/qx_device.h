@@ -45,8 +45,26 @@ __device__ __forceinline__ cplx<R> cmul(const cplx<R>& a, const cplx<R>& b) {
 // parity of x) and the y, z, t neighbours are cb +- s1, s2, s3 with wrap.
 struct Site {
   int x0, x1, x2, x3;
-  int fwd[4];
-  int bwd[4];
+  int f0, f1, f2, f3;  // checkerboard index of x + mu
+  int b0, b1, b2, b3;  // checkerboard index of x - mu
+  // neighbour of hop h (h < 4: x + mu_h, else x - mu_{h-4}); h known at compile time
+  template <int H>
+  __host__ __device__ __forceinline__ int nbr() const {
+    if constexpr (H == 0) return f0;
+    else if constexpr (H == 1) return f1;
+    else if constexpr (H == 2) return f2;
+    else if constexpr (H == 3) return f3;
+    else if constexpr (H == 4) return b0;
+    else if constexpr (H == 5) return b1;
+    else if constexpr (H == 6) return b2;
+    else return b3;
+  }
+  __host__ __device__ __forceinline__ int fwd(int mu) const {
+    return mu == 0 ? f0 : mu == 1 ? f1 : mu == 2 ? f2 : f3;
+  }
+  __host__ __device__ __forceinline__ int bwd(int mu) const {
+    return mu == 0 ? b0 : mu == 1 ? b1 : mu == 2 ? b2 : b3;
+  }
 };
 
 __host__ __device__ __forceinline__ void site_geometry(const Geo& g, int p, int cb, Site& s) {
@@ -64,14 +82,14 @@ __host__ __device__ __forceinline__ void site_geometry(const Geo& g, int p, int 
   const int row = r * g.Lh;
   const int x0p = (x0 + 1 == g.L0) ? 0 : x0 + 1;
   const int x0m = (x0 == 0) ? g.L0 - 1 : x0 - 1;
-  s.fwd[0] = row + (x0p >> 1);
-  s.bwd[0] = row + (x0m >> 1);
-  s.fwd[1] = (x1 + 1 == g.L1) ? cb - (g.L1 - 1) * g.s1 : cb + g.s1;
-  s.bwd[1] = (x1 == 0) ? cb + (g.L1 - 1) * g.s1 : cb - g.s1;
-  s.fwd[2] = (x2 + 1 == g.L2) ? cb - (g.L2 - 1) * g.s2 : cb + g.s2;
-  s.bwd[2] = (x2 == 0) ? cb + (g.L2 - 1) * g.s2 : cb - g.s2;
-  s.fwd[3] = (x3 + 1 == g.L3) ? cb - (g.L3 - 1) * g.s3 : cb + g.s3;
-  s.bwd[3] = (x3 == 0) ? cb + (g.L3 - 1) * g.s3 : cb - g.s3;
+  s.f0 = row + (x0p >> 1);
+  s.b0 = row + (x0m >> 1);
+  s.f1 = (x1 + 1 == g.L1) ? cb - (g.L1 - 1) * g.s1 : cb + g.s1;
+  s.b1 = (x1 == 0) ? cb + (g.L1 - 1) * g.s1 : cb - g.s1;
+  s.f2 = (x2 + 1 == g.L2) ? cb - (g.L2 - 1) * g.s2 : cb + g.s2;
+  s.b2 = (x2 == 0) ? cb + (g.L2 - 1) * g.s2 : cb - g.s2;
+  s.f3 = (x3 + 1 == g.L3) ? cb - (g.L3 - 1) * g.s3 : cb + g.s3;
+  s.b3 = (x3 == 0) ? cb + (g.L3 - 1) * g.s3 : cb - g.s3;
 }
 
 // Staggered phase eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}).
@@ -148,7 +166,52 @@ struct FieldIn {
   }
 };
 
+// acc[j] += hop H applied to in_j, j < NBT (bit j of act).
+template <int H, typename R, int RECON, int NBT, typename In>
+__device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restrict__ lf,
+                                            const cplx<R>* __restrict__ lb, int cb, const Site& s,
+                                            const In& in, unsigned act, cplx<R> (&acc)[NBT][3]) {
+  constexpr int E = RECON == 12 ? 6 : 9;
+  constexpr int mu = H & 3;
+  constexpr bool fwd = H < 4;
+  const size_t hv = (size_t)g.hv;
+  int sign = 1;
+  if constexpr (RECON == 12) {
+    // Forward link U_mu(x); backward link U_mu(x - mu), which has the same
+    // eta (eta_mu does not depend on x_mu) and the antiperiodic sign when
+    // (x - mu)_3 = L3 - 1, i.e. x3 = 0 for mu = t.
+    const int e = eta_sign(mu, s.x0, s.x1, s.x2);
+    const bool flip = mu == 3 && g.anti_t && (fwd ? s.x3 == g.L3 - 1 : s.x3 == 0);
+    sign = flip ? -e : e;
+  }
+  const int nb = s.template nbr<H>();
+  cplx<R> u[9];
+  load_link<R, RECON>(u, (fwd ? lf + (size_t)mu * E * hv + cb : lb + (size_t)mu * E * hv + nb), hv,
+                      sign);
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+    const cplx<R> c0 = in(j, 0, nb), c1 = in(j, 1, nb), c2 = in(j, 2, nb);
+    if constexpr (fwd) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cfma(acc[j][a], u[3 * a + 0], c0);
+        cfma(acc[j][a], u[3 * a + 1], c1);
+        cfma(acc[j][a], u[3 * a + 2], c2);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        cfms_conj(acc[j][a], u[0 + a], c0);
+        cfms_conj(acc[j][a], u[3 + a], c1);
+        cfms_conj(acc[j][a], u[6 + a], c2);
+      }
+    }
+  }
+}
+
 // acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT (bit j of act).
+// Each hop is its own instantiation, guarded by a wavefront-uniform test.
 template <typename R, int RECON, int NBT, int LPS, typename In>
 __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __restrict__ links,
                                              int pout, int cb, const Site& s, int dp, const In& in,
@@ -157,45 +220,17 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __rest
   const size_t hv = (size_t)g.hv;
   const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
   const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
-#pragma unroll
-  for (int h = 0; h < 8; ++h) {
-    if (LPS > 1 && (h % LPS) != dp) continue;  // uniform across the wavefront
-    const int mu = h & 3;
-    const bool fwd = h < 4;
-    int sign = 1;
-    if constexpr (RECON == 12) {
-      // Forward link U_mu(x); backward link U_mu(x - mu), which has the same
-      // eta (eta_mu does not depend on x_mu) and the antiperiodic sign when
-      // (x - mu)_3 = L3 - 1, i.e. x3 = 0 for mu = t.
-      const int e = eta_sign(mu, s.x0, s.x1, s.x2);
-      const bool flip = mu == 3 && g.anti_t && (fwd ? s.x3 == g.L3 - 1 : s.x3 == 0);
-      sign = flip ? -e : e;
-    }
-    const int nb = fwd ? s.fwd[mu] : s.bwd[mu];
-    cplx<R> u[9];
-    load_link<R, RECON>(u, (fwd ? lf + (size_t)mu * E * hv + cb : lb + (size_t)mu * E * hv + nb),
-                        hv, sign);
-#pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      if (!(act >> j & 1u)) continue;
-      const cplx<R> c0 = in(j, 0, nb), c1 = in(j, 1, nb), c2 = in(j, 2, nb);
-      if (fwd) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          cfma(acc[j][a], u[3 * a + 0], c0);
-          cfma(acc[j][a], u[3 * a + 1], c1);
-          cfma(acc[j][a], u[3 * a + 2], c2);
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          cfms_conj(acc[j][a], u[0 + a], c0);
-          cfms_conj(acc[j][a], u[3 + a], c1);
-          cfms_conj(acc[j][a], u[6 + a], c2);
-        }
-      }
-    }
-  }
+#define QX_HOP(H) \
+  if (LPS == 1 || (H) % LPS == dp) stencil_hop<H, R, RECON, NBT>(g, lf, lb, cb, s, in, act, acc)
+  QX_HOP(0);
+  QX_HOP(1);
+  QX_HOP(2);
+  QX_HOP(3);
+  QX_HOP(4);
+  QX_HOP(5);
+  QX_HOP(6);
+  QX_HOP(7);
+#undef QX_HOP
 }
 
 template <typename R, int NBT>
@@ -206,15 +241,22 @@ __device__ __forceinline__ void zero_acc(cplx<R> (&acc)[NBT][3]) {
     for (int a = 0; a < 3; ++a) acc[j][a] = {(R)0, (R)0};
 }
 
-// Sum the LPS hop parts of a block through LDS.  Wave w of the block is
-// (part dp = w % LPS, group grp = w / LPS); after the call, item i = 3 j + c
-// (source j of the group, colour c) is complete in the wave whose part is
-// i % LPS, in acc[j][c].  The sources are reduced one slot j at a time, so
-// red holds G * LPS * 3 * 64 complex numbers.
-template <typename R, int NBT, int LPS>
-__device__ __forceinline__ void reduce_parts(cplx<R> (&acc)[NBT][3], cplx<R>* red, int dp, int grp,
-                                             int lane) {
-  if constexpr (LPS > 1) {
+// Visit every reduced item of the block's stencil: f(j, c, v) is called for
+// item (source slot j, colour c) with the sum v over the LPS hop parts, in the
+// wavefront that owns it (part (3 j + c) % LPS).  Wave w of the block is
+// (part dp = w % LPS, group grp = w / LPS).  Without hop splitting f sees
+// acc[j][c] directly; with it the parts meet in LDS, one slot j at a time, so
+// red holds G * LPS * 3 * 64 complex numbers.  All threads of the block must
+// call it (it synchronises when LPS > 1).
+template <typename R, int NBT, int LPS, typename F>
+__device__ __forceinline__ void for_each_item(const cplx<R> (&acc)[NBT][3], cplx<R>* red, int dp,
+                                              int grp, int lane, F&& f) {
+  if constexpr (LPS == 1) {
+#pragma unroll
+    for (int j = 0; j < NBT; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f(j, c, acc[j][c]);
+  } else {
     cplx<R>* mine = red + (size_t)(grp * LPS + dp) * 3 * 64;
     const cplx<R>* base = red + (size_t)grp * LPS * 3 * 64;
 #pragma unroll
@@ -233,7 +275,7 @@ __device__ __forceinline__ void reduce_parts(cplx<R> (&acc)[NBT][3], cplx<R>* re
           t.re += v.re;
           t.im += v.im;
         }
-        acc[j][c] = t;
+        f(j, c, t);
       }
     }
   }
@@ -242,12 +284,6 @@ __device__ __forceinline__ void reduce_parts(cplx<R> (&acc)[NBT][3], cplx<R>* re
 // Threads per stencil block allowed by the register budget (see max_waves).
 template <typename R, int NBT>
 constexpr int kMaxThreads = sizeof(R) * NBT > 8 ? 512 : 1024;
-
-// Does the wave of part dp own item i = 3 j + c after reduce_parts?
-template <int LPS>
-__device__ __forceinline__ bool owns_item(int i, int dp) {
-  return LPS == 1 || i % LPS == dp;
-}
 
 // ------------------------------------------------------------- reductions
 

@@ -36,15 +36,9 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const c
     stencil_part<R, RECON, NBT, LPS>(g, links, pout, cb, s, dp, FieldIn<R>{in + k0 * ss, ss, hv},
                                      act, acc);
   }
-  reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
-#pragma unroll
-  for (int j = 0; j < NBT; ++j) {
-    if (!(act >> j & 1u)) continue;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (owns_item<LPS>(3 * j + c, dp))
-        out[(k0 + j) * ss + c * hv + cb] = {scale * acc[j][c].re, scale * acc[j][c].im};
-  }
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+    if (act >> j & 1u) out[(k0 + j) * ss + c * hv + cb] = {scale * v.re, scale * v.im};
+  });
 }
 
 struct Masses16 {

@@ -16,10 +16,11 @@
 // writes back the issuing XCD's L2, so a fence per block (last-block
 // reductions, grid barriers) costs far more than the extra launch.
 //
-// One iteration is five launches: D_oe (applying the pending p update on the
-// fly), D_eo fused with the A epilogue, the p update store and the <p, Ap>
-// partials, the alpha finalize, the x/r update with the |r|^2 partials, and
-// the beta finalize.
+// One iteration is six launches: the p update (p = r + beta p), D_oe, D_eo
+// fused with the A epilogue and the <p, Ap> partials, the alpha finalize, the
+// x/r update with the |r|^2 partials, and the beta finalize.  (Applying the p
+// update on the fly inside D_oe saves a pass but doubles the neighbour loads
+// the compiler hoists, which spills registers; the separate pass is cheaper.)
 //
 // Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd)}, FP64
 // vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv].
@@ -101,24 +102,6 @@ struct SumIn {
     const cplx<double> a = hi[j * ss + c * hv + site];
     const cplx<Rlo> b = lo[j * ss + c * hv + site];
     return {a.re + (double)b.re, a.im + (double)b.im};
-  }
-};
-
-// Input of the D_oe pass of an iteration: p, or r + beta p for sources whose
-// search direction is still to be updated (bit j of pend).
-template <typename R, int NBT>
-struct PendIn {
-  const cplx<R>* __restrict__ p;
-  const cplx<R>* __restrict__ r;
-  size_t ss, hv;
-  unsigned pend;
-  R beta[NBT];
-  __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
-    const size_t i = j * ss + c * hv + site;
-    const cplx<R> pv = p[i];
-    if (!(pend >> j & 1u)) return pv;
-    const cplx<R> rv = r[i];
-    return {fma(beta[j], pv.re, rv.re), fma(beta[j], pv.im, rv.im)};
   }
 };
 
@@ -295,8 +278,9 @@ __device__ __forceinline__ void finalize_one(const SysDesc* __restrict__ sys, in
   if (threadIdx.x == 0) finalize_source<FRESH>(kind, st[g], t);
 }
 
-// One block per source of the batch.
-__global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, int nsys,
+// One block of 1024 threads per source of the batch (the partials of a 32^4
+// system number 8192 per source: four loads per thread keep this short).
+__global__ void __launch_bounds__(1024) k_finalize(const SysDesc* __restrict__ sys, int nsys,
                                                   SrcState* st, int kind) {
   __shared__ double sh[16];
   finalize_one<false>(sys, nsys, st, blockIdx.x, kind, sh);
@@ -308,8 +292,7 @@ __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sy
 // a 256-element vector tile) so that the same code serves the launch-per-pass
 // kernels and the persistent kernel.
 
-// E1: t = 2 D_oe p for running sources, with p = r + beta p applied on the fly
-// where the previous iteration left it pending.
+// E1: t = 2 D_oe p for running sources.
 template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b) {
@@ -326,33 +309,19 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
   if (act) {
-    PendIn<R, NBT> in{slot<R>(d.vlo, 2, vs) + k0 * ss, slot<R>(d.vlo, 1, vs) + k0 * ss, ss, hv, 0u, {}};
-#pragma unroll
-    for (int j = 0; j < NBT; ++j) {
-      in.beta[j] = (R)0;
-      if (act >> j & 1u) {
-        in.beta[j] = (R)rd<FRESH>(q0[k0 + j].beta);
-        if (rd<FRESH>(q0[k0 + j].pend)) in.pend |= 1u << j;
-      }
-    }
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp, in, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp,
+                                     FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv}, act, acc);
   }
-  reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
-#pragma unroll
-  for (int j = 0; j < NBT; ++j) {
-    if (!(act >> j & 1u)) continue;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (owns_item<LPS>(3 * j + c, dp)) t[(k0 + j) * ss + c * hv + cb] = acc[j][c];
-  }
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+    if (act >> j & 1u) t[(k0 + j) * ss + c * hv + cb] = v;
+  });
   if constexpr (LPS > 1) __syncthreads();  // the LDS buffer is reused by the next tile
 }
 
-// E2: p = r + beta p where pending (stored), Ap = m^2 p - 1/4 (2D_eo) t and the
-// partials of Re<p, Ap>.
+// E2: Ap = m^2 p - 1/4 (2D_eo) t and the partials of Re<p, Ap>.
 template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b, double* sh, double* tot) {
@@ -374,35 +343,20 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
     stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 0, cb, s, dp,
                                      FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
   }
-  reduce_parts<R, NBT, LPS>(acc, red, dp, grp, lane);
   double dot[NBT];
 #pragma unroll
   for (int j = 0; j < NBT; ++j) dot[j] = 0.0;
-  cplx<R>* p = slot<R>(d.vlo, 2, vs);
-  const cplx<R>* rr = slot<R>(d.vlo, 1, vs);
+  const cplx<R>* p = slot<R>(d.vlo, 2, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
-#pragma unroll
-  for (int j = 0; j < NBT; ++j) {
-    if (!(act >> j & 1u)) continue;
-    const SrcState& q = q0[k0 + j];
-    const R m2 = (R)rd<FRESH>(q.m2);
-    const bool pend = rd<FRESH>(q.pend) != 0;
-    const R be = (R)rd<FRESH>(q.beta);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (!owns_item<LPS>(3 * j + c, dp)) continue;
-      const size_t i = (k0 + j) * ss + c * hv + cb;
-      cplx<R> pv = p[i];
-      if (pend) {
-        const cplx<R> rv = rr[i];
-        pv = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
-        p[i] = pv;
-      }
-      const cplx<R> r = {m2 * pv.re - (R)0.25 * acc[j][c].re, m2 * pv.im - (R)0.25 * acc[j][c].im};
-      Ap[i] = r;
-      dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
-    }
-  }
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+    if (!(act >> j & 1u)) return;
+    const R m2 = (R)rd<FRESH>(q0[k0 + j].m2);
+    const size_t i = (k0 + j) * ss + c * hv + cb;
+    const cplx<R> pv = p[i];
+    const cplx<R> r = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
+    Ap[i] = r;
+    dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
+  });
   const int G = (int)(blockDim.x >> 6) / LPS;
   group_sum<NBT>(dot, LPS, grp, dp, G, sh, tot);
   if (threadIdx.x == 0)
@@ -436,6 +390,33 @@ __device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsy
     return (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
   });
   if (threadIdx.x == 0) d.partials[(size_t)k * d.vtiles + tile] = t;
+}
+
+// E0: p = r + beta p over one vector tile, for running sources whose search
+// direction the previous iteration left pending.  Works for any block size.
+template <typename R, bool FRESH>
+__device__ __forceinline__ void p_tile(const SysDesc* __restrict__ sys, int nsys,
+                                       const SrcState* st, int b) {
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const SrcState& q = st[d.src0 + k];
+  if (rd<FRESH>(q.phase) != PH_RUN || !rd<FRESH>(q.pend)) return;
+  const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
+  const R be = (R)rd<FRESH>(q.beta);
+  const cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
+  cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  for (int t = threadIdx.x; t < kVTile; t += blockDim.x) {
+    const size_t e = (size_t)tile * kVTile + t;
+    if (e >= n) break;
+    const cplx<R> rv = r[e], pv = p[e];
+    p[e] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_iter_p(const SysDesc* __restrict__ sys, int nsys,
+                                                const SrcState* st, int xcd) {
+  p_tile<R, false>(sys, nsys, st, logical_block(xcd));
 }
 
 template <typename R, int RECON, int NBT, int LPS>
@@ -525,6 +506,8 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
       ru |= ph == PH_RU;
     }
     if (!run || ru) break;
+    for (int b = blockIdx.x; b < nvblk_total; b += gridDim.x) p_tile<R, true>(sys, nsys, st, b);
+    if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
       doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
@@ -668,7 +651,7 @@ bool engine_supported(const EngineCfg& c) {
 
 namespace {
 hipError_t finalize(const EngineCfg& c, int kind, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(256), 0, s, c.d_sys, c.nsys, c.d_st,
+  hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(1024), 0, s, c.d_sys, c.nsys, c.d_st,
                      kind);
   return hipGetLastError();
 }
@@ -695,6 +678,7 @@ hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
   hipError_t e = with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+      hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,

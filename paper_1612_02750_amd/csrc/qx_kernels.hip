@@ -114,8 +114,8 @@ __global__ void __launch_bounds__(256) k_index_maps(Geo g, int32_t* __restrict__
   const int other = (1 - p) * g.hv;
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
-    nbr[eo * 8 + mu] = other + s.fwd[mu];
-    nbr[eo * 8 + 4 + mu] = other + s.bwd[mu];
+    nbr[eo * 8 + mu] = other + s.fwd(mu);
+    nbr[eo * 8 + 4 + mu] = other + s.bwd(mu);
   }
 }
 
@@ -323,6 +323,33 @@ __global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src,
     dst[i + 3 * stride] = d;
   }
   for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// Read-only streaming pass (16-byte loads, four in flight per thread); the
+// xor of the words of each block goes to out[block] so that nothing is elided.
+__global__ void __launch_bounds__(256) k_read16(const uint4* __restrict__ src, size_t n,
+                                                unsigned* __restrict__ out) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned acc = 0;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+  }
+  for (; i < n; i += stride) {
+    const uint4 a = src[i];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  for (int off = 32; off >= 1; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicXor(out + blockIdx.x, acc);
+}
+
+hipError_t launch_read(const void* src, size_t bytes, unsigned* out, hipStream_t s) {
+  const size_t n = bytes / 16;
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 32);
+  hipLaunchKernelGGL(k_read16, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, (const uint4*)src, n,
+                     out);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {

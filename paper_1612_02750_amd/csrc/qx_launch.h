@@ -85,6 +85,8 @@ hipError_t launch_su3_force(const Geo& g, const void* U, const void* G, double* 
 hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials, int nblk,
                         double* out, hipStream_t s);
 
+// Read bytes (a multiple of 16) once; out: 8192 unsigned words of scratch.
+hipError_t launch_read(const void* src, size_t bytes, unsigned* out, hipStream_t s);
 // dst = src, bytes a multiple of 16.
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
