@@ -85,6 +85,7 @@ Geo make_geo(const int32_t d[4], uint32_t flags) {
   g.s2 = g.Lh * d[1];
   g.s3 = g.Lh * d[1] * d[2];
   g.anti_t = (flags & QX_BC_T_ANTIPERIODIC) ? 1 : 0;
+  g.stream_links = 0;
   return g;
 }
 
@@ -481,6 +482,8 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     const SysSpec& s = B->specs[i];
     SysDesc d{};
     d.g = s.g64->geo;
+    d.g.stream_links = gauge_bytes(d.g, s.glo->prec, s.glo->recon) > kStreamLinkBytes &&
+                       shape_groups(sh, nb) == 1;
     d.nsrc = s.nrhs;
     d.src0 = src;
     d.blk0 = blk;

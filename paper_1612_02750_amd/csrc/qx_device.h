@@ -124,14 +124,30 @@ __device__ __forceinline__ int logical_block(int xcd_order) {
 
 // ------------------------------------------------------------------- links
 
+// Non-temporal load of one complex number.  Links are read once per
+// half-Dslash; when they cannot stay in the Infinity Cache anyway they stream
+// past the caches, which then keep the colour vectors (each read by eight
+// neighbouring sites).
+template <typename R>
+__device__ __forceinline__ cplx<R> ld_stream(const cplx<R>* p) {
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return {t.x, t.y};
+}
+
 // Packed links: [parity][mu][element][cb], element e = 3 * row + column, E = 9
 // (18 reals) or 6 (12 reals: rows 0 and 1).  p points at element 0 of one link.
 template <typename R, int RECON>
 __device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<R>* __restrict__ p, size_t hv,
-                                          int sign) {
+                                          int sign, bool stream) {
   constexpr int E = RECON == 12 ? 6 : 9;
+  if (stream) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) u[e] = p[e * hv];
+    for (int e = 0; e < E; ++e) u[e] = ld_stream(p + e * hv);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) u[e] = p[e * hv];
+  }
   if constexpr (RECON == 12) {
     // For W = s U with U in SU(3), s = +-1: row2(W) = s * conj(row0(W) x row1(W)).
     const R s = (R)sign;
@@ -187,7 +203,7 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
   const int nb = s.template nbr<H>();
   cplx<R> u[9];
   load_link<R, RECON>(u, (fwd ? lf + (size_t)mu * E * hv + cb : lb + (size_t)mu * E * hv + nb), hv,
-                      sign);
+                      sign, g.stream_links != 0);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     if (!(act >> j & 1u)) continue;

@@ -96,15 +96,18 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
   const size_t field = (size_t)3 * g.hv * csz;
   const int per = sources_per_pass(sh, csz);
   const unsigned grid = grid_for(g.hv, kTile);
+  const size_t link_bytes = (size_t)8 * g.hv * (recon == 12 ? 6 : 9) * csz;
   for (int k0 = 0; k0 < nsrc; k0 += per) {
     const int n = std::min(per, nsrc - k0);
     const int threads = 64 * sh.lps * shape_groups(sh, n);
+    Geo gl = g;
+    gl.stream_links = link_bytes > kStreamLinkBytes && shape_groups(sh, n) == 1;
     const size_t lds = shape_lds(sh, n, csz);
     const char* pin = (const char*)in + k0 * field;
     char* po = (char*)out + k0 * field;
     hipError_t e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
       return with_nbt_lps(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
-        hipLaunchKernelGGL((k_dslash<R, RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, g,
+        hipLaunchKernelGGL((k_dslash<R, RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, gl,
                            (const cplx<R>*)links, pout, (const cplx<R>*)pin, (cplx<R>*)po, n,
                            (R)scale, sh.xcd);
         return hipGetLastError();

@@ -24,7 +24,12 @@ struct Geo {
   int Lh;        // L0 / 2
   int s1, s2, s3;  // Lh, Lh*L1, Lh*L1*L2
   int anti_t;    // antiperiodic time boundary
+  int stream_links;  // load links non-temporally (set per launch by the host)
 };
+
+// Links bigger than this do not fit the Infinity Cache next to the vectors
+// and are streamed past the caches when one wavefront group reads each link.
+constexpr size_t kStreamLinkBytes = (size_t)256 << 20;
 
 // ------------------------------------------------------------ solver state
 

@@ -325,28 +325,33 @@ __global__ void __launch_bounds__(256) k_copy16(const uint4* __restrict__ src,
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
-// Read-only streaming pass (16-byte loads, four in flight per thread); the
-// xor of the words of each block goes to out[block] so that nothing is elided.
+// Read-only streaming pass: non-temporal 16-byte loads, four in flight per
+// thread; the xor of the words of each block goes to out[block % 8192] so that
+// nothing is elided.
 __global__ void __launch_bounds__(256) k_read16(const uint4* __restrict__ src, size_t n,
                                                 unsigned* __restrict__ out) {
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  const v4u* s = reinterpret_cast<const v4u*>(src);
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned acc = 0;
   for (; i + 3 * stride < n; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    const v4u a = __builtin_nontemporal_load(s + i), b = __builtin_nontemporal_load(s + i + stride),
+              c = __builtin_nontemporal_load(s + i + 2 * stride),
+              d = __builtin_nontemporal_load(s + i + 3 * stride);
     acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
   }
   for (; i < n; i += stride) {
-    const uint4 a = src[i];
+    const v4u a = __builtin_nontemporal_load(s + i);
     acc ^= a.x ^ a.y ^ a.z ^ a.w;
   }
   for (int off = 32; off >= 1; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) atomicXor(out + blockIdx.x, acc);
+  if ((threadIdx.x & 63) == 0) atomicXor(out + (blockIdx.x & 8191), acc);
 }
 
 hipError_t launch_read(const void* src, size_t bytes, unsigned* out, hipStream_t s) {
   const size_t n = bytes / 16;
-  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 32);
+  const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
   hipLaunchKernelGGL(k_read16, dim3(grid > 0 ? grid : 1), dim3(256), 0, s, (const uint4*)src, n,
                      out);
   return hipGetLastError();
