@@ -9,8 +9,9 @@ includes packing b, every inner iteration and reliable update, and unpacking x.
 
 Reported beside it (same run):
   * the same solve in plain FP64 (time-to-solution, mixed vs FP64);
-  * the dominant kernel (the FP32 half-Dslash) timed alone with HIP events on
-    its stream, against the HBM roofline;
+  * the dominant kernel (the FP32 half-Dslash) timed alone, launches replayed
+    from a HIP graph between HIP events on their stream, against the HBM
+    roofline;
   * the half-Dslash on 32^4 (the size where links no longer fit the 256 MB
     Infinity Cache) in FP32-12 and FP64-18, one and twelve sources;
   * the measured bandwidth of a plain copy kernel;
@@ -78,7 +79,7 @@ def dominant_kernel(torch, qx, lat, g32, bd, reps):
     """The FP32 12-real half-Dslash on the workload lattice, timed alone."""
     p32 = qx.pack(lat, bd, "f32")
     o32 = qx.dslash(g32, p32, 0, 1)
-    t_k = time_kernel(torch, lambda: qx.dslash(g32, p32, 0, 1, out=o32), reps)
+    t_k = qx.time_dslash(g32, p32, 0, 1, out=o32, reps=reps)
     achieved = BYTES_SITE_F32_12 * lat.hv / t_k / 1e9
     log(f"dominant kernel (FP32-12 half-Dslash, {lat.dims}): {t_k * 1e6:.2f} us, "
         f"{achieved:.0f} GB/s algorithmic, {FLOPS_SITE * lat.hv / t_k / 1e9:.0f} GFLOP/s")
@@ -243,7 +244,7 @@ def main():
             src = torch.from_numpy(synth.gauss_source(nrhs, lat32.hv, 2)).cuda()
             pin = qx.pack(lat32, src, prec)
             pout = qx.dslash(g, pin, 0, nrhs)
-            t = time_kernel(torch, lambda: qx.dslash(g, pin, 0, nrhs, out=pout), 50)
+            t = qx.time_dslash(g, pin, 0, nrhs, out=pout, reps=50)
             by = (link_b + 2 * vec_b * nrhs) * lat32.hv
             d32[f"{prec}-{recon}-nrhs{nrhs}"] = {
                 "us": round(t * 1e6, 2),
@@ -268,7 +269,7 @@ def main():
         src = torch.from_numpy(synth.gauss_source(1, lat48.hv, 3)).cuda()
         pin = qx.pack(lat48, src, prec)
         pout = qx.dslash(g, pin, 0, 1)
-        t = time_kernel(torch, lambda: qx.dslash(g, pin, 0, 1, out=pout), 30)
+        t = qx.time_dslash(g, pin, 0, 1, out=pout, reps=30)
         by = (link_b + 2 * vec_b) * lat48.hv
         d32[f"48^4-{prec}-{recon}-nrhs1"] = {
             "us": round(t * 1e6, 2),

@@ -93,7 +93,7 @@ typedef struct qx_batch qx_batch_t;
 /* engines of the CG iteration */
 enum {
   QX_ENGINE_AUTO = 0,      /* the default engine (currently QX_ENGINE_LAUNCH) */
-  QX_ENGINE_LAUNCH = 1,    /* five kernel launches per iteration (graph-captured in batches) */
+  QX_ENGINE_LAUNCH = 1,    /* six kernel launches per iteration (graph-captured in batches) */
   QX_ENGINE_PERSISTENT = 2 /* one cooperative launch runs many iterations with grid barriers;
                               same results bit for bit, but slower on MI355X, where every
                               barrier costs each block an agent-scope release (L2 writeback) */
@@ -276,7 +276,8 @@ int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_
 /* ------------------------------------------------------------- tuning */
 
 /* Pick the launch shape of the stencil kernels for this gauge handle and nrhs
-   sources by timing every candidate on the stream.  A stencil block covers 64
+   sources by timing every candidate (20 launches replayed from a HIP graph on
+   a private stream that waits for `stream`).  A stencil block covers 64
    sites with lps * groups wavefronts: lps (1, 2, 4, 8) wavefronts share the
    eight hops of each site (more loads in flight on small lattices), and each
    of the groups = ceil(nrhs / nbt) takes nbt (1, 2, 4) sources, every link
@@ -288,6 +289,15 @@ int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_
    precision, link storage, nrhs) in the process and in the JSON file named by
    QX_TUNE_CACHE if set.  Synchronises the stream. */
 int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream);
+
+/* Average device time, in ms, of one half-Dslash launch (as qx_dslash, with
+   the handle's launch shape for nrhs): `reps` (1..10000) launches are captured
+   into a HIP graph on a private stream that first waits for `stream`; the graph
+   is replayed once untimed and once between two HIP events on that stream, so
+   the figure holds kernel time and the dispatch gaps between dependent
+   kernels, not the host's launch rate.  Writes `out`; synchronises. */
+int qx_time_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const void* in, void* out,
+                   int reps, double* avg_ms, hipStream_t stream);
 
 /* Launch shape currently used for (handle, nrhs). */
 int qx_get_launch(const qx_gauge_t* g, int nrhs, int* nbt, int* lps, int* xcd_order);

@@ -100,6 +100,7 @@ def load():
         "qx_force": ([_P, _P, _P, _I, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P, _P], _I),
         "qx_force_su3": ([_P, _P, _P, _P, _P], _I),
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
+        "qx_time_dslash": ([_P, _I, _I, _P, _P, _I, _P, _P], _I),
         "qx_get_launch": ([_P, _I, _P, _P, _P], _I),
         "qx_set_launch": ([_P, _I, _I, _I, _I], _I),
         "qx_probe_copy": ([_P, _P, _SZ, _P], _I),
@@ -258,6 +259,18 @@ def dslash(g: Gauge, packed_in, out_parity: int, nrhs: int = 1, out=None, stream
         out = _bytes(g.lat.field_bytes(nrhs, g.prec))
     _check(load().qx_dslash(g._h, out_parity, nrhs, _ptr(packed_in), _ptr(out), _stream(stream)))
     return out
+
+
+def time_dslash(g: Gauge, packed_in, out_parity: int, nrhs: int = 1, out=None, reps: int = 100,
+                stream=None) -> float:
+    """Average device seconds of one half-Dslash launch, from `reps` launches
+    replayed out of a HIP graph between two HIP events."""
+    if out is None:
+        out = _bytes(g.lat.field_bytes(nrhs, g.prec))
+    ms = ctypes.c_double()
+    _check(load().qx_time_dslash(g._h, out_parity, nrhs, _ptr(packed_in), _ptr(out), reps,
+                                 ctypes.byref(ms), _stream(stream)))
+    return ms.value * 1e-3
 
 
 def apply_A(g: Gauge, packed_in, masses: Sequence[float], out=None, tmp=None, stream=None):

@@ -906,6 +906,55 @@ extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, in
   return QX_OK;
 }
 
+namespace {
+
+// Average device time (ms) of one of `reps` back-to-back launches made by
+// enqueue(stream, r).  The launches are captured into a HIP graph on a private
+// stream, which first waits for the caller's stream, and the graph is replayed
+// once untimed and once between two HIP events on that stream: the host's
+// launch rate does not enter the figure, only each kernel and the dispatch gap
+// between dependent kernels, as inside a solver graph.
+template <typename F>
+int time_launches(const char* what, hipStream_t caller, int reps, F&& enqueue, float* ms_out) {
+  hipStream_t ps = nullptr;
+  hipEvent_t dep = nullptr, e0 = nullptr, e1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&dep);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipEventRecord(dep, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ps, dep, 0);
+  if (e == hipSuccess) e = hipStreamBeginCapture(ps, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t el = hipSuccess;
+    for (int r = 0; r < reps && el == hipSuccess; ++r) el = enqueue(ps, r);
+    e = hipStreamEndCapture(ps, &graph);
+    if (e == hipSuccess) e = el;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, ps);
+  if (e == hipSuccess) e = hipEventRecord(e0, ps);
+  if (e == hipSuccess) e = hipGraphLaunch(exec, ps);
+  if (e == hipSuccess) e = hipEventRecord(e1, ps);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (ps) hipStreamSynchronize(ps);
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (e1) hipEventDestroy(e1);
+  if (e0) hipEventDestroy(e0);
+  if (dep) hipEventDestroy(dep);
+  if (ps) hipStreamDestroy(ps);
+  if (e != hipSuccess) return hip_fail(e, what);
+  *ms_out = ms / reps;
+  return QX_OK;
+}
+
+}  // namespace
+
 extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream) {
   if (!g || nrhs < 1 || !scratch) return fail(QX_EINVAL, "qx_tune_dslash: bad argument");
   const Geo& geo = g->geo;
@@ -913,34 +962,23 @@ extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipS
   char* in = (char*)scratch;
   char* out = in + fb;
   QX_HIP(hipMemsetAsync(in, 0, fb, stream), "qx_tune_dslash: clear");
-  hipEvent_t e0, e1;
-  QX_HIP(hipEventCreate(&e0), "qx_tune_dslash: event");
-  QX_HIP(hipEventCreate(&e1), "qx_tune_dslash: event");
   LaunchShape best{};
   float best_ms = 1e30f;
   const int nbts[3] = {1, 2, 4}, lpss[4] = {1, 2, 4, 8};
-  int rc = QX_OK;
   for (int nbt : nbts) {
     if (nbt > 1 && nbt > nrhs) continue;
     for (int lps : lpss) {
-      for (int x = 0; x < 2 && rc == QX_OK; ++x) {
+      for (int x = 0; x < 2; ++x) {
         const LaunchShape sh{nbt, lps, x};
         if (!nbt_lps_instantiated(nbt, lps) || !shape_ok(sh, nrhs, cplx_bytes(g->prec))) continue;
-        hipError_t e = hipSuccess;
-        for (int w = 0; w < 3 && e == hipSuccess; ++w)
-          e = launch_dslash(geo, g->prec, g->recon, g->packed, w & 1, in, out, nrhs, 0.5, sh, stream);
-        if (e == hipSuccess) e = hipEventRecord(e0, stream);
-        const int reps = 20;
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-          e = launch_dslash(geo, g->prec, g->recon, g->packed, r & 1, in, out, nrhs, 0.5, sh, stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-          rc = hip_fail(e, "qx_tune_dslash: timing");
-          break;
-        }
+        const int rc = time_launches("qx_tune_dslash: timing", stream, 20,
+                                     [&](hipStream_t s, int r) {
+                                       return launch_dslash(geo, g->prec, g->recon, g->packed,
+                                                            r & 1, in, out, nrhs, 0.5, sh, s);
+                                     },
+                                     &ms);
+        if (rc) return rc;
         if (ms < best_ms) {
           best_ms = ms;
           best = sh;
@@ -948,13 +986,29 @@ extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipS
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (rc) return rc;
   const_cast<qx_gauge*>(g)->shapes[nrhs] = best;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   g_tune[tune_key(g, nrhs)] = best;
   tune_save_locked();
+  return QX_OK;
+}
+
+extern "C" int qx_time_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const void* in,
+                              void* out, int reps, double* avg_ms, hipStream_t stream) {
+  if (!g || !in || !out || !avg_ms || nrhs < 1 || reps < 1 || reps > 10000 ||
+      (out_parity != 0 && out_parity != 1))
+    return fail(QX_EINVAL, "qx_time_dslash: bad argument");
+  if (in == out) return fail(QX_EINVAL, "qx_time_dslash: in and out must not alias");
+  const LaunchShape sh = shape_for(g, nrhs);
+  float ms = 0.f;
+  const int rc = time_launches("qx_time_dslash", stream, reps,
+                               [&](hipStream_t s, int) {
+                                 return launch_dslash(g->geo, g->prec, g->recon, g->packed,
+                                                      out_parity, in, out, nrhs, 0.5, sh, s);
+                               },
+                               &ms);
+  if (rc) return rc;
+  *avg_ms = ms;
   return QX_OK;
 }

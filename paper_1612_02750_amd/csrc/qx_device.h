@@ -124,30 +124,39 @@ __device__ __forceinline__ int logical_block(int xcd_order) {
 
 // ------------------------------------------------------------------- links
 
-// Non-temporal load of one complex number.  Links are read once per
-// half-Dslash; when they cannot stay in the Infinity Cache anyway they stream
-// past the caches, which then keep the colour vectors (each read by eight
-// neighbouring sites).
-template <typename R>
-__device__ __forceinline__ cplx<R> ld_stream(const cplx<R>* p) {
-  typedef R v2 __attribute__((ext_vector_type(2)));
-  const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
-  return {t.x, t.y};
+// Element idx of an array whose base is the same across the wavefront.  The
+// byte offset is formed in 32 bits (arrays here hold fewer than 2^28
+// elements), so the load takes the scalar-base + 32-bit-lane-offset form and
+// costs one VGPR of address instead of a 64-bit pointer per element.  NT: a
+// non-temporal load, which streams past the caches.
+template <bool NT, typename R>
+__device__ __forceinline__ cplx<R> ld_cplx(const cplx<R>* __restrict__ base, unsigned idx) {
+  const cplx<R>* p =
+      reinterpret_cast<const cplx<R>*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(cplx<R>));
+  if constexpr (NT) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return {t.x, t.y};
+  } else {
+    return *p;
+  }
 }
 
+// Wave index of the calling thread, as a scalar.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // Packed links: [parity][mu][element][cb], element e = 3 * row + column, E = 9
-// (18 reals) or 6 (12 reals: rows 0 and 1).  p points at element 0 of one link.
-template <typename R, int RECON>
-__device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<R>* __restrict__ p, size_t hv,
-                                          int sign, bool stream) {
+// (18 reals) or 6 (12 reals: rows 0 and 1).  base points at element 0 of
+// direction mu of one parity; idx is the checkerboard index of the link.
+// Links are read once per half-Dslash: when they cannot stay in the Infinity
+// Cache anyway they are loaded non-temporally (NT), so that the caches keep
+// the colour vectors, each read by eight neighbouring sites.
+template <typename R, int RECON, bool NT>
+__device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<R>* __restrict__ base,
+                                          unsigned idx, size_t hv, int sign) {
   constexpr int E = RECON == 12 ? 6 : 9;
-  if (stream) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = ld_stream(p + e * hv);
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) u[e] = p[e * hv];
-  }
+  for (int e = 0; e < E; ++e) u[e] = ld_cplx<NT>(base + e * hv, idx);
   if constexpr (RECON == 12) {
     // For W = s U with U in SU(3), s = +-1: row2(W) = s * conj(row0(W) x row1(W)).
     const R s = (R)sign;
@@ -178,12 +187,12 @@ struct FieldIn {
   const cplx<R>* __restrict__ p;  // first source of the thread
   size_t ss, hv;                  // source stride (3 hv), colour stride (hv)
   __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
-    return p[j * ss + c * hv + site];
+    return ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
   }
 };
 
 // acc[j] += hop H applied to in_j, j < NBT (bit j of act).
-template <int H, typename R, int RECON, int NBT, typename In>
+template <int H, typename R, int RECON, int NBT, bool NT, typename In>
 __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restrict__ lf,
                                             const cplx<R>* __restrict__ lb, int cb, const Site& s,
                                             const In& in, unsigned act, cplx<R> (&acc)[NBT][3]) {
@@ -202,8 +211,8 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
   }
   const int nb = s.template nbr<H>();
   cplx<R> u[9];
-  load_link<R, RECON>(u, (fwd ? lf + (size_t)mu * E * hv + cb : lb + (size_t)mu * E * hv + nb), hv,
-                      sign, g.stream_links != 0);
+  load_link<R, RECON, NT>(u, (fwd ? lf : lb) + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv,
+                          sign);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     if (!(act >> j & 1u)) continue;
@@ -228,16 +237,13 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
 
 // acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT (bit j of act).
 // Each hop is its own instantiation, guarded by a wavefront-uniform test.
-template <typename R, int RECON, int NBT, int LPS, typename In>
-__device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __restrict__ links,
-                                             int pout, int cb, const Site& s, int dp, const In& in,
-                                             unsigned act, cplx<R> (&acc)[NBT][3]) {
-  constexpr int E = RECON == 12 ? 6 : 9;
-  const size_t hv = (size_t)g.hv;
-  const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
-  const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
+template <typename R, int RECON, int NBT, int LPS, bool NT, typename In>
+__device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<R>* __restrict__ lf,
+                                             const cplx<R>* __restrict__ lb, int cb, const Site& s,
+                                             int dp, const In& in, unsigned act,
+                                             cplx<R> (&acc)[NBT][3]) {
 #define QX_HOP(H) \
-  if (LPS == 1 || (H) % LPS == dp) stencil_hop<H, R, RECON, NBT>(g, lf, lb, cb, s, in, act, acc)
+  if (LPS == 1 || (H) % LPS == dp) stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, cb, s, in, act, acc)
   QX_HOP(0);
   QX_HOP(1);
   QX_HOP(2);
@@ -247,6 +253,22 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __rest
   QX_HOP(6);
   QX_HOP(7);
 #undef QX_HOP
+}
+
+// The same for the links of output parity pout; whether the links stream past
+// the caches is decided once per launch (Geo::stream_links).
+template <typename R, int RECON, int NBT, int LPS, typename In>
+__device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __restrict__ links,
+                                             int pout, int cb, const Site& s, int dp, const In& in,
+                                             unsigned act, cplx<R> (&acc)[NBT][3]) {
+  constexpr int E = RECON == 12 ? 6 : 9;
+  const size_t hv = (size_t)g.hv;
+  const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
+  const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
+  if (g.stream_links)
+    stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, cb, s, dp, in, act, acc);
+  else
+    stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, cb, s, dp, in, act, acc);
 }
 
 template <typename R, int NBT>

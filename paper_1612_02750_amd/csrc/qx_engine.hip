@@ -99,8 +99,8 @@ struct SumIn {
   const cplx<Rlo>* __restrict__ lo;
   size_t ss, hv;
   __device__ __forceinline__ cplx<double> operator()(int j, int c, int site) const {
-    const cplx<double> a = hi[j * ss + c * hv + site];
-    const cplx<Rlo> b = lo[j * ss + c * hv + site];
+    const cplx<double> a = ld_cplx<false>(hi + j * ss + c * hv, (unsigned)site);
+    const cplx<Rlo> b = ld_cplx<false>(lo + j * ss + c * hv, (unsigned)site);
     return {a.re + (double)b.re, a.im + (double)b.im};
   }
 };
@@ -297,7 +297,7 @@ template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
+  const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
   const unsigned long long run = phase_bits<FRESH>(q0, d.nsrc, PH_RUN);
@@ -326,7 +326,7 @@ template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b, double* sh, double* tot) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, dp = w % LPS, grp = w / LPS;
+  const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
   const unsigned long long run = phase_bits<FRESH>(q0, d.nsrc, PH_RUN);
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
 template <typename Rlo, int RECON, int NBT>
 __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
     k_ru_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd) {
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, grp = wave_id();
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const unsigned long long ru = phase_bits<false>(st + d.src0, d.nsrc, PH_RU);
@@ -565,7 +565,7 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
     k_ru_residual(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, grp = wave_id();
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;

@@ -121,6 +121,30 @@ def test_dslash_launch_shapes(qx, nbt, lps, prec, recon, tol):
         assert rel(out[k], ref) <= tol, (k, nbt, lps)
 
 
+@pytest.mark.parametrize("prec,recon,tol", [("f64", 18, 1e-13), ("f32", 12, 1e-5)])
+def test_tuner_and_graph_timer(qx, prec, recon, tol):
+    """The autotuner settles on a compiled shape, and the graph-replayed timer
+    writes the same half-Dslash as qx_dslash (checked against the oracle) and
+    returns a positive time."""
+    dims = (8, 8, 8, 12)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    U = gauge(dims, seed=9)
+    g = qx.Gauge(lat, to_dev(U), prec, recon)
+    for nrhs in (1, 3):
+        nbt, lps, xcd = g.tune(nrhs)
+        assert (nbt, lps) in SHAPES_NL and xcd in (0, 1)
+        chi = synth.gauss_source(nrhs, lat.hv, 10 + nrhs)
+        pin = qx.pack(lat, to_dev(chi), prec)
+        out = qx.dslash(g, pin, 1, nrhs)
+        out.zero_()
+        t = qx.time_dslash(g, pin, 1, nrhs, out=out, reps=5)
+        assert 0.0 < t < 1.0
+        got = to_host(qx.unpack(lat, out, nrhs, prec))
+        for k in range(nrhs):
+            ref = oracle.dslash_eo(dims, U, chi[k], 1, oracle.BC_T_ANTIPERIODIC)
+            assert rel(got[k], ref) <= tol, (k, nrhs)
+
+
 @pytest.mark.parametrize("nbt,lps", SHAPES_NL)
 def test_cg_launch_shapes(qx, nbt, lps):
     """The CG engine under every launch shape: 3 sources of different masses."""
