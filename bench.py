@@ -25,6 +25,7 @@ costs 606 V (two half-Dslash + BLAS-1), one reliable update 570 V + 12 V.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -74,11 +75,33 @@ def time_kernel(torch, fn, reps):
 
 BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colour vector
 
+# HBM-side bytes per launch of the dominant kernel from two rocprofv3 counter
+# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
+# counters read for the library's copy kernel on 1 GiB (FETCH x 2.000, WRITE
+# x 1.000).  Reported only while the kernel sources and the launch shape are
+# the ones the counters were taken with.
+TRAFFIC = None
+KERNEL_SOURCES = ("qx_dslash.hip", "qx_device.h", "qx_internal.h", "qx_launch.h", "qx_dispatch.h")
 
-def dominant_kernel(torch, qx, lat, g32, bd, reps):
-    """The FP32 12-real half-Dslash on the workload lattice, timed alone."""
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1612_02750_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def dominant_kernel(torch, qx, lat, g32, bd, reps, plain=False):
+    """The FP32 12-real half-Dslash on the workload lattice, timed alone
+    (plain=True: a few ordinary launches for a counter run, not timed)."""
     p32 = qx.pack(lat, bd, "f32")
     o32 = qx.dslash(g32, p32, 0, 1)
+    if plain:
+        for _ in range(reps):
+            qx.dslash(g32, p32, 0, 1, out=o32)
+        torch.cuda.synchronize()
+        return None, None
     t_k = qx.time_dslash(g32, p32, 0, 1, out=o32, reps=reps)
     achieved = BYTES_SITE_F32_12 * lat.hv / t_k / 1e9
     log(f"dominant kernel (FP32-12 half-Dslash, {lat.dims}): {t_k * 1e6:.2f} us, "
@@ -86,10 +109,79 @@ def dominant_kernel(torch, qx, lat, g32, bd, reps):
     return t_k, achieved
 
 
-def copy_probe(torch, qx, nb=1 << 30):
+def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key, out):
+    from paper_1612_02750_amd import synth
+
+    src = torch.from_numpy(synth.gauss_source(nrhs, lat.hv, seed)).cuda()
+    pin = qx.pack(lat, src, g.prec)
+    pout = qx.dslash(g, pin, 0, nrhs)
+    if plain:
+        for _ in range(5):
+            qx.dslash(g, pin, 0, nrhs, out=pout)
+        torch.cuda.synchronize()
+        return
+    t = qx.time_dslash(g, pin, 0, nrhs, out=pout, reps=reps)
+    by = (link_b + 2 * vec_b * nrhs) * lat.hv
+    out[key] = {
+        "us": round(t * 1e6, 2),
+        "gflops": round(FLOPS_SITE * nrhs * lat.hv / t / 1e9, 1),
+        "gbs_algorithmic": round(by / t / 1e9, 1),
+        "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
+        "shape": list(g.launch(nrhs)),
+    }
+    log(f"{key}: {out[key]}")
+
+
+def dslash_sweep(torch, qx, tune=True, plain=False):
+    """Half-Dslash at 32^4 (Haar links; FP32 12-real links fit the 256 MB
+    Infinity Cache, FP64 18-real ones do not) with one and twelve sources, and
+    at 48^4 (every operand far beyond the cache) with one source.  Compulsory
+    bytes per output site: 8 links + one input and one output colour vector
+    per source.  tune=False keeps the shapes already known (the tuning cache
+    of an earlier run); plain=True only launches (for counter runs)."""
+    from paper_1612_02750_amd import synth
+
+    res = {}
+    variants = (("f32", 12, 384, 24), ("f64", 18, 1152, 48))
+    dims32 = (32, 32, 32, 32)
+    lat32 = qx.Lattice(dims32)
+    U32 = torch.from_numpy(synth.haar_gauge(dims32, 0)).cuda()
+    for prec, recon, link_b, vec_b in variants:
+        g = qx.Gauge(lat32, U32, prec, recon)
+        for nrhs in (1, 12):
+            if tune:
+                g.tune(nrhs)
+            _dslash_point(torch, qx, g, lat32, nrhs, 2, link_b, vec_b, 50, plain,
+                          f"32^4-{prec}-{recon}-nrhs{nrhs}", res)
+        del g
+    del U32
+    # link values do not change the traffic: a unit gauge field built on the device
+    dims48 = (48, 48, 48, 48)
+    lat48 = qx.Lattice(dims48)
+    U48 = torch.zeros((4, lat48.V, 3, 3), dtype=torch.complex128, device="cuda")
+    U48[..., 0, 0] = U48[..., 1, 1] = U48[..., 2, 2] = 1.0
+    for prec, recon, link_b, vec_b in variants:
+        g = qx.Gauge(lat48, U48, prec, recon)
+        if tune:
+            g.tune(1)
+        _dslash_point(torch, qx, g, lat48, 1, 3, link_b, vec_b, 30, plain,
+                      f"48^4-{prec}-{recon}-nrhs1", res)
+        del g
+    del U48
+    return res
+
+
+def copy_probe(torch, qx, nb=1 << 30, timed=True):
     """Plain copy of nb bytes: measured bandwidth (read + write) and counter calibration."""
     a = torch.zeros(nb, dtype=torch.uint8, device="cuda")
     c = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    if not timed:
+        scratch = torch.zeros(8192, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            qx.probe_copy(c, a, nb)
+            qx.probe_read(a, nb, scratch)
+        torch.cuda.synchronize()
+        return None, None
     t_copy = time_kernel(torch, lambda: qx.probe_copy(c, a, nb), 20)
     copy_gbs = 2 * nb / t_copy / 1e9
     scratch = torch.zeros(8192, dtype=torch.int32, device="cuda")
@@ -121,6 +213,15 @@ def multi_rhs(torch, qx, synth):
     st = mixed.solve()
     torch.cuda.synchronize()
     t_mx = time.perf_counter() - t0
+    x_b64 = torch.empty_like(bd)
+    batch64 = qx.Batch([(g64, None, bd, [m] * nsrc, x_b64)], tol=1e-10, mode=qx.CG_FP64)
+    batch64.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stb = batch64.solve()
+    torch.cuda.synchronize()
+    t_b64 = time.perf_counter() - t0
+    del batch64, x_b64
     x_64 = torch.empty_like(bd)
     plains = [qx.Batch([(g64, None, bd[k:k + 1], [m], x_64[k:k + 1])], tol=1e-10, mode=qx.CG_FP64)
               for k in range(nsrc)]
@@ -135,10 +236,13 @@ def multi_rhs(torch, qx, synth):
         "mixed_batch_12_ms": round(t_mx * 1e3, 2),
         "fp64_sequential_12_ms": round(t_64 * 1e3, 2),
         "speedup": round(t_64 / t_mx, 3),
+        "fp64_batch_12_ms": round(t_b64 * 1e3, 2),
+        "speedup_vs_fp64_batch": round(t_b64 / t_mx, 3),
         "mixed_iters_max": max(s.iters for s in st),
         "fp64_iters_max": max(s.iters for s in st64),
         "max_true_rel_residual": max(max(s.true_rel_residual for s in st),
-                                     max(s.true_rel_residual for s in st64)),
+                                     max(s.true_rel_residual for s in st64),
+                                     max(s.true_rel_residual for s in stb)),
         "launch_shape_f32_12src": list(shape12),
         "launch_shape_f64_1src": list(shape1),
     }
@@ -172,16 +276,17 @@ def main():
     bd = torch.from_numpy(b).cuda()
     g64 = qx.Gauge(lat, Ud, "f64", 18)
     g32 = qx.Gauge(lat, Ud, "f32", 12)
+    if args.kernels_only:
+        # counter runs: the kernels of the timed run with its launch shapes
+        # (read from the tuning cache that run wrote), a few plain launches each
+        dominant_kernel(torch, qx, lat, g32, bd, 10, plain=True)
+        dslash_sweep(torch, qx, tune=False, plain=True)
+        copy_probe(torch, qx, timed=False)
+        print(json.dumps({"kernels_only": True, "shape_f32_12_16^4": list(g32.launch(1))}))
+        return
     shape32 = g32.tune(1)
     shape64 = g64.tune(1)
     log(f"tuned launch shapes: f32-12 {shape32}, f64-18 {shape64}")
-    if args.kernels_only:
-        t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
-        copy_gbs, read_gbs = copy_probe(torch, qx)
-        print(json.dumps({"kernels_only": True, "dominant_us": round(t_k * 1e6, 3),
-                          "achieved_gbs": round(achieved, 1), "copy_probe_gbs": round(copy_gbs, 1),
-                          "read_probe_gbs": round(read_gbs, 1)}))
-        return
     x_mx = torch.empty_like(bd)
     x_64 = torch.empty_like(bd)
     mixed = qx.Batch([(g64, g32, bd, [m], x_mx)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
@@ -230,57 +335,13 @@ def main():
 
     # ---------------------------------------------- dominant kernel vs roofline
     t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
+    sha = kernel_sha()
+    traffic = None
+    if TRAFFIC and TRAFFIC["sha"] == sha and TRAFFIC["shape"] == list(shape32):
+        traffic = TRAFFIC["bytes"]
 
-    # --------------------------------------------------- 32^4 Dslash (HBM size)
-    d32 = {}
-    dims32 = (32, 32, 32, 32)
-    lat32 = qx.Lattice(dims32)
-    U32 = torch.from_numpy(synth.haar_gauge(dims32, 0)).cuda()
-    # compulsory bytes per output site: 8 links + one input and one output colour vector per source
-    for prec, recon, link_b, vec_b in (("f32", 12, 384, 24), ("f64", 18, 1152, 48)):
-        g = qx.Gauge(lat32, U32, prec, recon)
-        for nrhs in (1, 12):
-            g.tune(nrhs)
-            src = torch.from_numpy(synth.gauss_source(nrhs, lat32.hv, 2)).cuda()
-            pin = qx.pack(lat32, src, prec)
-            pout = qx.dslash(g, pin, 0, nrhs)
-            t = qx.time_dslash(g, pin, 0, nrhs, out=pout, reps=50)
-            by = (link_b + 2 * vec_b * nrhs) * lat32.hv
-            d32[f"{prec}-{recon}-nrhs{nrhs}"] = {
-                "us": round(t * 1e6, 2),
-                "gflops": round(FLOPS_SITE * nrhs * lat32.hv / t / 1e9, 1),
-                "gbs_algorithmic": round(by / t / 1e9, 1),
-                "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
-            }
-            log(f"32^4 {prec}-{recon} nrhs {nrhs}: {d32[f'{prec}-{recon}-nrhs{nrhs}']}")
-            del src, pin, pout
-        del g
-    del U32
-
-    # 48^4: every operand far beyond the 256 MB Infinity Cache (link values do
-    # not change the traffic, so a unit gauge field built on the device is used)
-    dims48 = (48, 48, 48, 48)
-    lat48 = qx.Lattice(dims48)
-    U48 = torch.zeros((4, lat48.V, 3, 3), dtype=torch.complex128, device="cuda")
-    U48[..., 0, 0] = U48[..., 1, 1] = U48[..., 2, 2] = 1.0
-    for prec, recon, link_b, vec_b in (("f32", 12, 384, 24), ("f64", 18, 1152, 48)):
-        g = qx.Gauge(lat48, U48, prec, recon)
-        g.tune(1)
-        src = torch.from_numpy(synth.gauss_source(1, lat48.hv, 3)).cuda()
-        pin = qx.pack(lat48, src, prec)
-        pout = qx.dslash(g, pin, 0, 1)
-        t = qx.time_dslash(g, pin, 0, 1, out=pout, reps=30)
-        by = (link_b + 2 * vec_b) * lat48.hv
-        d32[f"48^4-{prec}-{recon}-nrhs1"] = {
-            "us": round(t * 1e6, 2),
-            "gflops": round(FLOPS_SITE * lat48.hv / t / 1e9, 1),
-            "gbs_algorithmic": round(by / t / 1e9, 1),
-            "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
-            "shape": list(g.launch(1)),
-        }
-        log(f"48^4 {prec}-{recon}: {d32[f'48^4-{prec}-{recon}-nrhs1']}")
-        del g, src, pin, pout
-    del U48
+    # ------------------------------------------- 32^4 and 48^4 Dslash (HBM size)
+    d32 = dslash_sweep(torch, qx)
 
     copy_gbs, read_gbs = copy_probe(torch, qx)
 
@@ -336,14 +397,17 @@ def main():
                           "fp64": s_64.iters},
         "true_rel_residual": {"mixed": s_mx.true_rel_residual, "fp64": s_64.true_rel_residual},
         "roofline": {
-            "kernel": "k_dslash<float,12,1> (FP32 12-real half-Dslash, 16^4)",
+            "kernel": f"k_dslash<float, 12, {shape32[0]}, {shape32[1]}> (FP32 12-real half-Dslash, 16^4, "
+                      f"one source)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_us": round(t_k * 1e6, 3),
+            "launch_shape": list(shape32),
+            "kernel_src_sha": sha,
             "bytes_per_site": BYTES_SITE_F32_12,
             "sites_per_launch": hv,
         },

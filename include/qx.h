@@ -281,8 +281,11 @@ int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_
    sites with lps * groups wavefronts: lps (1, 2, 4, 8) wavefronts share the
    eight hops of each site (more loads in flight on small lattices), and each
    of the groups = ceil(nrhs / nbt) takes nbt (1, 2, 4) sources, every link
-   loaded once per wavefront and applied to all of its sources; xcd_order
-   gives each of the eight XCDs a contiguous range of sites.  scratch: two
+   loaded once per wavefront and applied to all of its sources.  xcd_order
+   is the block order: 0 as dispatched, 1 gives each of the eight XCDs a
+   contiguous range of sites, 2 and 3 do the same and walk the (z, t) planes
+   in tiles of 2 x 8 and 4 x 4 planes (when Lh * L1 is a multiple of 64),
+   which keeps the colour vectors of many sources in L2 between their uses.  scratch: two
    packed fields of nrhs sources of the handle's precision
    (2 * qx_field_bytes).  The result is used by every later call with this
    handle and nrhs (Dslash, A and the solvers) and cached per (lattice,

@@ -127,7 +127,7 @@ void tune_load_locked() {
     int nbt = 0, lps = 0, x = 0;
     if (sscanf(s.c_str() + j + 1, " : [ %d , %d , %d ]", &nbt, &lps, &x) == 3 &&
         nbt_lps_instantiated(nbt, lps))
-      g_tune[key] = LaunchShape{nbt, lps, x ? 1 : 0};
+      g_tune[key] = LaunchShape{nbt, lps, x < 0 ? 0 : x > 3 ? 3 : x};
     i = j + 1;
   }
 }
@@ -897,7 +897,7 @@ extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* nbt, int* lps, 
 extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, int xcd_order) {
   if (!g || nrhs < 1 || !nbt_lps_instantiated(nbt, lps))
     return fail(QX_EINVAL, "qx_set_launch: unsupported shape (nbt %d, lps %d)", nbt, lps);
-  const LaunchShape sh{nbt, lps, xcd_order ? 1 : 0};
+  const LaunchShape sh{nbt, lps, xcd_order};
   // the standalone operators split the sources into passes that fit a block;
   // a solver whose sources do not fit falls back to the default shape
   if (!shape_ok(sh, 1, cplx_bytes(g->prec)))
@@ -968,7 +968,7 @@ extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipS
   for (int nbt : nbts) {
     if (nbt > 1 && nbt > nrhs) continue;
     for (int lps : lpss) {
-      for (int x = 0; x < 2; ++x) {
+      for (int x = 0; x < 4; ++x) {
         const LaunchShape sh{nbt, lps, x};
         if (!nbt_lps_instantiated(nbt, lps) || !shape_ok(sh, nrhs, cplx_bytes(g->prec))) continue;
         float ms = 0.f;

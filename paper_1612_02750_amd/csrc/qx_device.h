@@ -122,6 +122,38 @@ __device__ __forceinline__ int logical_block(int xcd_order) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
 }
 
+// Largest divisor of L that is at most cap.
+__host__ __device__ __forceinline__ int divisor_upto(int L, int cap) {
+  int d = cap < L ? cap : L;
+  while (d > 1 && L % d) --d;
+  return d;
+}
+
+// Checkerboard block (64 sites) visited at position bl of a lattice's block
+// range.  Orders 0 and 1 visit blocks in checkerboard order.  Orders 2 and 3
+// walk the (z, t) planes in tiles of tz x tt planes (2 x 8 and 4 x 4, cut to
+// divisors of L2 and L3), z fastest inside a tile: the t neighbours of a site
+// are then visited a few planes apart instead of a whole t-slice apart, so
+// the colour vectors of many sources stay in an XCD's L2 between their eight
+// uses.  The tiling needs whole blocks per (z, t) plane (Lh * L1 a multiple
+// of 64) and falls back to checkerboard order otherwise.  A bijection of
+// [0, hv / 64) onto itself.
+__host__ __device__ __forceinline__ int tile_block(int bl, const Geo& g, int order) {
+  if (order < 2 || (g.s2 & 63)) return bl;
+  const int P = g.s2 >> 6;  // blocks per (z, t) plane
+  const int tz = divisor_upto(g.L2, order == 2 ? 2 : 4);
+  const int tt = divisor_upto(g.L3, order == 2 ? 8 : 4);
+  const int k = bl % P;
+  int r = bl / P;
+  const int zi = r % tz;
+  r /= tz;
+  const int ti = r % tt;
+  r /= tt;
+  const int nz = g.L2 / tz;
+  const int z = (r % nz) * tz + zi, t = (r / nz) * tt + ti;
+  return (z + g.L2 * t) * P + k;
+}
+
 // ------------------------------------------------------------------- links
 
 // Element idx of an array whose base is the same across the wavefront.  The

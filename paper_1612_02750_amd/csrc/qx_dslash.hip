@@ -21,7 +21,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const c
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id();
   const int dp = w % LPS, grp = w / LPS;
-  const int cb = logical_block(xcd) * kTile + lane;
+  const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
   const size_t hv = g.hv, ss = 3 * hv;
   const int k0 = grp * NBT;
   unsigned act = 0;
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_deo_axpy(Geo g, const
                                                    cplx<R>* __restrict__ out, int nsrc, Masses16 m,
                                                    int xcd) {
   const int lane = threadIdx.x & 63, grp = wave_id();
-  const int cb = logical_block(xcd) * kTile + lane;
+  const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
   const size_t hv = g.hv, ss = 3 * hv;
   const int k0 = grp * NBT;
   unsigned act = 0;

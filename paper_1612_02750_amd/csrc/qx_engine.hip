@@ -295,14 +295,14 @@ __global__ void __launch_bounds__(1024) k_finalize(const SysDesc* __restrict__ s
 // E1: t = 2 D_oe p for running sources.
 template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int nsys,
-                                         const SrcState* st, int b) {
+                                         const SrcState* st, int b, int order) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
   const unsigned long long run = phase_bits<FRESH>(q0, d.nsrc, PH_RUN);
   if (!run) return;
-  const int cb = (b - d.blk0) * kTile + lane;
+  const int cb = tile_block(b - d.blk0, d.g, order) * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
   const int k0 = grp * NBT;
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
@@ -324,14 +324,15 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
 // E2: Ap = m^2 p - 1/4 (2D_eo) t and the partials of Re<p, Ap>.
 template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
-                                         const SrcState* st, int b, double* sh, double* tot) {
+                                         const SrcState* st, int b, int order, double* sh,
+                                         double* tot) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
   const unsigned long long run = phase_bits<FRESH>(q0, d.nsrc, PH_RUN);
   if (!run) return;
-  const int bl = b - d.blk0, cb = bl * kTile + lane;
+  const int bl = tile_block(b - d.blk0, d.g, order), cb = bl * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
   const int k0 = grp * NBT;
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
@@ -423,7 +424,7 @@ template <typename R, int RECON, int NBT, int LPS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDesc* __restrict__ sys,
                                                                     int nsys, const SrcState* st,
                                                                     int xcd) {
-  doe_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd));
+  doe_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), xcd);
 }
 
 template <typename R, int RECON, int NBT, int LPS>
@@ -432,7 +433,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDes
                                                                     int xcd) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), sh, tot);
+  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), xcd, sh, tot);
 }
 
 template <typename R>
@@ -509,10 +510,10 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     for (int b = blockIdx.x; b < nvblk_total; b += gridDim.x) p_tile<R, true>(sys, nsys, st, b);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
-      doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b);
+      doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
-      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, sh, tot);
+      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0, sh, tot);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int g = blockIdx.x; g < nsrc_total; g += gridDim.x)
       finalize_one<true>(sys, nsys, st, g, FIN_ALPHA, sh);
@@ -536,7 +537,7 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const unsigned long long ru = phase_bits<false>(st + d.src0, d.nsrc, PH_RU);
-  const int cb = (b - d.blk0) * kTile + lane;
+  const int cb = tile_block(b - d.blk0, d.g, xcd) * kTile + lane;
   const int k0 = grp * NBT;
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(ru, k0) : 0u;
   if (!act) return;
@@ -571,7 +572,7 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
   const SrcState* q0 = st + d.src0;
   const unsigned long long ru = phase_bits<false>(q0, d.nsrc, PH_RU);
   if (!ru) return;
-  const int bl = b - d.blk0, cb = bl * kTile + lane;
+  const int bl = tile_block(b - d.blk0, d.g, xcd), cb = bl * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
   const int k0 = grp * NBT;
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(ru, k0) : 0u;

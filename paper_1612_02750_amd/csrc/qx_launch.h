@@ -11,7 +11,8 @@ namespace qx {
 struct LaunchShape {
   int nbt = 1;  // sources per thread: 1, 2 or 4
   int lps = 1;  // wavefronts per site: 1, 2, 4 or 8
-  int xcd = 1;  // XCD-contiguous block order
+  int xcd = 1;  // block order: 0 as dispatched, 1 XCD-contiguous, 2 and 3 XCD-contiguous
+                // with (z, t)-tiled traversal (tile_block)
 };
 
 inline int shape_groups(const LaunchShape& s, int nsrc) { return (nsrc + s.nbt - 1) / s.nbt; }
@@ -27,7 +28,7 @@ inline int max_waves(int nbt, size_t cplx_sz) { return (cplx_sz / 2) * nbt > 8 ?
 inline bool shape_ok(const LaunchShape& s, int nsrc, size_t cplx_sz) {
   const bool nbt_ok = s.nbt == 1 || s.nbt == 2 || s.nbt == 4;
   const bool lps_ok = s.lps == 1 || s.lps == 2 || s.lps == 4 || s.lps == 8;
-  if (!nbt_ok || !lps_ok || nsrc < 1) return false;
+  if (!nbt_ok || !lps_ok || s.xcd < 0 || s.xcd > 3 || nsrc < 1) return false;
   const int waves = s.lps * shape_groups(s, nsrc);
   return waves <= max_waves(s.nbt, cplx_sz) && shape_lds(s, nsrc, cplx_sz) <= 64 * 1024;
 }

@@ -121,6 +121,48 @@ def test_dslash_launch_shapes(qx, nbt, lps, prec, recon, tol):
         assert rel(out[k], ref) <= tol, (k, nbt, lps)
 
 
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+@pytest.mark.parametrize("dims", [(8, 16, 4, 8), (16, 16, 6, 12)])
+def test_dslash_block_orders(qx, order, dims):
+    """Every block order, on lattices whose (z, t) planes hold whole 64-site
+    blocks so that the tiled orders 2 and 3 are in effect (tiles cut to the
+    divisors 2/3 of L2 = 6 and 6/4 of L3 = 12 on the second lattice)."""
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    U = gauge(dims, seed=12)
+    nrhs = 3
+    chi = synth.gauss_source(nrhs, lat.hv, 13)
+    refs = [oracle.dslash_eo(dims, U, chi[k], 0, oracle.BC_T_ANTIPERIODIC) for k in range(nrhs)]
+    for prec, recon, tol in (("f64", 18, 1e-13), ("f32", 12, 1e-5)):
+        g = qx.Gauge(lat, to_dev(U), prec, recon)
+        for nbt, lps in ((1, 1), (1, 4), (2, 2), (4, 1)):
+            g.set_launch(nrhs, nbt, lps, order)
+            out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), 0, nrhs),
+                                    nrhs, prec))
+            for k in range(nrhs):
+                assert rel(out[k], refs[k]) <= tol, (prec, nbt, lps, order, k)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+def test_cg_tiled_block_order(qx, order):
+    """The CG engine (stencil passes, reliable updates and the per-block
+    partials of the dot products) under a tiled block order."""
+    dims = (8, 16, 4, 8)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=14)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    g32.set_launch(2, 1, 4, order)
+    masses = [0.1, 0.2]
+    b = synth.gauss_source(2, lat.hv, 15)
+    x, st = qx.cg(g64, to_dev(b), masses, glo=g32, tol=1e-10)
+    _check_solution(dims, U, masses, b, to_host(x), st)
+    g32.set_launch(2, 1, 4, 1)
+    x1, _ = qx.cg(g64, to_dev(b), masses, glo=g32, tol=1e-10)
+    # the partials sit at the blocks' checkerboard positions: same sums, same bits
+    assert np.array_equal(to_host(x), to_host(x1))
+
+
 @pytest.mark.parametrize("prec,recon,tol", [("f64", 18, 1e-13), ("f32", 12, 1e-5)])
 def test_tuner_and_graph_timer(qx, prec, recon, tol):
     """The autotuner settles on a compiled shape, and the graph-replayed timer
@@ -132,7 +174,7 @@ def test_tuner_and_graph_timer(qx, prec, recon, tol):
     g = qx.Gauge(lat, to_dev(U), prec, recon)
     for nrhs in (1, 3):
         nbt, lps, xcd = g.tune(nrhs)
-        assert (nbt, lps) in SHAPES_NL and xcd in (0, 1)
+        assert (nbt, lps) in SHAPES_NL and xcd in (0, 1, 2, 3)
         chi = synth.gauss_source(nrhs, lat.hv, 10 + nrhs)
         pin = qx.pack(lat, to_dev(chi), prec)
         out = qx.dslash(g, pin, 1, nrhs)
