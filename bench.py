@@ -80,7 +80,29 @@ BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colou
 # counters read for the library's copy kernel on 1 GiB (FETCH x 2.000, WRITE
 # x 1.000).  Reported only while the kernel sources and the launch shape are
 # the ones the counters were taken with.
-TRAFFIC = None
+# From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
+# launch shape "nbt,lps,order".
+TRAFFIC = {
+    "sha": "2337cf40a5ac0bc1",
+    "bytes": {
+        "1,1,0": 16658432,
+        "1,1,1": 15084544,
+        "1,1,2": 14887936,
+        "1,1,3": 14887936,
+        "1,2,0": 16677888,
+        "1,2,1": 15105024,
+        "1,2,2": 14908416,
+        "1,2,3": 14908416,
+        "1,4,0": 16669696,
+        "1,4,1": 15096832,
+        "1,4,2": 14900224,
+        "1,4,3": 14900224,
+        "1,8,0": 16678912,
+        "1,8,1": 15106048,
+        "1,8,2": 14909440,
+        "1,8,3": 14909440
+    },
+}
 KERNEL_SOURCES = ("qx_dslash.hip", "qx_device.h", "qx_internal.h", "qx_launch.h", "qx_dispatch.h")
 
 
@@ -279,10 +301,18 @@ def main():
     if args.kernels_only:
         # counter runs: the kernels of the timed run with its launch shapes
         # (read from the tuning cache that run wrote), a few plain launches each
-        dominant_kernel(torch, qx, lat, g32, bd, 10, plain=True)
+        # the dominant kernel under every one-source launch shape, three
+        # dispatches each in this order (the counter summaries map dispatches
+        # to shapes by their order)
+        order = []
+        for lps in (1, 2, 4, 8):
+            for xo in (0, 1, 2, 3):
+                g32.set_launch(1, 1, lps, xo)
+                dominant_kernel(torch, qx, lat, g32, bd, 3, plain=True)
+                order.append([1, lps, xo])
         dslash_sweep(torch, qx, tune=False, plain=True)
         copy_probe(torch, qx, timed=False)
-        print(json.dumps({"kernels_only": True, "shape_f32_12_16^4": list(g32.launch(1))}))
+        print(json.dumps({"kernels_only": True, "dominant_shapes_in_order": order}))
         return
     shape32 = g32.tune(1)
     shape64 = g64.tune(1)
@@ -337,8 +367,8 @@ def main():
     t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
     sha = kernel_sha()
     traffic = None
-    if TRAFFIC and TRAFFIC["sha"] == sha and TRAFFIC["shape"] == list(shape32):
-        traffic = TRAFFIC["bytes"]
+    if TRAFFIC and TRAFFIC["sha"] == sha:
+        traffic = TRAFFIC["bytes"].get(",".join(str(v) for v in shape32))
 
     # ------------------------------------------- 32^4 and 48^4 Dslash (HBM size)
     d32 = dslash_sweep(torch, qx)
