@@ -92,11 +92,17 @@ typedef struct qx_batch qx_batch_t;
 
 /* engines of the CG iteration */
 enum {
-  QX_ENGINE_AUTO = 0,      /* the default engine (currently QX_ENGINE_LAUNCH) */
-  QX_ENGINE_LAUNCH = 1,    /* six kernel launches per iteration (graph-captured in batches) */
-  QX_ENGINE_PERSISTENT = 2 /* one cooperative launch runs many iterations with grid barriers;
-                              same results bit for bit, but slower on MI355X, where every
-                              barrier costs each block an agent-scope release (L2 writeback) */
+  QX_ENGINE_AUTO = 0,       /* QX_ENGINE_FUSED when every system of the batch has at most
+                               1024 stencil blocks (V/2 <= 65536), else QX_ENGINE_LAUNCH */
+  QX_ENGINE_LAUNCH = 1,     /* six kernel launches per iteration, five per reliable update
+                               (graph-captured in chunks) */
+  QX_ENGINE_PERSISTENT = 2, /* one cooperative launch runs many iterations with grid barriers;
+                               slower on MI355X, where every barrier costs each block an
+                               agent-scope release (L2 writeback) */
+  QX_ENGINE_FUSED = 3       /* four launches per iteration, three per reliable update: the
+                               reductions are finished redundantly by every block of the
+                               next vector pass (cheap while partials per source are few) */
+  /* all engines give the same results bit for bit */
 };
 
 /* Solver parameters.  tol: relative residual |b - A x| / |b| to reach, measured

@@ -329,6 +329,7 @@ namespace {
 
 constexpr int kMaxSrcPerSys = 12;
 constexpr double kStopFactor = 0.9;  // stop at an FP64 residual of 0.9 tol
+constexpr int kFuseMaxBlocks = 1024;  // AUTO engine: fused sequence up to V/2 = 65536 per system
 
 struct SysSpec {
   const qx_gauge* g64;
@@ -341,7 +342,7 @@ struct SysSpec {
 
 struct Layout {
   size_t sys_off = 0, st_off = 0, gs_off = 0, total = 0;
-  std::vector<size_t> partial_off, vlo_off, vhi_off;
+  std::vector<size_t> partial_off, partial_v_off, vlo_off, vhi_off;
 };
 
 int lo_prec(const qx_cg_params_t* p) { return p->mode == QX_CG_FP64 ? QX_PREC_F64 : QX_PREC_F32; }
@@ -354,16 +355,17 @@ Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
   L.st_off = off;
   size_t nsrc = 0;
   for (const auto& s : specs) nsrc += s.nrhs;
-  off = align_up(off + sizeof(SrcState) * nsrc, 256);
+  off = align_up(off + 2 * sizeof(SrcState) * nsrc, 256);  // two state slots
   L.gs_off = off;
   off = align_up(off + sizeof(GridSync), 256);
   for (const auto& s : specs) {
     const Geo& g = s.g64->geo;
     const int nblk = (g.hv + kTile - 1) / kTile;
     const int vtiles = (3 * g.hv + kVTile - 1) / kVTile;
-    const size_t n1 = std::max(nblk, vtiles);
     L.partial_off.push_back(off);
-    off = align_up(off + sizeof(double) * s.nrhs * n1, 256);
+    off = align_up(off + sizeof(double) * s.nrhs * nblk, 256);
+    L.partial_v_off.push_back(off);
+    off = align_up(off + sizeof(double) * s.nrhs * vtiles, 256);
     L.vlo_off.push_back(off);
     off = align_up(off + 5 * field_bytes(g, s.nrhs, prec_lo), 256);
     L.vhi_off.push_back(off);
@@ -381,7 +383,7 @@ int check_params(const qx_cg_params_t* p) {
   if (p->mode == QX_CG_MIXED_F32 && !(p->delta > 0.0 && p->delta < 1.0))
     return fail(QX_EINVAL, "solver: delta must be in (0, 1) for the mixed mode");
   if (p->chunk < 0) return fail(QX_EINVAL, "solver: chunk must be >= 0");
-  if (p->engine < QX_ENGINE_AUTO || p->engine > QX_ENGINE_PERSISTENT)
+  if (p->engine < QX_ENGINE_AUTO || p->engine > QX_ENGINE_FUSED)
     return fail(QX_EINVAL, "solver: unknown engine %d", p->engine);
   return QX_OK;
 }
@@ -473,6 +475,11 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   B->cfg.nsys = (int)B->specs.size();
   B->cfg.d_sys = (const SysDesc*)(B->ws + B->layout.sys_off);
   B->cfg.d_st = (SrcState*)(B->ws + B->layout.st_off);
+  {
+    int nsrc_all = 0;
+    for (const auto& s : B->specs) nsrc_all += s.nrhs;
+    B->cfg.d_st1 = B->cfg.d_st + nsrc_all;
+  }
 
   B->sys.clear();
   B->st0.clear();
@@ -495,6 +502,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     d.vlo = B->ws + B->layout.vlo_off[i];
     d.vhi = B->ws + B->layout.vhi_off[i];
     d.partials = (double*)(B->ws + B->layout.partial_off[i]);
+    d.partials_v = (double*)(B->ws + B->layout.partial_v_off[i]);
     blk += d.nblk;
     vblk += d.nsrc * d.vtiles;
     src += d.nsrc;
@@ -526,6 +534,15 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
       return fail(QX_EINVAL, "solver: the persistent engine cannot be launched on this device");
     B->persistent = true;
     B->pgrid = std::min(cap, B->cfg.nblk_total);
+  }
+  // the fused launch sequence finishes each reduction in every block of the
+  // next vector pass: cheap while a source has few partials
+  B->cfg.fused = false;
+  if (!B->persistent) {
+    int max_nblk = 0;
+    for (const auto& d : B->sys) max_nblk = std::max(max_nblk, d.nblk);
+    B->cfg.fused = p.engine == QX_ENGINE_FUSED ||
+                   (p.engine == QX_ENGINE_AUTO && max_nblk <= kFuseMaxBlocks);
   }
   if (B->persistent) {
     B->chunk = p.chunk > 0 ? p.chunk : 512;

@@ -127,6 +127,25 @@ __device__ __forceinline__ double tile_sum(int tile, size_t n, double* sh, F&& f
   return t;
 }
 
+// Sum of a[0..n) in an order that does not depend on the block size: 256
+// virtual lanes, lane j adding a[j], a[j + 256], ... in turn, each virtual
+// wavefront of 64 lanes reduced by one butterfly, the four wavefront sums
+// added in order.  Every thread of the block calls it (the block is a whole
+// number of wavefronts) and every thread gets the result.  sh: 4 doubles.
+__device__ __forceinline__ double canon_sum(const double* __restrict__ a, int n, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  for (int vw = w; vw < 4; vw += nw) {
+    double v = 0.0;
+    for (int i = vw * 64 + lane; i < n; i += 256) v += a[i];
+    v = wave_sum(v);
+    if (lane == 0) sh[vw] = v;
+  }
+  __syncthreads();
+  const double t = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  __syncthreads();
+  return t;
+}
+
 }  // namespace
 
 // =================================================================== init
@@ -151,7 +170,7 @@ __global__ void __launch_bounds__(256) k_init(const SysDesc* __restrict__ sys, i
     const cplx<double> bv = bb[e];
     return bv.re * bv.re + bv.im * bv.im;
   });
-  if (threadIdx.x == 0) d.partials[(size_t)k * d.vtiles + tile] = t;
+  if (threadIdx.x == 0) d.partials_v[(size_t)k * d.vtiles + tile] = t;
 }
 
 // x_hi = 0 for zero sources (the solution of A x = 0).
@@ -170,15 +189,56 @@ __global__ void __launch_bounds__(256) k_zero_done(const SysDesc* __restrict__ s
 
 enum FinKind : int { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RU = 3, FIN_COMMIT = 4 };
 
-// Sum of the n partials of source k in index order (valid in thread 0).
-__device__ __forceinline__ double partial_total(const SysDesc& d, int k, int n, double* sh) {
-  double v[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += d.partials[(size_t)k * n + i];
-  block_sum<1>(v, sh);
-  return v[0];
+// Total of the partials a reduction of the given kind left for source k: the
+// stencil passes' (<p, Ap>, FP64 |r|^2) or the vector passes' (|b|^2, |r|^2).
+__device__ __forceinline__ double partial_total(const SysDesc& d, int k, int kind, double* sh) {
+  if (kind == FIN_ALPHA || kind == FIN_RU)
+    return canon_sum(d.partials + (size_t)k * d.nblk, d.nblk, sh);
+  return canon_sum(d.partials_v + (size_t)k * d.vtiles, d.vtiles, sh);
 }
 
-// The state update of one source after a reduction (thread 0 only).
+// Decisions taken from a reduction.  The finalize kernels apply them to the
+// source state; the fused passes also act on them in every block, so both go
+// through these functions.
+struct AlphaStep {
+  bool ok;       // <p, Ap> > 0 and finite; otherwise a breakdown
+  double alpha;  // rho / <p, Ap>
+};
+__device__ __forceinline__ AlphaStep alpha_step(double rho, double pAp) {
+  const bool ok = pAp > 0.0 && isfinite(pAp);
+  return {ok, ok ? rho / pAp : 0.0};
+}
+
+enum BetaOutcome : int { BETA_GO = 0, BETA_UPDATE = 1, BETA_MAXED = 2, BETA_NONFINITE = 3 };
+struct BetaStep {
+  int outcome;
+  double rmax;  // max |r| since the last update, including this one
+  double beta;  // |r|^2 / rho when the recurrence goes on
+};
+// iters: the iteration count including this step.
+__device__ __forceinline__ BetaStep beta_step(double t, int iters, int max_iter, double rmax,
+                                              double stop2, double delta, double rho) {
+  if (!isfinite(t)) return {BETA_NONFINITE, rmax, 0.0};
+  const double rn = sqrt(t);
+  const double rm = rn > rmax ? rn : rmax;
+  if (iters >= max_iter) return {BETA_MAXED, rm, 0.0};
+  if (t <= stop2 || rn < delta * rm) return {BETA_UPDATE, rm, 0.0};
+  return {BETA_GO, rm, t / rho};
+}
+
+enum RuOutcome : int { RU_GO = 0, RU_CONVERGED = 1, RU_NONFINITE = 2, RU_STOP = 3 };
+struct RuStep {
+  int outcome;
+  double beta;  // 0 after the initial residual, else |r_hi|^2 / rho
+};
+__device__ __forceinline__ RuStep ru_step(double t, double stop2, int reason, double rho) {
+  if (t <= stop2) return {RU_CONVERGED, 0.0};
+  if (!isfinite(t)) return {RU_NONFINITE, 0.0};
+  if (reason == RU_FINAL) return {RU_STOP, 0.0};
+  return {RU_GO, reason == RU_INIT ? 0.0 : t / rho};
+}
+
+// The state update of one source after a reduction (one thread).
 template <bool FRESH>
 __device__ __forceinline__ void finalize_source(int kind, StateRef<FRESH> q, double t) {
   switch (kind) {
@@ -195,59 +255,52 @@ __device__ __forceinline__ void finalize_source(int kind, StateRef<FRESH> q, dou
         q.relres = t;
       }
       break;
-    case FIN_ALPHA:  // <p, Ap>: alpha, or a breakdown when <p, Ap> <= 0 or not finite
+    case FIN_ALPHA: {  // <p, Ap>: alpha, or a breakdown
+      const AlphaStep a = alpha_step(q.rho, t);
       q.pAp = t;
       q.pend = 0;
-      if (!(t > 0.0) || !isfinite(t)) {
+      if (a.ok) {
+        q.alpha = a.alpha;
+      } else {
         q.phase = PH_RU;
         q.reason = RU_FINAL;
         q.status = kStatusBreakdown;
-      } else {
-        q.alpha = q.rho / t;
-      }
-      break;
-    case FIN_BETA: {  // |r|^2 of the recurrence: continue, update, or stop
-      q.iters = q.iters + 1;
-      if (!isfinite(t)) {
-        q.phase = PH_RU;
-        q.reason = RU_FINAL;
-        q.status = kStatusBreakdown;
-        break;
-      }
-      const double rn = sqrt(t);
-      if (rn > q.rmax) q.rmax = rn;
-      if (q.iters >= q.max_iter) {
-        q.phase = PH_RU;
-        q.reason = RU_FINAL;
-        q.status = kStatusNotConverged;
-      } else if (t <= q.stop2 || rn < q.delta * q.rmax) {
-        q.phase = PH_RU;
-        q.reason = RU_DROP;
-      } else {
-        q.beta = t / q.rho;
-        q.rho = t;
-        q.pend = 1;
       }
       break;
     }
-    case FIN_RU:  // FP64 |b - A x|^2: converged, or restart the recurrence from it
+    case FIN_BETA: {  // |r|^2 of the recurrence: continue, update, or stop
+      const int it = q.iters + 1;
+      const BetaStep b = beta_step(t, it, q.max_iter, q.rmax, q.stop2, q.delta, q.rho);
+      q.iters = it;
+      q.rmax = b.rmax;
+      if (b.outcome == BETA_GO) {
+        q.beta = b.beta;
+        q.rho = t;
+        q.pend = 1;
+      } else {
+        q.phase = PH_RU;
+        q.reason = b.outcome == BETA_UPDATE ? RU_DROP : RU_FINAL;
+        if (b.outcome == BETA_MAXED) q.status = kStatusNotConverged;
+        if (b.outcome == BETA_NONFINITE) q.status = kStatusBreakdown;
+      }
+      break;
+    }
+    case FIN_RU: {  // FP64 |b - A x|^2: converged, or restart the recurrence from it
+      const RuStep r = ru_step(t, q.stop2, q.reason, q.rho);
       q.updates = q.updates + 1;
       q.relres = sqrt(t / q.bnorm2);
-      if (t <= q.stop2) {
-        q.phase = PH_DONE;
-        q.status = kStatusOk;
-      } else if (!isfinite(t)) {
-        q.phase = PH_DONE;
-        q.status = kStatusBreakdown;
-      } else if (q.reason == RU_FINAL) {
-        q.phase = PH_DONE;
-      } else {
-        q.beta = q.reason == RU_INIT ? 0.0 : t / q.rho;
+      if (r.outcome == RU_GO) {
+        q.beta = r.beta;
         q.rho = t;
         q.rmax = sqrt(t);
         q.phase = PH_RU2;
+      } else {
+        q.phase = PH_DONE;
+        if (r.outcome == RU_CONVERGED) q.status = kStatusOk;
+        if (r.outcome == RU_NONFINITE) q.status = kStatusBreakdown;
       }
       break;
+    }
     case FIN_COMMIT:  // a finished update lets the source iterate again
       q.phase = PH_RUN;
       q.pend = 0;
@@ -270,17 +323,12 @@ __device__ __forceinline__ void finalize_one(const SysDesc* __restrict__ sys, in
   const int k = g - d.src0;
   const int ph = fin_phase(kind);
   if (ph >= 0 && rd<FRESH>(st[g].phase) != ph) return;
-  double t = 0.0;
-  if (kind != FIN_COMMIT) {
-    const int n = (kind == FIN_ALPHA || kind == FIN_RU) ? d.nblk : d.vtiles;
-    t = partial_total(d, k, n, sh);
-  }
+  const double t = kind != FIN_COMMIT ? partial_total(d, k, kind, sh) : 0.0;
   if (threadIdx.x == 0) finalize_source<FRESH>(kind, st[g], t);
 }
 
-// One block of 1024 threads per source of the batch (the partials of a 32^4
-// system number 8192 per source: four loads per thread keep this short).
-__global__ void __launch_bounds__(1024) k_finalize(const SysDesc* __restrict__ sys, int nsys,
+// One block per source of the batch.
+__global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sys, int nsys,
                                                   SrcState* st, int kind) {
   __shared__ double sh[16];
   finalize_one<false>(sys, nsys, st, blockIdx.x, kind, sh);
@@ -365,16 +413,11 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   __syncthreads();  // the shared scratch is reused by the next tile
 }
 
-// E3: x_lo += alpha p, r -= alpha Ap over one vector tile and the partial of
-// |r|^2.  Works for any block size.
-template <typename R, bool FRESH>
-__device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsys,
-                                        const SrcState* st, int b, double* sh) {
-  const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
-  if (rd<FRESH>(st[d.src0 + k].phase) != PH_RUN) return;
+// x_lo += alpha p, r -= alpha Ap over vector tile `tile` of source k of a
+// system, and the partial of |r|^2.  Works for any block size.
+template <typename R>
+__device__ __forceinline__ void xr_body(const SysDesc& d, int k, int tile, R al, double* sh) {
   const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
-  const R al = (R)rd<FRESH>(st[d.src0 + k].alpha);
   cplx<R>* x = slot<R>(d.vlo, 0, vs) + k * n;
   cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
   const cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
@@ -390,20 +433,13 @@ __device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsy
     r[e] = rv;
     return (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
   });
-  if (threadIdx.x == 0) d.partials[(size_t)k * d.vtiles + tile] = t;
+  if (threadIdx.x == 0) d.partials_v[(size_t)k * d.vtiles + tile] = t;
 }
 
-// E0: p = r + beta p over one vector tile, for running sources whose search
-// direction the previous iteration left pending.  Works for any block size.
-template <typename R, bool FRESH>
-__device__ __forceinline__ void p_tile(const SysDesc* __restrict__ sys, int nsys,
-                                       const SrcState* st, int b) {
-  const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
-  const SrcState& q = st[d.src0 + k];
-  if (rd<FRESH>(q.phase) != PH_RUN || !rd<FRESH>(q.pend)) return;
+// p = r + beta p over vector tile `tile` of source k.  Works for any block size.
+template <typename R>
+__device__ __forceinline__ void p_body(const SysDesc& d, int k, int tile, R be) {
   const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
-  const R be = (R)rd<FRESH>(q.beta);
   const cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
   cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
   for (int t = threadIdx.x; t < kVTile; t += blockDim.x) {
@@ -412,6 +448,28 @@ __device__ __forceinline__ void p_tile(const SysDesc* __restrict__ sys, int nsys
     const cplx<R> rv = r[e], pv = p[e];
     p[e] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
   }
+}
+
+// E3: x_lo += alpha p, r -= alpha Ap and the partials of |r|^2, for running sources.
+template <typename R, bool FRESH>
+__device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsys,
+                                        const SrcState* st, int b, double* sh) {
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  if (rd<FRESH>(st[d.src0 + k].phase) != PH_RUN) return;
+  xr_body<R>(d, k, tile, (R)rd<FRESH>(st[d.src0 + k].alpha), sh);
+}
+
+// E0: p = r + beta p for running sources whose search direction the previous
+// iteration left pending.
+template <typename R, bool FRESH>
+__device__ __forceinline__ void p_tile(const SysDesc* __restrict__ sys, int nsys,
+                                       const SrcState* st, int b) {
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const SrcState& q = st[d.src0 + k];
+  if (rd<FRESH>(q.phase) != PH_RUN || !rd<FRESH>(q.pend)) return;
+  p_body<R>(d, k, tile, (R)rd<FRESH>(q.beta));
 }
 
 template <typename R>
@@ -441,6 +499,119 @@ __global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys
                                                  const SrcState* st, int xcd) {
   __shared__ double sh[16];
   xr_tile<R, false>(sys, nsys, st, logical_block(xcd), sh);
+}
+
+// ------------------------------------------------- fused launch sequence
+//
+// With few partials per source (small lattices) the two finalize launches of
+// an iteration and three of a reliable update are folded into the vector
+// pass that follows them: every block of a source adds the source's partials
+// itself (canon_sum: the same sum, in the same order, in every block and in
+// k_finalize), applies the state update to a private copy and acts on it.
+// The source's first vector tile writes the updated state to the other of two
+// state slots (st_out); every kernel of the launch reads only the slot the
+// previous launches wrote (st_in), so no block reads a state another block of
+// the same launch is writing.  An iteration is k_fiter_p (slot 0 -> 1),
+// k_iter_doe and k_iter_deo (reading slot 1), k_fiter_xr (slot 1 -> 0); a
+// reliable update is k_ru_doe (slot 0), k_ru_residual (copying slot 0 -> 1),
+// k_fru_finish (slot 1 -> 0).  Sources start and end each iteration and each
+// update in slot 0, as the other engines keep them.
+
+// The state written by the designated thread of a fused pass: a copy of the
+// source's state with the reduction applied (the same update k_finalize
+// makes), plus the fused-sequence flags.
+template <int KIND>
+__device__ __forceinline__ void write_state(const SrcState& in, SrcState* out, bool apply,
+                                            double t, int have_rr) {
+  *out = in;
+  if (apply) finalize_source<false>(KIND, *out, t);
+  if (KIND == FIN_RU && out->phase == PH_RU2) finalize_source<false>(FIN_COMMIT, *out, 0.0);
+  out->pend = 0;
+  out->have_rr = have_rr;
+}
+
+// F0: the beta step of the last x/r update (continue, update, or stop), then
+// p = r + beta p for sources that continue.  The state is read in place (the
+// same values in every block); the source's first tile writes the new one.
+template <typename R>
+__global__ void __launch_bounds__(256) k_fiter_p(const SysDesc* __restrict__ sys, int nsys,
+                                                 const SrcState* __restrict__ st_in,
+                                                 SrcState* __restrict__ st_out, int xcd) {
+  __shared__ double sh[4];
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const int g = d.src0 + k;
+  const SrcState& q = st_in[g];
+  const bool step = q.phase == PH_RUN && q.have_rr;
+  double t = 0.0;
+  BetaStep bs{BETA_UPDATE, 0.0, 0.0};
+  if (step) {
+    t = canon_sum(d.partials_v + (size_t)k * d.vtiles, d.vtiles, sh);
+    bs = beta_step(t, q.iters + 1, q.max_iter, q.rmax, q.stop2, q.delta, q.rho);
+  }
+  if (tile == 0 && threadIdx.x == 0) write_state<FIN_BETA>(q, st_out + g, step, t, step ? 0 : q.have_rr);
+  if (step && bs.outcome == BETA_GO) p_body<R>(d, k, tile, (R)bs.beta);
+}
+
+// F3: the alpha step from the <p, Ap> partials (or a breakdown), then
+// x_lo += alpha p, r -= alpha Ap and the |r|^2 partials.
+template <typename R>
+__global__ void __launch_bounds__(256) k_fiter_xr(const SysDesc* __restrict__ sys, int nsys,
+                                                  const SrcState* __restrict__ st_in,
+                                                  SrcState* __restrict__ st_out, int xcd) {
+  __shared__ double sh[16];
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const int g = d.src0 + k;
+  const SrcState& q = st_in[g];
+  const bool run = q.phase == PH_RUN;
+  double t = 0.0;
+  AlphaStep as{false, 0.0};
+  if (run) {
+    t = canon_sum(d.partials + (size_t)k * d.nblk, d.nblk, sh);
+    as = alpha_step(q.rho, t);
+  }
+  const bool go = run && as.ok;
+  if (tile == 0 && threadIdx.x == 0) write_state<FIN_ALPHA>(q, st_out + g, run, t, go ? 1 : q.have_rr);
+  if (go) xr_body<R>(d, k, tile, (R)as.alpha, sh);
+}
+
+// R3 fused: the FP64 residual step (converged, broken down, or restart the
+// recurrence), then r = lo(r_hi), p = r + beta p for sources that go on.
+template <typename R>
+__global__ void __launch_bounds__(256) k_fru_finish(const SysDesc* __restrict__ sys, int nsys,
+                                                    const SrcState* __restrict__ st_in,
+                                                    SrcState* __restrict__ st_out, int xcd) {
+  __shared__ double sh[4];
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const int g = d.src0 + k;
+  const SrcState& q = st_in[g];
+  const bool ru = q.phase == PH_RU;
+  double t = 0.0;
+  RuStep rs{RU_STOP, 0.0};
+  if (ru) {
+    t = canon_sum(d.partials + (size_t)k * d.nblk, d.nblk, sh);
+    rs = ru_step(t, q.stop2, q.reason, q.rho);
+  }
+  if (tile == 0 && threadIdx.x == 0) write_state<FIN_RU>(q, st_out + g, ru, t, ru ? 0 : q.have_rr);
+  if (!(ru && rs.outcome == RU_GO)) return;
+  const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
+  const R be = (R)rs.beta;
+  const cplx<double>* rhi = slot<double>(d.vhi, 1, vs) + k * n;
+  cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
+  cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  for (int e0 = threadIdx.x; e0 < kVTile; e0 += blockDim.x) {
+    const size_t e = (size_t)tile * kVTile + e0;
+    if (e >= n) break;
+    const cplx<double> h = rhi[e];
+    const cplx<R> rv = {(R)h.re, (R)h.im}, pv = p[e];
+    r[e] = rv;
+    p[e] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+  }
 }
 
 // ------------------------------------------------------- persistent kernel
@@ -561,15 +732,20 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
 
 // R2: x_hi += x_lo, x_lo = 0, r_hi = b - (m^2 x_hi - 1/4 (2D_eo) t_hi) and the
 // partials of |r_hi|^2, all in FP64.
+// st_copy (fused sequence, else null): the system's first block copies its
+// source states there.
 template <typename Rlo, int RECON, int NBT>
 __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
-    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd) {
+    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd,
+                  SrcState* st_copy) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
   const int lane = threadIdx.x & 63, grp = wave_id();
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
+  if (st_copy && b == d.blk0)
+    for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x) st_copy[d.src0 + k] = q0[k];
   const unsigned long long ru = phase_bits<false>(q0, d.nsrc, PH_RU);
   if (!ru) return;
   const int bl = tile_block(b - d.blk0, d.g, xcd), cb = bl * kTile + lane;
@@ -652,7 +828,7 @@ bool engine_supported(const EngineCfg& c) {
 
 namespace {
 hipError_t finalize(const EngineCfg& c, int kind, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(1024), 0, s, c.d_sys, c.nsys, c.d_st,
+  hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(256), 0, s, c.d_sys, c.nsys, c.d_st,
                      kind);
   return hipGetLastError();
 }
@@ -677,16 +853,31 @@ hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
   const dim3 sgrid(c.nblk_total), sblock(64 * c.shape.lps * G);
   const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
+  // the stencil passes read slot 1 in the fused sequence (written by k_fiter_p)
+  SrcState* st_s = c.fused ? c.d_st1 : c.d_st;
   hipError_t e = with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-      hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+      if (c.fused)
+        hipLaunchKernelGGL(k_fiter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.d_st1,
+                           c.shape.xcd);
+      else
+        hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         c.d_st, c.shape.xcd);
+                         st_s, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         c.d_st, c.shape.xcd);
+                         st_s, c.shape.xcd);
       return hipGetLastError();
     });
   });
+  if (c.fused) {
+    if (e == hipSuccess)
+      e = with_prec(c.prec_lo, [&]<typename R>() {
+        hipLaunchKernelGGL(k_fiter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,
+                           c.shape.xcd);
+        return hipGetLastError();
+      });
+    return e;
+  }
   if (e == hipSuccess) e = finalize(c, FIN_ALPHA, s);
   if (e == hipSuccess)
     e = with_prec(c.prec_lo, [&]<typename R>() {
@@ -757,22 +948,32 @@ hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * G);
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
+  SrcState* copy = c.fused ? c.d_st1 : nullptr;
   hipError_t e = with_prec(c.prec_lo, [&]<typename Rlo>() {
     return with_nbt(c.shape.nbt, [&]<int NBT>() {
       if (c.recon_hi == 12) {
         hipLaunchKernelGGL((k_ru_doe<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
                            c.shape.xcd);
         hipLaunchKernelGGL((k_ru_residual<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
-                           c.d_st, c.shape.xcd);
+                           c.d_st, c.shape.xcd, copy);
       } else {
         hipLaunchKernelGGL((k_ru_doe<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
                            c.shape.xcd);
         hipLaunchKernelGGL((k_ru_residual<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
-                           c.d_st, c.shape.xcd);
+                           c.d_st, c.shape.xcd, copy);
       }
       return hipGetLastError();
     });
   });
+  if (c.fused) {
+    if (e == hipSuccess)
+      e = with_prec(c.prec_lo, [&]<typename Rlo>() {
+        hipLaunchKernelGGL(k_fru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1,
+                           c.d_st, c.shape.xcd);
+        return hipGetLastError();
+      });
+    return e;
+  }
   if (e == hipSuccess) e = finalize(c, FIN_RU, s);
   if (e == hipSuccess)
     e = with_prec(c.prec_lo, [&]<typename Rlo>() {

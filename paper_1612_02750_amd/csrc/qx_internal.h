@@ -58,8 +58,8 @@ struct SrcState {
   int reason;       // RuReason of a pending update
   int status;       // QX_* status
   int iters, updates, max_iter;
-  int pend;         // p is still to be replaced by r + beta p (done inside the next stencil passes)
-  int pad;
+  int pend;         // p is still to be replaced by r + beta p (done by the next p pass)
+  int have_rr;      // |r|^2 partials of the last x/r update await the beta step (fused engine)
 };
 
 // One system of a solver launch: a lattice, its links in the inner precision
@@ -77,7 +77,8 @@ struct SysDesc {
   const void* links_hi;
   void* vlo;        // inner precision: x_lo, r, p, Ap (even), t (odd); each [nsrc][3][hv]
   void* vhi;        // FP64: x_hi, r_hi, b (even), t_hi (odd); each [nsrc][3][hv]
-  double* partials;   // per-block partial sums: [nsrc][nblk] (stencil) or [nsrc][vtiles] (vector)
+  double* partials;    // per-block partial sums of the stencil passes: [nsrc][nblk]
+  double* partials_v;  // per-tile partial sums of the vector passes: [nsrc][vtiles]
 };
 
 // Grid barrier of the persistent solver kernel (zeroed before first use).

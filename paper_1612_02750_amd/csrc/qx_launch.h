@@ -65,7 +65,9 @@ struct EngineCfg {
   LaunchShape shape;
   int nsys = 0, nblk_total = 0, nvblk_total = 0, nsrc_total = 0;
   const SysDesc* d_sys = nullptr;
-  SrcState* d_st = nullptr;
+  SrcState* d_st = nullptr;   // the source states (slot 0)
+  SrcState* d_st1 = nullptr;  // second slot of the fused launch sequence
+  bool fused = false;         // four launches per iteration (redundant reductions), see the engine
 };
 
 bool engine_supported(const EngineCfg& c);

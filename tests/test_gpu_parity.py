@@ -534,13 +534,19 @@ def test_autograd_action(qx):
     assert rel(to_host(Ut.grad), Go) <= 1e-9
 
 
-# ------------------------------------------------------- persistent engine
+# ------------------------------------------------------------------ engines
 
+@pytest.mark.parametrize("dims", [(8, 4, 6, 8), (16, 16, 16, 36)])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_engines_agree_bitwise(qx, mixed):
-    """The persistent kernel (grid barriers) and the launch-per-pass engine run the
-    same reductions in the same order and update at the same iterations."""
-    dims = (8, 4, 6, 8)
+def test_engines_agree_bitwise(qx, mixed, dims):
+    """The launch-per-pass engine, the fused launch sequence (reductions
+    finished redundantly in every block, two state slots) and the persistent
+    kernel (grid barriers) run the same reductions in the same order and
+    update at the same iterations.  The second lattice has 1152 stencil blocks
+    and 864 vector tiles per source, so the block-size-independent sums span
+    several rounds of their 256 lanes, and AUTO picks the launch-per-pass
+    engine there (more than 1024 blocks)."""
+    dims = tuple(dims)
     lat = qx.Lattice(dims, antiperiodic_t=True)
     U = gauge(dims, seed=9)
     Ud = to_dev(U)
@@ -548,15 +554,20 @@ def test_engines_agree_bitwise(qx, mixed):
     glo = qx.Gauge(lat, Ud, "f32", 12) if mixed else None
     masses = [0.05, 0.2, 0.1]
     b = synth.gauss_source(3, lat.hv, 11)
-    xa, sa = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_LAUNCH)
-    xb, sb = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_PERSISTENT)
-    assert np.array_equal(to_host(xa), to_host(xb))
-    assert [s.iters for s in sa] == [s.iters for s in sb]
-    assert [s.reliable_updates for s in sa] == [s.reliable_updates for s in sb]
-    _check_solution(dims, U, masses, b, to_host(xb), sb, flags=oracle.BC_T_ANTIPERIODIC)
+    runs = [qx.cg(g64, to_dev(b), masses, glo=glo, engine=e)
+            for e in (qx.ENGINE_LAUNCH, qx.ENGINE_FUSED, qx.ENGINE_PERSISTENT, qx.ENGINE_AUTO)]
+    xa, sa = runs[0]
+    for xb, sb in runs[1:]:
+        assert np.array_equal(to_host(xa), to_host(xb))
+        assert [s.iters for s in sa] == [s.iters for s in sb]
+        assert [s.reliable_updates for s in sa] == [s.reliable_updates for s in sb]
+    _check_solution(dims, U, masses, b, to_host(xa), sa, flags=oracle.BC_T_ANTIPERIODIC)
 
 
-def test_persistent_edge_cases(qx):
+@pytest.mark.parametrize("engine", ["PERSISTENT", "FUSED", "LAUNCH"])
+def test_engine_edge_cases(qx, engine):
+    """Zero source, max_iter, a non-finite source (breakdown), m = 0 on the free
+    field (singular A), and a plain solve, under each engine."""
     import torch
 
     dims = (4, 4, 4, 4)
@@ -565,7 +576,7 @@ def test_persistent_edge_cases(qx):
     g64 = qx.Gauge(lat, to_dev(U), "f64")
     g32 = qx.Gauge(lat, to_dev(U), "f32")
     b = synth.gauss_source(1, lat.hv, 1)
-    P = qx.ENGINE_PERSISTENT
+    P = getattr(qx, "ENGINE_" + engine)
     x, st = qx.cg(g64, torch.zeros((1, lat.hv, 3), dtype=torch.complex128, device="cuda"), 0.1,
                   engine=P)
     assert st[0].status == 0 and st[0].iters == 0 and not to_host(x).any()
@@ -582,7 +593,7 @@ def test_persistent_edge_cases(qx):
     _check_solution(dims, U, [0.1], b, to_host(x), st)
 
 
-def test_persistent_uneven_batch(qx):
+def test_engines_uneven_batch(qx):
     import torch
 
     shapes = [(4, 4, 4, 4), (8, 4, 4, 6), (6, 6, 6, 6), (8, 8, 8, 8)]
@@ -600,7 +611,7 @@ def test_persistent_uneven_batch(qx):
         xd = torch.empty_like(bd)
         systems.append((g64, g32, bd, masses, xd))
         keep.append((dims, U, b, masses, xd))
-    for engine in (qx.ENGINE_PERSISTENT, qx.ENGINE_LAUNCH):
+    for engine in (qx.ENGINE_PERSISTENT, qx.ENGINE_LAUNCH, qx.ENGINE_FUSED):
         stats = qx.Batch(systems, tol=1e-10, engine=engine).solve()
         j = 0
         for dims, U, b, masses, xd in keep:
