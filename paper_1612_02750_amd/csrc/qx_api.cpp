@@ -367,7 +367,7 @@ Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
     L.partial_v_off.push_back(off);
     off = align_up(off + sizeof(double) * s.nrhs * vtiles, 256);
     L.vlo_off.push_back(off);
-    off = align_up(off + 5 * field_bytes(g, s.nrhs, prec_lo), 256);
+    off = align_up(off + 6 * field_bytes(g, s.nrhs, prec_lo), 256);
     L.vhi_off.push_back(off);
     off = align_up(off + 4 * field_bytes(g, s.nrhs, QX_PREC_F64), 256);
   }
@@ -459,8 +459,16 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   int nb = 1;
   for (const auto& s : B->specs) nb = std::max(nb, s.nrhs);
   LaunchShape sh = shape_for(s0.glo, nb);
-  if (!shape_ok(sh, nb, cplx_bytes(prec_lo)) || !nbt_lps_instantiated(sh.nbt, sh.lps))
-    sh = LaunchShape{};
+  if (!shape_ok(sh, nb, cplx_bytes(prec_lo)) || !nbt_lps_instantiated(sh.nbt, sh.lps)) {
+    // the first default that takes nb sources in one block
+    const LaunchShape cands[4] = {{1, 2, 1}, {2, 2, 1}, {4, 2, 1}, {4, 1, 1}};
+    sh = cands[0];
+    for (const LaunchShape& c : cands)
+      if (shape_ok(c, nb, cplx_bytes(prec_lo))) {
+        sh = c;
+        break;
+      }
+  }
 
   B->cfg = EngineCfg{};
   B->cfg.prec_lo = prec_lo;
@@ -533,7 +541,9 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     if (cap < 1)
       return fail(QX_EINVAL, "solver: the persistent engine cannot be launched on this device");
     B->persistent = true;
-    B->pgrid = std::min(cap, B->cfg.nblk_total);
+    // half the occupancy bound: a grid at the bound has timed out in a barrier
+    // (blocks left unscheduled), the grid-stride passes take any grid size
+    B->pgrid = std::max(1, std::min(cap / 2, B->cfg.nblk_total));
   }
   // the fused launch sequence finishes each reduction in every block of the
   // next vector pass: cheap while a source has few partials
@@ -550,6 +560,8 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     B->use_graph = false;
   } else {
     B->chunk = p.chunk > 0 ? p.chunk : 16;
+    // the fused sequence alternates two p slots: even chunks and update periods
+    if (B->cfg.fused) B->chunk += B->chunk & 1;
     B->ru_every = std::min(B->chunk, 4);
   }
   return QX_OK;
@@ -575,7 +587,7 @@ int enqueue_chunk(qx_batch* B, hipStream_t s) {
     QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
   } else {
     for (int i = 0; i < B->chunk; ++i) {
-      QX_HIP(engine_iteration(B->cfg, s), "solver: iteration");
+      QX_HIP(engine_iteration(B->cfg, i & 1, s), "solver: iteration");
       if ((i + 1) % B->ru_every == 0 || i + 1 == B->chunk)
         QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
     }

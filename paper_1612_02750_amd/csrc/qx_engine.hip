@@ -22,8 +22,9 @@
 // update on the fly inside D_oe saves a pass but doubles the neighbour loads
 // the compiler hoists, which spills registers; the separate pass is cheaper.)
 //
-// Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd)}, FP64
-// vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv].
+// Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd), p'}, FP64
+// vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv]; p' is the
+// second p slot of the fused sequence.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -372,8 +373,8 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
 // E2: Ap = m^2 p - 1/4 (2D_eo) t and the partials of Re<p, Ap>.
 template <typename R, int RECON, int NBT, int LPS, bool FRESH>
 __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
-                                         const SrcState* st, int b, int order, double* sh,
-                                         double* tot) {
+                                         const SrcState* st, int b, int order, int pslot,
+                                         double* sh, double* tot) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
@@ -395,7 +396,7 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   double dot[NBT];
 #pragma unroll
   for (int j = 0; j < NBT; ++j) dot[j] = 0.0;
-  const cplx<R>* p = slot<R>(d.vlo, 2, vs);
+  const cplx<R>* p = slot<R>(d.vlo, pslot, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
     if (!(act >> j & 1u)) return;
@@ -416,11 +417,12 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
 // x_lo += alpha p, r -= alpha Ap over vector tile `tile` of source k of a
 // system, and the partial of |r|^2.  Works for any block size.
 template <typename R>
-__device__ __forceinline__ void xr_body(const SysDesc& d, int k, int tile, R al, double* sh) {
+__device__ __forceinline__ void xr_body(const SysDesc& d, int k, int tile, R al, int pslot,
+                                        double* sh) {
   const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
   cplx<R>* x = slot<R>(d.vlo, 0, vs) + k * n;
   cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
-  const cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  const cplx<R>* p = slot<R>(d.vlo, pslot, vs) + k * n;
   const cplx<R>* Ap = slot<R>(d.vlo, 3, vs) + k * n;
   const double t = tile_sum(tile, n, sh, [&](size_t e) {
     const cplx<R> pv = p[e], av = Ap[e];
@@ -457,7 +459,7 @@ __device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsy
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
   const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
   if (rd<FRESH>(st[d.src0 + k].phase) != PH_RUN) return;
-  xr_body<R>(d, k, tile, (R)rd<FRESH>(st[d.src0 + k].alpha), sh);
+  xr_body<R>(d, k, tile, (R)rd<FRESH>(st[d.src0 + k].alpha), 2, sh);
 }
 
 // E0: p = r + beta p for running sources whose search direction the previous
@@ -488,10 +490,10 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDes
 template <typename R, int RECON, int NBT, int LPS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDesc* __restrict__ sys,
                                                                     int nsys, const SrcState* st,
-                                                                    int xcd) {
+                                                                    int pslot, int xcd) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), xcd, sh, tot);
+  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), xcd, pslot, sh, tot);
 }
 
 template <typename R>
@@ -511,11 +513,14 @@ __global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys
 // The source's first vector tile writes the updated state to the other of two
 // state slots (st_out); every kernel of the launch reads only the slot the
 // previous launches wrote (st_in), so no block reads a state another block of
-// the same launch is writing.  An iteration is k_fiter_p (slot 0 -> 1),
-// k_iter_doe and k_iter_deo (reading slot 1), k_fiter_xr (slot 1 -> 0); a
-// reliable update is k_ru_doe (slot 0), k_ru_residual (copying slot 0 -> 1),
+// the same launch is writing.  An iteration is k_fiter_doe (slot 0 -> 1, with
+// the p update of the previous step folded in: p alternates between two
+// vector slots so that the neighbours read the old p while a block writes the
+// new one), k_iter_deo (reading slot 1), k_fiter_xr (slot 1 -> 0); a reliable
+// update is k_ru_doe (slot 0), k_ru_residual (copying slot 0 -> 1),
 // k_fru_finish (slot 1 -> 0).  Sources start and end each iteration and each
-// update in slot 0, as the other engines keep them.
+// update in slot 0, as the other engines keep them; p is in vector slot 2
+// after every even number of iterations, where updates happen.
 
 // The state written by the designated thread of a fused pass: a copy of the
 // source's state with the reduction applied (the same update k_finalize
@@ -530,28 +535,110 @@ __device__ __forceinline__ void write_state(const SrcState& in, SrcState* out, b
   out->have_rr = have_rr;
 }
 
-// F0: the beta step of the last x/r update (continue, update, or stop), then
-// p = r + beta p for sources that continue.  The state is read in place (the
-// same values in every block); the source's first tile writes the new one.
-template <typename R>
-__global__ void __launch_bounds__(256) k_fiter_p(const SysDesc* __restrict__ sys, int nsys,
-                                                 const SrcState* __restrict__ st_in,
-                                                 SrcState* __restrict__ st_out, int xcd) {
-  __shared__ double sh[4];
-  const int b = logical_block(xcd);
-  const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
-  const int g = d.src0 + k;
-  const SrcState& q = st_in[g];
-  const bool step = q.phase == PH_RUN && q.have_rr;
-  double t = 0.0;
-  BetaStep bs{BETA_UPDATE, 0.0, 0.0};
-  if (step) {
-    t = canon_sum(d.partials_v + (size_t)k * d.vtiles, d.vtiles, sh);
-    bs = beta_step(t, q.iters + 1, q.max_iter, q.rmax, q.stop2, q.delta, q.rho);
+// Stencil input of the fused D_oe pass: r + beta_j p at the neighbours for
+// sources whose p update is due (bit j of upd), else p, in the same
+// arithmetic as p_body.
+template <typename R, int NBT>
+struct PendIn {
+  const cplx<R>* __restrict__ r;  // first source of the thread
+  const cplx<R>* __restrict__ p;
+  size_t ss, hv;
+  unsigned upd;
+  R beta[NBT];
+  __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
+    const cplx<R> pv = ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
+    if (!(upd >> j & 1u)) return pv;
+    const cplx<R> rv = ld_cplx<false>(r + j * ss + c * hv, (unsigned)site);
+    return {fma(beta[j], pv.re, rv.re), fma(beta[j], pv.im, rv.im)};
   }
-  if (tile == 0 && threadIdx.x == 0) write_state<FIN_BETA>(q, st_out + g, step, t, step ? 0 : q.have_rr);
-  if (step && bs.outcome == BETA_GO) p_body<R>(d, k, tile, (R)bs.beta);
+};
+
+// F1: the beta step of the last x/r update folded into the D_oe pass.  Every
+// block adds each stepping source's |r|^2 partials and takes the decision of
+// k_finalize; it then writes p_new = r + beta p (or a copy of p, for sources
+// that keep p: fresh after an update, or waiting for one) at its own even
+// sites into slot pout, and computes t = 2 D_oe p_new for running sources
+// with p_new formed on the fly at the neighbours from slot pin.  The system's
+// first block writes the updated states (slot st_out).
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>))
+    k_fiter_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* __restrict__ st_in,
+                SrcState* __restrict__ st_out, int pin, int pout, int xcd) {
+  __shared__ double sh[4];
+  __shared__ double beta_sh[64], t_sh[64];
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  const SrcState* q0 = st_in + d.src0;
+  // decisions, the same in every block: run (stencil), upd (p = r + beta p),
+  // keep (p copied), step (the beta step was taken)
+  unsigned long long run = 0, upd = 0, keep = 0, step = 0;
+  for (int k = 0; k < d.nsrc; ++k) {
+    const SrcState& q = q0[k];
+    double t = 0.0, be = 0.0;
+    if (q.phase == PH_RUN && q.have_rr) {
+      t = canon_sum(d.partials_v + (size_t)k * d.vtiles, d.vtiles, sh);
+      const BetaStep bs = beta_step(t, q.iters + 1, q.max_iter, q.rmax, q.stop2, q.delta, q.rho);
+      step |= 1ull << k;
+      if (bs.outcome == BETA_GO) {
+        run |= 1ull << k;
+        upd |= 1ull << k;
+        be = bs.beta;
+      } else {
+        keep |= 1ull << k;
+      }
+    } else if (q.phase == PH_RUN) {
+      run |= 1ull << k;
+      keep |= 1ull << k;
+    } else if (q.phase == PH_RU) {
+      keep |= 1ull << k;
+    }
+    if (threadIdx.x == 0) {
+      beta_sh[k] = be;
+      t_sh[k] = t;
+    }
+  }
+  __syncthreads();
+  if (b == d.blk0)
+    for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x) {
+      const bool sk = step >> k & 1ull;
+      write_state<FIN_BETA>(q0[k], st_out + d.src0 + k, sk, t_sh[k], sk ? 0 : q0[k].have_rr);
+    }
+  if (!(run | keep)) return;
+  const int cb = tile_block(b - d.blk0, d.g, xcd) * kTile + lane;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  const int k0 = grp * NBT;
+  const bool in_range = cb < d.g.hv;
+  const cplx<R>* p_in = slot<R>(d.vlo, pin, vs);
+  const cplx<R>* r_in = slot<R>(d.vlo, 1, vs);
+  PendIn<R, NBT> src{r_in + k0 * ss, p_in + k0 * ss, ss, hv, group_bits<NBT>(upd, k0), {}};
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) src.beta[j] = k0 + j < d.nsrc ? (R)beta_sh[k0 + j] : (R)0;
+  // p_new at the block's own even sites
+  if (dp == 0 && in_range) {
+    cplx<R>* p_out = slot<R>(d.vlo, pout, vs);
+    const unsigned mine = group_bits<NBT>(upd | keep, k0);
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (!(mine >> j & 1u)) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p_out[(k0 + j) * ss + c * hv + cb] = src(j, c, cb);
+    }
+  }
+  if (!run) return;
+  const unsigned act = in_range ? group_bits<NBT>(run, k0) : 0u;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(d.g, 1, cb, s);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp, src, act, acc);
+  }
+  cplx<R>* t = slot<R>(d.vlo, 4, vs);
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+    if (act >> j & 1u) t[(k0 + j) * ss + c * hv + cb] = v;
+  });
 }
 
 // F3: the alpha step from the <p, Ap> partials (or a breakdown), then
@@ -559,7 +646,8 @@ __global__ void __launch_bounds__(256) k_fiter_p(const SysDesc* __restrict__ sys
 template <typename R>
 __global__ void __launch_bounds__(256) k_fiter_xr(const SysDesc* __restrict__ sys, int nsys,
                                                   const SrcState* __restrict__ st_in,
-                                                  SrcState* __restrict__ st_out, int xcd) {
+                                                  SrcState* __restrict__ st_out, int pslot,
+                                                  int xcd) {
   __shared__ double sh[16];
   const int b = logical_block(xcd);
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
@@ -575,7 +663,7 @@ __global__ void __launch_bounds__(256) k_fiter_xr(const SysDesc* __restrict__ sy
   }
   const bool go = run && as.ok;
   if (tile == 0 && threadIdx.x == 0) write_state<FIN_ALPHA>(q, st_out + g, run, t, go ? 1 : q.have_rr);
-  if (go) xr_body<R>(d, k, tile, (R)as.alpha, sh);
+  if (go) xr_body<R>(d, k, tile, (R)as.alpha, pslot, sh);
 }
 
 // R3 fused: the FP64 residual step (converged, broken down, or restart the
@@ -684,7 +772,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
       doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
-      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0, sh, tot);
+      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0, 2, sh, tot);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int g = blockIdx.x; g < nsrc_total; g += gridDim.x)
       finalize_one<true>(sys, nsys, st, g, FIN_ALPHA, sh);
@@ -848,36 +936,36 @@ hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s) {
   return e;
 }
 
-hipError_t engine_iteration(const EngineCfg& c, hipStream_t s) {
+hipError_t engine_iteration(const EngineCfg& c, int parity, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * c.shape.lps * G);
   const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
-  // the stencil passes read slot 1 in the fused sequence (written by k_fiter_p)
-  SrcState* st_s = c.fused ? c.d_st1 : c.d_st;
+  if (c.fused) {
+    // p alternates between slots 2 and 5; the states between the two slots
+    const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
+    return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
+      return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+        hipLaunchKernelGGL((k_fiter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys,
+                           c.nsys, c.d_st, c.d_st1, pin, pout, c.shape.xcd);
+        hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys,
+                           c.nsys, c.d_st1, pout, c.shape.xcd);
+        hipLaunchKernelGGL(k_fiter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,
+                           pout, c.shape.xcd);
+        return hipGetLastError();
+      });
+    });
+  }
   hipError_t e = with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-      if (c.fused)
-        hipLaunchKernelGGL(k_fiter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.d_st1,
-                           c.shape.xcd);
-      else
-        hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+      hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         st_s, c.shape.xcd);
+                         c.d_st, c.shape.xcd);
       hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         st_s, c.shape.xcd);
+                         c.d_st, 2, c.shape.xcd);
       return hipGetLastError();
     });
   });
-  if (c.fused) {
-    if (e == hipSuccess)
-      e = with_prec(c.prec_lo, [&]<typename R>() {
-        hipLaunchKernelGGL(k_fiter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,
-                           c.shape.xcd);
-        return hipGetLastError();
-      });
-    return e;
-  }
   if (e == hipSuccess) e = finalize(c, FIN_ALPHA, s);
   if (e == hipSuccess)
     e = with_prec(c.prec_lo, [&]<typename R>() {

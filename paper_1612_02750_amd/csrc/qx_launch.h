@@ -10,7 +10,7 @@ namespace qx {
 // each group takes nbt sources (groups = ceil(nsrc / nbt)).
 struct LaunchShape {
   int nbt = 1;  // sources per thread: 1, 2 or 4
-  int lps = 1;  // wavefronts per site: 1, 2, 4 or 8
+  int lps = 2;  // wavefronts per site: 1, 2, 4 or 8
   int xcd = 1;  // block order: 0 as dispatched, 1 XCD-contiguous, 2 and 3 XCD-contiguous
                 // with (z, t)-tiled traversal (tile_block)
 };
@@ -72,7 +72,9 @@ struct EngineCfg {
 
 bool engine_supported(const EngineCfg& c);
 hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s);
-hipError_t engine_iteration(const EngineCfg& c, hipStream_t s);
+// parity: of the iteration's index in its chunk (the fused sequence alternates
+// two p slots; its chunks hold an even number of iterations).
+hipError_t engine_iteration(const EngineCfg& c, int parity, hipStream_t s);
 hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s);
 // Co-resident blocks of the persistent solver kernel on this device (0 if it
 // cannot be launched), and one cooperative launch of up to `iters` iterations.
