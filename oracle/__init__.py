@@ -26,6 +26,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 BC_T_ANTIPERIODIC = 1
+NAIK = 2  # improved operator: one-hop term x 9/8 plus the three-hop (Naik) term x (-1/24)
 OK, NOTCONVERGED, BREAKDOWN, EINVAL = 0, 1, 2, 3
 
 _lib = None

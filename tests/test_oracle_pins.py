@@ -379,3 +379,139 @@ def test_force_matches_torch_autograd():
     S.backward()
     _, G, _, _ = oracle.force(dims, U, m, phi, tol=1e-14)
     np.testing.assert_allclose(Ut.grad.numpy(), G, rtol=0, atol=1e-11 * np.abs(G).max())
+
+
+# ------------------------------------------------------------- Naik term (f1)
+#
+# The improved operator: the one-hop term times 9/8 plus the three-hop term
+# times -1/24 (Naik's coefficients), both with thin links.  Pins: the free
+# field in closed form (sin p -> 9/8 sin p - 1/24 sin 3p), the operator built
+# independently from dense covariant shift matrices (the three-hop term is the
+# cube of the one-hop shift), anti-Hermiticity, gauge covariance, and a CG
+# against numpy.linalg.solve.
+
+def _shift_matrices(dims, U, flags):
+    """Dense forward covariant shifts T_mu: (T_mu chi)(x) = bc U_mu(x) chi(x + mu),
+    built site by site from the links, and the diagonal staggered phases."""
+    sites = coords_bf(dims)
+    pos = {c: i for i, c in enumerate(sites)}
+    V = len(sites)
+    T, E = [], []
+    for mu in range(4):
+        M = np.zeros((3 * V, 3 * V), dtype=complex)
+        e = np.empty(3 * V)
+        for i, c in enumerate(sites):
+            y = list(c)
+            y[mu] = (y[mu] + 1) % dims[mu]
+            j = pos[tuple(y)]
+            s = -1.0 if (flags & oracle.BC_T_ANTIPERIODIC and mu == 3 and c[3] == dims[3] - 1) else 1.0
+            M[3 * i:3 * i + 3, 3 * j:3 * j + 3] += s * U[mu, i]
+            e[3 * i:3 * i + 3] = eta_bf(mu, c)
+        T.append(M)
+        E.append(np.diag(e))
+    return T, E
+
+
+@pytest.mark.parametrize("dims", [(4, 2, 2, 6), (2, 4, 6, 4), (6, 2, 4, 2)])
+@pytest.mark.parametrize("anti", [False, True])
+def test_naik_from_covariant_shifts(dims, anti):
+    """D = 1/2 sum_mu eta_mu [9/8 (T_mu - T_mu^dag) - 1/24 (T_mu^3 - (T_mu^dag)^3)] with T_mu the
+    dense one-step covariant shift; extents 2 and 4 make x + 3 mu wrap onto x - mu / x + mu."""
+    flags = oracle.NAIK | (oracle.BC_T_ANTIPERIODIC if anti else 0)
+    U = _haar(dims, 21)
+    T, E = _shift_matrices(dims, U, flags)
+    D = np.zeros_like(T[0])
+    for mu in range(4):
+        Td = T[mu].conj().T
+        D += E[mu] @ (9 / 8 * (T[mu] - Td) - 1 / 24 * (T[mu] @ T[mu] @ T[mu] - Td @ Td @ Td))
+    D *= 0.5
+    got = oracle.dense_D(dims, U, flags)
+    assert np.abs(got - D).max() < 1e-14
+
+
+@pytest.mark.parametrize("dims,anti", [((8, 4, 4, 8), False), ((8, 4, 4, 8), True),
+                                       ((6, 6, 2, 4), False)])
+def test_naik_free_field_pointwise(dims, anti):
+    """U = 1: (D phi_p)(x) = i sum_mu eta_mu(x) (9/8 sin p_mu - 1/24 sin 3 p_mu) phi_p(x)."""
+    U = synth.unit_gauge(dims)
+    rng = np.random.default_rng(5)
+    flags = oracle.NAIK | (oracle.BC_T_ANTIPERIODIC if anti else 0)
+    for trial in range(4):
+        n = [int(rng.integers(0, d)) for d in dims]
+        c = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        phi, p, sites = plane_wave(dims, n, anti, c)
+        out = oracle.dslash_full(dims, U, phi, flags)
+        f = [9 / 8 * np.sin(p[mu]) - 1 / 24 * np.sin(3 * p[mu]) for mu in range(4)]
+        fac = np.array([1j * sum(eta_bf(mu, x) * f[mu] for mu in range(4)) for x in sites])
+        # the phases exp(i p.x) carry an error of about |p.x| ulp (|p.x| up to ~60 here)
+        np.testing.assert_allclose(out, fac[:, None] * phi, rtol=0, atol=1e-13 * np.abs(phi).max())
+
+
+@pytest.mark.parametrize("anti", [False, True])
+def test_naik_free_field_spectrum_of_A(anti):
+    """U = 1 on 4^4: the eigenvalues of A are m^2 + sum_mu (9/8 sin p_mu - 1/24 sin 3 p_mu)^2."""
+    dims = (4, 4, 4, 4)
+    m = 0.1
+    flags = oracle.NAIK | (oracle.BC_T_ANTIPERIODIC if anti else 0)
+    ev = np.linalg.eigvalsh(oracle.dense_A(dims, synth.unit_gauge(dims), m, flags))
+    lam = []
+    for n in itertools.product(*[range(d) for d in dims]):
+        p = [2 * np.pi * n[mu] / dims[mu] for mu in range(4)]
+        if anti:
+            p[3] += np.pi / dims[3]
+        lam.append(m * m + sum((9 / 8 * np.sin(q) - 1 / 24 * np.sin(3 * q)) ** 2 for q in p))
+    np.testing.assert_allclose(np.sort(np.repeat(ev, 2)), np.sort(np.repeat(lam, 3)), rtol=0,
+                               atol=1e-12)
+
+
+def test_naik_antihermitian_and_covariant():
+    dims = (4, 6, 4, 8)
+    flags = oracle.NAIK | oracle.BC_T_ANTIPERIODIC
+    U = _haar(dims, 22)
+    V = int(np.prod(dims))
+    psi = synth.gauss_source(1, V, 23)[0]
+    chi = synth.gauss_source(1, V, 24)[0]
+    a = np.vdot(psi, oracle.dslash_full(dims, U, chi, flags))
+    b = np.vdot(chi, oracle.dslash_full(dims, U, psi, flags))
+    assert abs(a + np.conj(b)) < 1e-12 * abs(a)
+    g = synth.random_su3_transform(dims, 25)
+    sites = coords_bf(dims)
+    pos = {c: i for i, c in enumerate(sites)}
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        fwd = []
+        for c in sites:
+            y = list(c)
+            y[mu] = (y[mu] + 1) % dims[mu]
+            fwd.append(pos[tuple(y)])
+        Ug[mu] = g @ U[mu] @ np.conj(np.swapaxes(g[fwd], -1, -2))
+    lhs = oracle.dslash_full(dims, Ug, np.einsum("xab,xb->xa", g, chi), flags)
+    rhs = np.einsum("xab,xb->xa", g, oracle.dslash_full(dims, U, chi, flags))
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13)
+    # the Naik term changes the operator: it is not the one-hop D
+    assert np.abs(oracle.dslash_full(dims, U, chi, oracle.BC_T_ANTIPERIODIC) -
+                  oracle.dslash_full(dims, U, chi, flags)).max() > 0.1
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 2, 4)])
+def test_naik_cg_vs_dense_solve(dims):
+    flags = oracle.NAIK
+    U = _haar(dims, 26)
+    m = 0.2
+    hv = int(np.prod(dims)) // 2
+    b = synth.gauss_source(1, hv, 27)[0]
+    A = oracle.dense_A(dims, U, m, flags)
+    x_ref = np.linalg.solve(A, b.reshape(-1))
+    x, st, it, rr = oracle.cg(dims, U, m, b, tol=1e-12, flags=flags)
+    assert st == oracle.OK and rr <= 1e-12
+    np.testing.assert_allclose(x.reshape(-1), x_ref, rtol=0, atol=1e-10 * np.abs(x_ref).max())
+    xm, stm, itm, upm, rrm = oracle.cg_mixed(dims, U, m, b, tol=1e-10, flags=flags)
+    assert stm == oracle.OK and rrm <= 1e-10
+
+
+def test_naik_force_rejected():
+    dims = (4, 4, 4, 4)
+    U = _haar(dims, 28)
+    phi = synth.gauss_source(1, 128, 29)[0]
+    with pytest.raises(Exception):
+        oracle.force(dims, U, 0.1, phi, flags=oracle.NAIK)
