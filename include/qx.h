@@ -78,7 +78,14 @@ enum { QX_PREC_F64 = 0, QX_PREC_F32 = 1 };
 
 /* link storage: 18 reals, or 12 reals (rows 0-1, row 2 rebuilt in-kernel as
    sign * conj(row0 x row1); exact for SU(3) links) */
-enum { QX_RECON_18 = 18, QX_RECON_12 = 12 };
+/* Link storage.  QX_RECON_NAIK: the improved operator of the paper's
+   benchmark "with the Naik term" (Sec. 4): the one-hop term scaled by 9/8 plus
+   the three-hop term  -1/24 [N_mu(x) chi(x+3mu) - N_mu(x-3mu)^dag chi(x-3mu)],
+   N_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu) with eta and the boundary signs,
+   thin links in both terms; 18 reals for each of the two link sets (1146
+   flops per output site per half-Dslash).  Every operator and solver call
+   takes it; the fermion-force calls reject it. */
+enum { QX_RECON_18 = 18, QX_RECON_12 = 12, QX_RECON_NAIK = 36 };
 
 /* solver modes */
 enum {

@@ -194,8 +194,14 @@ class Lattice:
 
 # ------------------------------------------------------------------- gauge
 
+RECON_18, RECON_12, RECON_NAIK = 18, 12, 36
+
+
 class Gauge:
-    """Packed gauge field (eta and boundary signs folded in) of one precision."""
+    """Packed gauge field (eta and boundary signs folded in) of one precision.
+    recon: 18 or 12 reals per link for the one-hop operator, or RECON_NAIK (36)
+    for the improved operator with the Naik three-hop term (one-hop and
+    three-hop links of 18 reals each)."""
 
     def __init__(self, lat: Lattice, U, prec="f64", recon: int = 18, stream=None):
         torch = _torch()

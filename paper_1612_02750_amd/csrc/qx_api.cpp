@@ -206,9 +206,11 @@ extern "C" int qx_debug_index_maps(const qx_lattice_t* lat, int32_t* lex_of_eo, 
 
 namespace {
 bool prec_ok(int p) { return p == QX_PREC_F64 || p == QX_PREC_F32; }
-bool recon_ok(int r) { return r == QX_RECON_18 || r == QX_RECON_12; }
+bool recon_ok(int r) { return r == QX_RECON_18 || r == QX_RECON_12 || r == QX_RECON_NAIK; }
+// recon / 2 complex numbers per (site, direction): 6, 9, or 9 + 9 for the
+// improved operator's one-hop and three-hop links
 size_t gauge_bytes(const Geo& g, int prec, int recon) {
-  return (size_t)8 * g.hv * (recon == 12 ? 6 : 9) * cplx_bytes(prec);
+  return (size_t)8 * g.hv * (recon / 2) * cplx_bytes(prec);
 }
 size_t field_bytes(const Geo& g, int nrhs, int prec) {
   return (size_t)nrhs * 3 * g.hv * cplx_bytes(prec);
@@ -395,6 +397,8 @@ int check_system(const qx_gauge* g64, const qx_gauge* glo, const qx_cg_params_t*
     if (!glo) return fail(QX_EINVAL, "solver: the mixed mode needs an FP32 gauge handle");
     if (glo->prec != QX_PREC_F32) return fail(QX_EINVAL, "solver: glo must be an FP32 gauge handle");
     if (!same_lattice(g64, glo)) return fail(QX_EINVAL, "solver: g64 and glo are on different lattices");
+    if ((glo->recon == QX_RECON_NAIK) != (g64->recon == QX_RECON_NAIK))
+      return fail(QX_EINVAL, "solver: g64 and glo must both hold the improved (Naik) operator or neither");
   }
   return QX_OK;
 }
@@ -802,6 +806,8 @@ extern "C" int qx_force_from_fields(const qx_gauge_t* g64, int nrhs, const void*
   if (!g64 || nrhs < 1 || !x_packed || !lam_packed || !tmp_odd || !grad_U)
     return fail(QX_EINVAL, "qx_force_from_fields: bad argument");
   if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "qx_force_from_fields: needs FP64 links");
+  if (g64->recon == QX_RECON_NAIK)
+    return fail(QX_EINVAL, "qx_force_from_fields: the force is implemented for the one-hop operator");
   const Geo& g = g64->geo;
   char* y = (char*)tmp_odd;
   char* nu = y + field_bytes(g, nrhs, QX_PREC_F64);
@@ -845,6 +851,8 @@ extern "C" int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_c
   if (rc) return rc;
   rc = check_system(g64, glo, params);
   if (rc) return rc;
+  if (g64->recon == QX_RECON_NAIK)
+    return fail(QX_EINVAL, "qx_force: the force is implemented for the one-hop operator");
   if (nrhs < 1 || nrhs > kMaxSrcPerSys || !phi || !grad_U || !ws)
     return fail(QX_EINVAL, "qx_force: bad argument");
   const Geo& g = g64->geo;

@@ -47,7 +47,10 @@ struct Site {
   int x0, x1, x2, x3;
   int f0, f1, f2, f3;  // checkerboard index of x + mu
   int b0, b1, b2, b3;  // checkerboard index of x - mu
-  // neighbour of hop h (h < 4: x + mu_h, else x - mu_{h-4}); h known at compile time
+  int g0, g1, g2, g3;  // checkerboard index of x + 3 mu (improved operator only)
+  int c0, c1, c2, c3;  // checkerboard index of x - 3 mu (improved operator only)
+  // neighbour of hop h: h < 4 x + mu_h, h < 8 x - mu_{h-4}, h < 12 x + 3 mu_{h-8},
+  // else x - 3 mu_{h-12}; h known at compile time
   template <int H>
   __host__ __device__ __forceinline__ int nbr() const {
     if constexpr (H == 0) return f0;
@@ -57,7 +60,15 @@ struct Site {
     else if constexpr (H == 4) return b0;
     else if constexpr (H == 5) return b1;
     else if constexpr (H == 6) return b2;
-    else return b3;
+    else if constexpr (H == 7) return b3;
+    else if constexpr (H == 8) return g0;
+    else if constexpr (H == 9) return g1;
+    else if constexpr (H == 10) return g2;
+    else if constexpr (H == 11) return g3;
+    else if constexpr (H == 12) return c0;
+    else if constexpr (H == 13) return c1;
+    else if constexpr (H == 14) return c2;
+    else return c3;
   }
   __host__ __device__ __forceinline__ int fwd(int mu) const {
     return mu == 0 ? f0 : mu == 1 ? f1 : mu == 2 ? f2 : f3;
@@ -90,6 +101,20 @@ __host__ __device__ __forceinline__ void site_geometry(const Geo& g, int p, int 
   s.b2 = (x2 == 0) ? cb + (g.L2 - 1) * g.s2 : cb - g.s2;
   s.f3 = (x3 + 1 == g.L3) ? cb - (g.L3 - 1) * g.s3 : cb + g.s3;
   s.b3 = (x3 == 0) ? cb + (g.L3 - 1) * g.s3 : cb - g.s3;
+}
+
+// The x +- 3 mu neighbours of a site (the Naik hops), with periodic wrap on
+// any even extent (on an extent of 2 or 4 they land on x -+ mu or x +- mu).
+__host__ __device__ __forceinline__ void three_hop_geometry(const Geo& g, int cb, Site& s) {
+  const int row = cb - (s.x0 >> 1);
+  s.g0 = row + (((s.x0 + 3) % g.L0) >> 1);
+  s.c0 = row + (((s.x0 - 3) % g.L0 + g.L0) % g.L0 >> 1);
+  s.g1 = cb + ((s.x1 + 3) % g.L1 - s.x1) * g.s1;
+  s.c1 = cb + (((s.x1 - 3) % g.L1 + g.L1) % g.L1 - s.x1) * g.s1;
+  s.g2 = cb + ((s.x2 + 3) % g.L2 - s.x2) * g.s2;
+  s.c2 = cb + (((s.x2 - 3) % g.L2 + g.L2) % g.L2 - s.x2) * g.s2;
+  s.g3 = cb + ((s.x3 + 3) % g.L3 - s.x3) * g.s3;
+  s.c3 = cb + (((s.x3 - 3) % g.L3 + g.L3) % g.L3 - s.x3) * g.s3;
 }
 
 // Staggered phase eta_mu(x) = (-1)^(x_0 + ... + x_{mu-1}).
@@ -224,13 +249,17 @@ struct FieldIn {
 };
 
 // acc[j] += hop H applied to in_j, j < NBT (bit j of act).
+// Hops 8..15 (RECON == 36) are the three-hop terms, with the links at lf3/lb3.
 template <int H, typename R, int RECON, int NBT, bool NT, typename In>
 __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restrict__ lf,
-                                            const cplx<R>* __restrict__ lb, int cb, const Site& s,
+                                            const cplx<R>* __restrict__ lb,
+                                            const cplx<R>* __restrict__ lf3,
+                                            const cplx<R>* __restrict__ lb3, int cb, const Site& s,
                                             const In& in, unsigned act, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   constexpr int mu = H & 3;
-  constexpr bool fwd = H < 4;
+  constexpr bool fwd = (H & 4) == 0;
+  constexpr bool three = H >= 8;
   const size_t hv = (size_t)g.hv;
   int sign = 1;
   if constexpr (RECON == 12) {
@@ -243,8 +272,8 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
   }
   const int nb = s.template nbr<H>();
   cplx<R> u[9];
-  load_link<R, RECON, NT>(u, (fwd ? lf : lb) + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv,
-                          sign);
+  const cplx<R>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
+  load_link<R, RECON, NT>(u, base + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv, sign);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     if (!(act >> j & 1u)) continue;
@@ -271,11 +300,14 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
 // Each hop is its own instantiation, guarded by a wavefront-uniform test.
 template <typename R, int RECON, int NBT, int LPS, bool NT, typename In>
 __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<R>* __restrict__ lf,
-                                             const cplx<R>* __restrict__ lb, int cb, const Site& s,
+                                             const cplx<R>* __restrict__ lb,
+                                             const cplx<R>* __restrict__ lf3,
+                                             const cplx<R>* __restrict__ lb3, int cb, const Site& s,
                                              int dp, const In& in, unsigned act,
                                              cplx<R> (&acc)[NBT][3]) {
-#define QX_HOP(H) \
-  if (LPS == 1 || (H) % LPS == dp) stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, cb, s, in, act, acc)
+#define QX_HOP(H)                               \
+  if (LPS == 1 || (H) % LPS == dp)              \
+  stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, act, acc)
   QX_HOP(0);
   QX_HOP(1);
   QX_HOP(2);
@@ -284,6 +316,16 @@ __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<R>* __rest
   QX_HOP(5);
   QX_HOP(6);
   QX_HOP(7);
+  if constexpr (RECON == 36) {
+    QX_HOP(8);
+    QX_HOP(9);
+    QX_HOP(10);
+    QX_HOP(11);
+    QX_HOP(12);
+    QX_HOP(13);
+    QX_HOP(14);
+    QX_HOP(15);
+  }
 #undef QX_HOP
 }
 
@@ -295,12 +337,25 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __rest
                                              unsigned act, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   const size_t hv = (size_t)g.hv;
+  // links [parity][mu][e][cb]; the improved operator's three-hop links follow
+  // the one-hop ones in the same layout
   const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
   const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
-  if (g.stream_links)
-    stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, cb, s, dp, in, act, acc);
-  else
-    stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, cb, s, dp, in, act, acc);
+  const cplx<R>* lf3 = links + (size_t)(2 + pout) * 4 * E * hv;
+  const cplx<R>* lb3 = links + (size_t)(3 - pout) * 4 * E * hv;
+  if constexpr (RECON == 36) {
+    Site s3 = s;
+    three_hop_geometry(g, cb, s3);
+    if (g.stream_links)
+      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s3, dp, in, act, acc);
+    else
+      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s3, dp, in, act, acc);
+  } else {
+    if (g.stream_links)
+      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s, dp, in, act, acc);
+    else
+      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s, dp, in, act, acc);
+  }
 }
 
 template <typename R, int NBT>

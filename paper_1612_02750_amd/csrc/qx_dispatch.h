@@ -7,12 +7,16 @@ namespace qx {
 
 inline unsigned grid_for(size_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// recon: link storage, 18 or 12 reals per link, or 36 for the improved
+// operator (one-hop and three-hop links of 18 reals each).
 template <typename F>
 hipError_t with_prec_recon(int prec, int recon, F&& f) {
   if (prec == 0 && recon == 18) return f.template operator()<double, 18>();
   if (prec == 0 && recon == 12) return f.template operator()<double, 12>();
   if (prec == 1 && recon == 18) return f.template operator()<float, 18>();
   if (prec == 1 && recon == 12) return f.template operator()<float, 12>();
+  if (prec == 0 && recon == 36) return f.template operator()<double, 36>();
+  if (prec == 1 && recon == 36) return f.template operator()<float, 36>();
   return hipErrorInvalidValue;
 }
 

@@ -96,7 +96,7 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
   const size_t field = (size_t)3 * g.hv * csz;
   const int per = sources_per_pass(sh, csz);
   const unsigned grid = grid_for(g.hv, kTile);
-  const size_t link_bytes = (size_t)8 * g.hv * (recon == 12 ? 6 : 9) * csz;
+  const size_t link_bytes = (size_t)8 * g.hv * (recon / 2) * csz;
   for (int k0 = 0; k0 < nsrc; k0 += per) {
     const int n = std::min(per, nsrc - k0);
     const int threads = 64 * sh.lps * shape_groups(sh, n);

@@ -905,8 +905,9 @@ __global__ void __launch_bounds__(256) k_ru_finish(const SysDesc* __restrict__ s
 // ================================================================ launchers
 
 bool engine_supported(const EngineCfg& c) {
-  const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) && (c.recon_lo == 18 || c.recon_lo == 12);
-  const bool ok_hi = c.recon_hi == 18 || c.recon_hi == 12;
+  const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) &&
+                     (c.recon_lo == 18 || c.recon_lo == 12 || c.recon_lo == 36);
+  const bool ok_hi = c.recon_hi == 18 || c.recon_hi == 12 || c.recon_hi == 36;
   const bool ok_shape = nbt_lps_instantiated(c.shape.nbt, c.shape.lps) &&
                         shape_ok(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo)) &&
                         shape_groups(c.shape, c.nsrc_max) <= max_waves(c.shape.nbt, 16);
@@ -1039,17 +1040,18 @@ hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
   SrcState* copy = c.fused ? c.d_st1 : nullptr;
   hipError_t e = with_prec(c.prec_lo, [&]<typename Rlo>() {
     return with_nbt(c.shape.nbt, [&]<int NBT>() {
-      if (c.recon_hi == 12) {
-        hipLaunchKernelGGL((k_ru_doe<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
+      auto ru = [&]<int RH>() {
+        hipLaunchKernelGGL((k_ru_doe<Rlo, RH, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
                            c.shape.xcd);
-        hipLaunchKernelGGL((k_ru_residual<Rlo, 12, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
+        hipLaunchKernelGGL((k_ru_residual<Rlo, RH, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
                            c.d_st, c.shape.xcd, copy);
-      } else {
-        hipLaunchKernelGGL((k_ru_doe<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                           c.shape.xcd);
-        hipLaunchKernelGGL((k_ru_residual<Rlo, 18, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
-                           c.d_st, c.shape.xcd, copy);
-      }
+      };
+      if (c.recon_hi == 12)
+        ru.template operator()<12>();
+      else if (c.recon_hi == 36)
+        ru.template operator()<36>();
+      else
+        ru.template operator()<18>();
       return hipGetLastError();
     });
   });

@@ -119,13 +119,91 @@ __global__ void __launch_bounds__(256) k_index_maps(Geo g, int32_t* __restrict__
   }
 }
 
+// Links of the improved operator (one-hop and Naik three-hop terms): for
+// every (mu, site x) the one-hop link 9/8 eta bc U_mu(x) and the three-hop
+// transporter -1/24 eta bc(x) bc(x+mu) bc(x+2mu) U_mu(x) U_mu(x+mu) U_mu(x+2mu)
+// (eta_mu is the same at the three sites), products in FP64.  Layout
+// [kind][parity][mu][9][cb]: kind 0 the one-hop links, kind 1 the three-hop.
+template <typename R>
+__global__ void __launch_bounds__(256) k_pack_gauge_naik(Geo g, const cplx<double>* __restrict__ U,
+                                                         cplx<R>* __restrict__ out) {
+  const int64_t V = 2 * (int64_t)g.hv;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * V) return;
+  const int mu = (int)(i / V);
+  const int lex = (int)(i - mu * V);
+  int x[4];
+  {
+    int t = lex;
+    x[0] = t % g.L0;
+    t /= g.L0;
+    x[1] = t % g.L1;
+    t /= g.L1;
+    x[2] = t % g.L2;
+    x[3] = t / g.L2;
+  }
+  const int L[4] = {g.L0, g.L1, g.L2, g.L3};
+  const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+  const int cb = lex >> 1;
+  const double eta = (double)eta_sign(mu, x[0], x[1], x[2]);
+  // walk three links along mu
+  cplx<double> P[9];
+  double sgn = 1.0;
+  int y[4] = {x[0], x[1], x[2], x[3]};
+  for (int step = 0; step < 3; ++step) {
+    const int ly = y[0] + L[0] * (y[1] + L[1] * (y[2] + L[2] * y[3]));
+    const cplx<double>* u = U + ((int64_t)mu * V + ly) * 9;
+    if (mu == 3 && g.anti_t && y[3] == L[3] - 1) sgn = -sgn;
+    if (step == 0) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) P[e] = u[e];
+      cplx<R>* o = out + (size_t)(p * 4 + mu) * 9 * g.hv + cb;
+      const double c = 1.125 * eta * sgn;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) o[(size_t)e * g.hv] = {(R)(c * P[e].re), (R)(c * P[e].im)};
+    } else {
+      cplx<double> Q[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          cplx<double> t = {0.0, 0.0};
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const cplx<double> m = cmul(P[3 * a + c], u[3 * c + b]);
+            t.re += m.re;
+            t.im += m.im;
+          }
+          Q[3 * a + b] = t;
+        }
+#pragma unroll
+      for (int e = 0; e < 9; ++e) P[e] = Q[e];
+    }
+    y[mu] = y[mu] + 1 == L[mu] ? 0 : y[mu] + 1;
+  }
+  cplx<R>* o = out + (size_t)(8 + p * 4 + mu) * 9 * g.hv + cb;
+  const double c = (-1.0 / 24.0) * eta * sgn;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) o[(size_t)e * g.hv] = {(R)(c * P[e].re), (R)(c * P[e].im)};
+}
+
 hipError_t launch_pack_gauge(const Geo& g, const void* U, int prec, int recon, void* packed,
                              unsigned long long* err_bits, hipStream_t s) {
   const size_t n = 8 * (size_t)g.hv;
+  if (recon == 36)
+    return with_prec(prec, [&]<typename R>() {
+      hipLaunchKernelGGL(k_pack_gauge_naik<R>, dim3(grid_for(n, 256)), dim3(256), 0, s, g,
+                         (const cplx<double>*)U, (cplx<R>*)packed);
+      return hipGetLastError();
+    });
   return with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
-    hipLaunchKernelGGL((k_pack_gauge<R, RECON>), dim3(grid_for(n, 256)), dim3(256), 0, s, g,
-                       (const cplx<double>*)U, (cplx<R>*)packed, err_bits);
-    return hipGetLastError();
+    if constexpr (RECON == 36) {
+      return hipErrorInvalidValue;
+    } else {
+      hipLaunchKernelGGL((k_pack_gauge<R, RECON>), dim3(grid_for(n, 256)), dim3(256), 0, s, g,
+                         (const cplx<double>*)U, (cplx<R>*)packed, err_bits);
+      return hipGetLastError();
+    }
   });
 }
 

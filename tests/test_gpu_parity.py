@@ -620,3 +620,99 @@ def test_engines_uneven_batch(qx):
                 rr = oracle.true_residual(dims, U, masses[s], b[s], x[s])
                 assert rr <= 1e-10 and stats[j].status == 0, (engine, dims, s, rr)
                 j += 1
+
+
+# ------------------------------------------------------------ Naik term (f1)
+
+NAIK_SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (4, 2, 6, 8), (6, 4, 2, 8), (8, 8, 8, 12)]
+
+
+@pytest.mark.parametrize("dims", NAIK_SHAPES)
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 1e-5)])
+def test_naik_dslash_parity(qx, dims, prec, tol):
+    """Improved operator (one-hop x 9/8 and three-hop x -1/24) against the oracle, both
+    parities and boundary conditions; extents 2 and 4 wrap the three-hop neighbours."""
+    for anti in (False, True):
+        lat = qx.Lattice(dims, antiperiodic_t=anti)
+        flags = oracle.NAIK | (oracle.BC_T_ANTIPERIODIC if anti else 0)
+        U = gauge(dims, seed=31)
+        g = qx.Gauge(lat, to_dev(U), prec, qx.RECON_NAIK)
+        for pout in (0, 1):
+            chi = synth.gauss_source(2, lat.hv, 32 + pout)
+            out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), pout, 2), 2,
+                                    prec))
+            for k in range(2):
+                ref = oracle.dslash_eo(dims, U, chi[k], pout, flags)
+                assert rel(out[k], ref) <= tol, (anti, pout, k)
+
+
+@pytest.mark.parametrize("nbt,lps", SHAPES_NL)
+def test_naik_launch_shapes(qx, nbt, lps):
+    dims = (6, 4, 2, 8)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    U = gauge(dims, seed=33)
+    nrhs = 5
+    chi = synth.gauss_source(nrhs, lat.hv, 34)
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-5)):
+        g = qx.Gauge(lat, to_dev(U), prec, qx.RECON_NAIK)
+        g.set_launch(nrhs, nbt, lps, (nbt + lps) % 4)
+        out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), 1, nrhs), nrhs,
+                                prec))
+        for k in range(nrhs):
+            ref = oracle.dslash_eo(dims, U, chi[k], 1, oracle.NAIK | oracle.BC_T_ANTIPERIODIC)
+            assert rel(out[k], ref) <= tol, (prec, nbt, lps, k)
+
+
+def test_naik_dslash_32_4(qx):
+    """Full-size lattice: FP64 and FP32 improved operator against the oracle."""
+    dims = (32, 32, 32, 32)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=0)
+    chi = synth.gauss_source(1, lat.hv, 1)
+    ref = oracle.dslash_eo(dims, U, chi[0], 0, oracle.NAIK)
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-5)):
+        g = qx.Gauge(lat, to_dev(U), prec, qx.RECON_NAIK)
+        out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), 0, 1), 1, prec))
+        assert rel(out[0], ref) <= tol
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_naik_cg_engines(qx, mixed):
+    """CG on the improved operator to 1e-10 (oracle-measured), under every engine, with
+    bitwise-identical results; three sources with different masses."""
+    dims = (8, 4, 6, 8)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    flags = oracle.NAIK | oracle.BC_T_ANTIPERIODIC
+    U = gauge(dims, seed=35)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64", qx.RECON_NAIK)
+    glo = qx.Gauge(lat, Ud, "f32", qx.RECON_NAIK) if mixed else None
+    masses = [0.05, 0.2, 0.1]
+    b = synth.gauss_source(3, lat.hv, 36)
+    runs = [qx.cg(g64, to_dev(b), masses, glo=glo, engine=e)
+            for e in (qx.ENGINE_LAUNCH, qx.ENGINE_FUSED, qx.ENGINE_PERSISTENT)]
+    xa, sa = runs[0]
+    for xb, sb in runs[1:]:
+        assert np.array_equal(to_host(xa), to_host(xb))
+        assert [s.iters for s in sa] == [s.iters for s in sb]
+    _check_solution(dims, U, masses, b, to_host(xa), sa, flags=flags)
+
+
+def test_naik_apply_A_and_rejections(qx):
+    dims = (4, 6, 4, 4)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=37)
+    Ud = to_dev(U)
+    gn = qx.Gauge(lat, Ud, "f64", qx.RECON_NAIK)
+    v = synth.gauss_source(2, lat.hv, 38)
+    out = to_host(qx.unpack(lat, qx.apply_A(gn, qx.pack(lat, to_dev(v), "f64"), [0.1, 0.3]), 2,
+                            "f64"))
+    for k, m in enumerate((0.1, 0.3)):
+        assert rel(out[k], oracle.apply_A(dims, U, m, v[k], oracle.NAIK)) <= 1e-13
+    # the force is implemented for the one-hop operator only
+    with pytest.raises(qx.QXError):
+        qx.force(gn, to_dev(v[:1]), 0.1)
+    # mixed solves need both handles of the same operator
+    g32 = qx.Gauge(lat, Ud, "f32", 18)
+    with pytest.raises(qx.QXError):
+        qx.cg(gn, to_dev(v[:1]), [0.1], glo=g32)
