@@ -18,7 +18,15 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqx.so")
-SOURCES = ["qx_engine.hip", "qx_dslash.hip", "qx_kernels.hip", "qx_api.cpp"]
+# (source, object name, extra flags): the engine's instantiation unit is
+# compiled once per (inner precision, link storage) pair, in parallel
+UNITS = [("qx_engine_inst.hip", f"qx_engine_{r}_{n}", [f"-DQX_R={r}", f"-DQX_RECON={n}"])
+         for r in ("float", "double") for n in (18, 12, 36)] + [
+    ("qx_engine.hip", "qx_engine", []),
+    ("qx_dslash.hip", "qx_dslash", []),
+    ("qx_kernels.hip", "qx_kernels", []),
+    ("qx_api.cpp", "qx_api", []),
+]
 ARCH = "gfx950"
 
 
@@ -42,9 +50,10 @@ def _flags():
     ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + _flags()
+def _compile(unit) -> str:
+    src, name, extra = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + _flags() + extra
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -54,8 +63,9 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libqx.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    workers = min(len(UNITS), os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

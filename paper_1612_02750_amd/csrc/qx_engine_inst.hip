@@ -1,0 +1,22 @@
+// Instantiates the CG engine's kernels and launch sequences for one (inner
+// precision, link storage) pair, given at compile time as QX_R (float or
+// double) and QX_RECON (12, 18 or 36); the build compiles this file once per
+// pair so the instantiations compile in parallel.
+#include "qx_engine_kernels.h"
+
+#if !defined(QX_R) || !defined(QX_RECON)
+#error "compile with -DQX_R=<float|double> -DQX_RECON=<12|18|36>"
+#endif
+
+namespace qx {
+
+template hipError_t iteration_impl<QX_R, QX_RECON>(const EngineCfg&, int, hipStream_t);
+template hipError_t reliable_update_impl<QX_R, QX_RECON>(const EngineCfg&, hipStream_t);
+template int persistent_per_cu_impl<QX_R, QX_RECON>(const EngineCfg&);
+template hipError_t persistent_impl<QX_R, QX_RECON>(const EngineCfg&, int, GridSync*, int,
+                                                     long long, hipStream_t);
+#if QX_RECON == 18
+template hipError_t init_impl<QX_R>(const EngineCfg&, int, hipStream_t);
+#endif
+
+}  // namespace qx
