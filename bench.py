@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FLOPS_SITE = 570
+FLOPS_SITE_NAIK = 1146  # 16 SU(3) x colour-vector products + 15 vector sums
 
 
 def parse():
@@ -131,7 +132,8 @@ def dominant_kernel(torch, qx, lat, g32, bd, reps, plain=False):
     return t_k, achieved
 
 
-def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key, out):
+def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key, out,
+                  flops_site=FLOPS_SITE):
     from paper_1612_02750_amd import synth
 
     src = torch.from_numpy(synth.gauss_source(nrhs, lat.hv, seed)).cuda()
@@ -146,7 +148,7 @@ def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key
     by = (link_b + 2 * vec_b * nrhs) * lat.hv
     out[key] = {
         "us": round(t * 1e6, 2),
-        "gflops": round(FLOPS_SITE * nrhs * lat.hv / t / 1e9, 1),
+        "gflops": round(flops_site * nrhs * lat.hv / t / 1e9, 1),
         "gbs_algorithmic": round(by / t / 1e9, 1),
         "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
         "shape": list(g.launch(nrhs)),
@@ -159,8 +161,10 @@ def dslash_sweep(torch, qx, tune=True, plain=False):
     Infinity Cache, FP64 18-real ones do not) with one and twelve sources, and
     at 48^4 (every operand far beyond the cache) with one source.  Compulsory
     bytes per output site: 8 links + one input and one output colour vector
-    per source.  tune=False keeps the shapes already known (the tuning cache
-    of an earlier run); plain=True only launches (for counter runs)."""
+    per source.  The improved operator (Naik term, link storage 36) is
+    measured beside it: 16 links per site, 1146 flops per output site.
+    tune=False keeps the shapes already known (the tuning cache of an earlier
+    run); plain=True only launches (for counter runs)."""
     from paper_1612_02750_amd import synth
 
     res = {}
@@ -176,6 +180,13 @@ def dslash_sweep(torch, qx, tune=True, plain=False):
             _dslash_point(torch, qx, g, lat32, nrhs, 2, link_b, vec_b, 50, plain,
                           f"32^4-{prec}-{recon}-nrhs{nrhs}", res)
         del g
+    for prec, link_b, vec_b in (("f32", 1152, 24), ("f64", 2304, 48)):
+        g = qx.Gauge(lat32, U32, prec, qx.RECON_NAIK)
+        if tune:
+            g.tune(1)
+        _dslash_point(torch, qx, g, lat32, 1, 2, link_b, vec_b, 50, plain,
+                      f"32^4-{prec}-naik-nrhs1", res, flops_site=FLOPS_SITE_NAIK)
+        del g
     del U32
     # link values do not change the traffic: a unit gauge field built on the device
     dims48 = (48, 48, 48, 48)
@@ -188,6 +199,13 @@ def dslash_sweep(torch, qx, tune=True, plain=False):
             g.tune(1)
         _dslash_point(torch, qx, g, lat48, 1, 3, link_b, vec_b, 30, plain,
                       f"48^4-{prec}-{recon}-nrhs1", res)
+        del g
+    for prec, link_b, vec_b in (("f32", 1152, 24), ("f64", 2304, 48)):
+        g = qx.Gauge(lat48, U48, prec, qx.RECON_NAIK)
+        if tune:
+            g.tune(1)
+        _dslash_point(torch, qx, g, lat48, 1, 3, link_b, vec_b, 20, plain,
+                      f"48^4-{prec}-naik-nrhs1", res, flops_site=FLOPS_SITE_NAIK)
         del g
     del U48
     return res
@@ -212,6 +230,35 @@ def copy_probe(torch, qx, nb=1 << 30, timed=True):
     log(f"copy probe: {nb} bytes, {t_copy * 1e6:.1f} us, {copy_gbs:.0f} GB/s (read + write); "
         f"read probe: {t_read * 1e6:.1f} us, {read_gbs:.0f} GB/s")
     return copy_gbs, read_gbs
+
+
+def naik_cg(torch, qx, synth):
+    """The improved operator (Naik term) on the step's 16^4 system: mixed and
+    FP64 time-to-solution to 1e-10."""
+    dims, m, eps, tol = (16, 16, 16, 16), 0.05, 0.3, 1e-10
+    lat = qx.Lattice(dims)
+    Ud = torch.from_numpy(synth.weak_gauge(dims, eps, 0)).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", qx.RECON_NAIK)
+    g32 = qx.Gauge(lat, Ud, "f32", qx.RECON_NAIK)
+    g64.tune(1)
+    g32.tune(1)
+    bd = torch.from_numpy(synth.gauss_source(1, lat.hv, 1)).cuda()
+    out = {"workload": "16^4 weak-field links eps=0.3, improved operator (Naik), m=0.05, tol 1e-10"}
+    for name, glo, mode in (("mixed", g32, qx.CG_MIXED_F32), ("fp64", None, qx.CG_FP64)):
+        x = torch.empty_like(bd)
+        B = qx.Batch([(g64, glo, bd, [m], x)], tol=tol, mode=mode)
+        B.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            st = B.solve()
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+        out[f"{name}_iters"] = st[0].iters
+        out[f"{name}_true_rel_residual"] = st[0].true_rel_residual
+    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms"] / out["mixed_ms"], 3)
+    log(f"16^4 Naik CG: {out}")
+    return out
 
 
 def multi_rhs(torch, qx, synth):
@@ -376,6 +423,7 @@ def main():
     copy_gbs, read_gbs = copy_probe(torch, qx)
 
     multi = None if args.no_multi else multi_rhs(torch, qx, synth)
+    naik = naik_cg(torch, qx, synth)
 
 
     # ------------------------------------------------------------ CPU oracle
@@ -443,6 +491,7 @@ def main():
         },
         "dslash_sweep": d32,
         "multi_rhs_32^4": multi,
+        "naik_cg_16^4": naik,
         "copy_probe_gbs": round(copy_gbs, 1),
         "read_probe_gbs": round(read_gbs, 1),
         "cpu_baseline": cpu,

@@ -463,6 +463,17 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   int nb = 1;
   for (const auto& s : B->specs) nb = std::max(nb, s.nrhs);
   LaunchShape sh = shape_for(s0.glo, nb);
+  // The D_oe pass of the fused sequence loads r and p at every neighbour;
+  // with all hops of one source in one wavefront that spills, so on batches
+  // the fused sequence serves (AUTO) every engine splits the hops in two (the
+  // engines agree bit for bit for one batch).
+  int max_nblk = 0;
+  for (const auto& s : B->specs) max_nblk = std::max(max_nblk, (s.g64->geo.hv + kTile - 1) / kTile);
+  if (sh.nbt == 1 && sh.lps == 1 && max_nblk <= kFuseMaxBlocks) {
+    LaunchShape s2 = sh;
+    s2.lps = 2;
+    if (shape_ok(s2, nb, cplx_bytes(prec_lo))) sh = s2;
+  }
   if (!shape_ok(sh, nb, cplx_bytes(prec_lo)) || !nbt_lps_instantiated(sh.nbt, sh.lps)) {
     // the first default that takes nb sources in one block
     const LaunchShape cands[4] = {{1, 2, 1}, {2, 2, 1}, {4, 2, 1}, {4, 1, 1}};
