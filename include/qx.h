@@ -286,6 +286,57 @@ int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_cg_params_t*
 int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_U, double* F,
                  hipStream_t stream);
 
+/* -------------------------------------------------- molecular dynamics */
+
+/* Hybrid Monte Carlo (the paper reports HMC gauge generation as in progress,
+   Sec. 4): Wilson plaquette action, pseudofermion action phi^dag A^-1 phi,
+   momenta p^a_mu(x) (a = 1..8, P = sum_a p^a lambda_a / 2), Hamiltonian
+   H = 1/2 sum p^2 + S_g + S_f, leapfrog integration of
+   U <- exp(i eps P) U,  p^a <- p^a - eps F^a,  F^a = d/dw S(exp(i w T_a) U)|_0.
+   Layouts (device, FP64): U canonical complex128 [4][V][3][3], p double
+   [4][V][8], phi canonical [V/2][3].  ws for the reductions: at least
+   qx_md_workspace_bytes (any params) or 8448 bytes. */
+
+/* S_g = beta sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3), written to *S (host).
+   Synchronises the stream. */
+int qx_gauge_action(const qx_lattice_t* lat, const void* U, double beta, void* ws,
+                    size_t ws_bytes, double* S, hipStream_t stream);
+/* Link gradient of S_g in the convention of qx_force: G = -(beta/3) A^dag,
+   A_mu(x) = sum_{nu != mu} [U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag
+                            + U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)].
+   accumulate != 0 adds it to G (e.g. to the pseudofermion gradient). */
+int qx_gauge_force(const qx_lattice_t* lat, const void* U, double beta, void* G, int accumulate,
+                   hipStream_t stream);
+/* p^a -= eps F^a, F^a = Re[i tr(T_a U G^dag)] for a link gradient G. */
+int qx_md_update_momenta(const qx_lattice_t* lat, const void* U, const void* G, double eps,
+                         double* p, hipStream_t stream);
+/* U <- exp(i eps sum_a p^a T_a) U (scaling and squaring of a 16-term series). */
+int qx_md_update_links(const qx_lattice_t* lat, const double* p, double eps, void* U,
+                       hipStream_t stream);
+/* K = 1/2 sum p^2 (host).  Synchronises the stream. */
+int qx_md_kinetic(const qx_lattice_t* lat, const double* p, void* ws, size_t ws_bytes, double* K,
+                  hipStream_t stream);
+
+typedef struct {
+  double beta;        /* gauge coupling */
+  double mass;        /* staggered mass of the pseudofermion action */
+  double eps;         /* step size */
+  int nsteps;         /* leapfrog steps (>= 1) */
+  qx_cg_params_t cg;  /* solver of the pseudofermion force */
+} qx_md_params_t;
+
+int qx_md_workspace_bytes(const qx_lattice_t* lat, const qx_md_params_t* params, size_t* bytes);
+
+/* One leapfrog trajectory of nsteps steps: U and p are advanced in place; the
+   gauge handles g64 (FP64) and glo (the inner precision of a mixed solve, or
+   NULL) must be loaded from U's lattice and are repacked from U after every
+   link update.  phi NULL: pure gauge.  Returns H at the start and the end and
+   the total CG iterations of the force solves.  One-hop operator only
+   (QX_EINVAL for the Naik link storage).  Synchronises the stream. */
+int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_params_t* params, void* U,
+                     double* p, const void* phi, void* ws, size_t ws_bytes, double* H_start,
+                     double* H_end, int* cg_iters, hipStream_t stream);
+
 /* ------------------------------------------------------------- tuning */
 
 /* Pick the launch shape of the stencil kernels for this gauge handle and nrhs

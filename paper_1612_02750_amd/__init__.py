@@ -41,6 +41,11 @@ class _Params(ctypes.Structure):
                 ("engine", ctypes.c_int)]
 
 
+class _MdParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mass", ctypes.c_double), ("eps", ctypes.c_double),
+                ("nsteps", ctypes.c_int), ("cg", _Params)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
                 ("reliable_updates", ctypes.c_int), ("true_rel_residual", ctypes.c_double),
@@ -100,6 +105,13 @@ def load():
         "qx_force": ([_P, _P, _P, _I, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P, _P], _I),
         "qx_force_su3": ([_P, _P, _P, _P, _P], _I),
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
+        "qx_gauge_action": ([_P, _P, ctypes.c_double, _P, _SZ, _P, _P], _I),
+        "qx_gauge_force": ([_P, _P, ctypes.c_double, _P, _I, _P], _I),
+        "qx_md_update_momenta": ([_P, _P, _P, ctypes.c_double, _P, _P], _I),
+        "qx_md_update_links": ([_P, _P, ctypes.c_double, _P, _P], _I),
+        "qx_md_kinetic": ([_P, _P, _P, _SZ, _P, _P], _I),
+        "qx_md_workspace_bytes": ([_P, _P, _P], _I),
+        "qx_md_trajectory": ([_P, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _P, _P], _I),
         "qx_time_dslash": ([_P, _I, _I, _P, _P, _I, _P, _P], _I),
         "qx_get_launch": ([_P, _I, _P, _P, _P], _I),
         "qx_set_launch": ([_P, _I, _I, _I, _I], _I),
@@ -401,6 +413,73 @@ def force(g64: Gauge, phi, mass: float, glo: Optional[Gauge] = None, tol=1e-10,
                       float(mass), _ptr(phi), _ptr(G), ctypes.byref(S), _ptr(x), _ptr(ws),
                       ws.numel(), st, _stream(stream)))
     return S.value, G, x, _stats(st, nrhs)
+
+
+# ------------------------------------------------------- molecular dynamics
+
+_MD_RED_BYTES = 8200 + 256
+
+
+def gauge_action(lat: Lattice, U, beta: float, stream=None) -> float:
+    """Wilson plaquette action beta sum_{x, mu<nu} (1 - Re tr P_munu / 3)."""
+    ws = _bytes(_MD_RED_BYTES)
+    S = ctypes.c_double()
+    _check(load().qx_gauge_action(lat._h, _ptr(U), float(beta), _ptr(ws), ws.numel(),
+                                  ctypes.byref(S), _stream(stream)))
+    return S.value
+
+
+def gauge_force(lat: Lattice, U, beta: float, G=None, accumulate=False, stream=None):
+    """Link gradient of the plaquette action, -(beta/3) A^dag (4, V, 3, 3); added to G
+    when accumulate."""
+    torch = _torch()
+    if G is None:
+        G = torch.empty((4, lat.V, 3, 3), dtype=torch.complex128, device="cuda")
+    _check(load().qx_gauge_force(lat._h, _ptr(U), float(beta), _ptr(G), 1 if accumulate else 0,
+                                 _stream(stream)))
+    return G
+
+
+def md_update_momenta(lat: Lattice, U, G, eps: float, p, stream=None):
+    """p^a -= eps Re[i tr(T_a U G^dag)] in place; p float64 (4, V, 8)."""
+    _check(load().qx_md_update_momenta(lat._h, _ptr(U), _ptr(G), float(eps), _ptr(p),
+                                       _stream(stream)))
+    return p
+
+
+def md_update_links(lat: Lattice, p, eps: float, U, stream=None):
+    """U <- exp(i eps sum_a p^a T_a) U in place."""
+    _check(load().qx_md_update_links(lat._h, _ptr(p), float(eps), _ptr(U), _stream(stream)))
+    return U
+
+
+def md_kinetic(lat: Lattice, p, stream=None) -> float:
+    ws = _bytes(_MD_RED_BYTES)
+    K = ctypes.c_double()
+    _check(load().qx_md_kinetic(lat._h, _ptr(p), _ptr(ws), ws.numel(), ctypes.byref(K),
+                                _stream(stream)))
+    return K.value
+
+
+def md_trajectory(g64: Gauge, U, p, beta: float, eps: float, nsteps: int, phi=None,
+                  mass: float = 0.1, glo: Optional[Gauge] = None, tol=1e-10, max_iter=100000,
+                  mode=None, delta=0.1, stream=None):
+    """One leapfrog trajectory: U (4, V, 3, 3) complex128 and p (4, V, 8) float64 advanced
+    in place; g64 (and glo) are repacked from U.  Returns (H_start, H_end, CG iterations)."""
+    L = load()
+    if mode is None:
+        mode = CG_MIXED_F32 if glo is not None else CG_FP64
+    mp = _MdParams(float(beta), float(mass), float(eps), int(nsteps),
+                   _params(tol, max_iter, mode, delta, 0, 0))
+    n = ctypes.c_size_t()
+    _check(L.qx_md_workspace_bytes(g64.lat._h, ctypes.byref(mp), ctypes.byref(n)))
+    ws = _bytes(n.value)
+    h0, h1, it = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    _check(L.qx_md_trajectory(g64._h, glo._h if glo is not None else None, ctypes.byref(mp),
+                              _ptr(U), _ptr(p), _ptr(phi) if phi is not None else None, _ptr(ws),
+                              ws.numel(), ctypes.byref(h0), ctypes.byref(h1), ctypes.byref(it),
+                              _stream(stream)))
+    return h0.value, h1.value, it.value
 
 
 def force_from_fields(g64: Gauge, x, lam, stream=None):

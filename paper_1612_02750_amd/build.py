@@ -25,6 +25,7 @@ UNITS = [("qx_engine_inst.hip", f"qx_engine_{r}_{n}", [f"-DQX_R={r}", f"-DQX_REC
     ("qx_engine.hip", "qx_engine", []),
     ("qx_dslash.hip", "qx_dslash", []),
     ("qx_kernels.hip", "qx_kernels", []),
+    ("qx_hmc.hip", "qx_hmc", []),
     ("qx_api.cpp", "qx_api", []),
 ]
 ARCH = "gfx950"

@@ -954,6 +954,154 @@ extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, in
   return QX_OK;
 }
 
+// ------------------------------------------------------- molecular dynamics
+
+namespace {
+constexpr int kMdBlocks = 1024;  // partial sums of the action and kinetic-energy reductions
+size_t md_reduce_bytes() { return align_up(sizeof(double) * (kMdBlocks + 1), 256); }
+
+int md_sum(double* ws, double* out_host, hipStream_t s) {
+  QX_HIP(hipMemcpyAsync(out_host, ws + kMdBlocks, sizeof(double), hipMemcpyDeviceToHost, s),
+         "md: readback");
+  QX_HIP(hipStreamSynchronize(s), "md: synchronise");
+  return QX_OK;
+}
+}  // namespace
+
+extern "C" int qx_gauge_action(const qx_lattice_t* lat, const void* U, double beta, void* ws,
+                               size_t ws_bytes, double* S, hipStream_t stream) {
+  if (!lat || !U || !ws || !S || ws_bytes < md_reduce_bytes())
+    return fail(QX_EINVAL, "qx_gauge_action: bad argument");
+  double* part = (double*)ws;
+  QX_HIP(launch_plaquette_sum(lat->geo, U, part, kMdBlocks, part + kMdBlocks, stream),
+         "qx_gauge_action");
+  double sum = 0.0;
+  int rc = md_sum(part, &sum, stream);
+  if (rc) return rc;
+  *S = beta * sum;
+  return QX_OK;
+}
+
+extern "C" int qx_gauge_force(const qx_lattice_t* lat, const void* U, double beta, void* G,
+                              int accumulate, hipStream_t stream) {
+  if (!lat || !U || !G) return fail(QX_EINVAL, "qx_gauge_force: bad argument");
+  QX_HIP(launch_gauge_grad(lat->geo, U, beta, G, accumulate ? 1 : 0, stream), "qx_gauge_force");
+  return QX_OK;
+}
+
+extern "C" int qx_md_update_momenta(const qx_lattice_t* lat, const void* U, const void* G,
+                                    double eps, double* p, hipStream_t stream) {
+  if (!lat || !U || !G || !p) return fail(QX_EINVAL, "qx_md_update_momenta: bad argument");
+  QX_HIP(launch_mom_update(lat->geo, U, G, eps, p, stream), "qx_md_update_momenta");
+  return QX_OK;
+}
+
+extern "C" int qx_md_update_links(const qx_lattice_t* lat, const double* p, double eps, void* U,
+                                  hipStream_t stream) {
+  if (!lat || !U || !p) return fail(QX_EINVAL, "qx_md_update_links: bad argument");
+  QX_HIP(launch_link_update(lat->geo, p, eps, U, stream), "qx_md_update_links");
+  return QX_OK;
+}
+
+extern "C" int qx_md_kinetic(const qx_lattice_t* lat, const double* p, void* ws, size_t ws_bytes,
+                             double* K, hipStream_t stream) {
+  if (!lat || !p || !ws || !K || ws_bytes < md_reduce_bytes())
+    return fail(QX_EINVAL, "qx_md_kinetic: bad argument");
+  double* part = (double*)ws;
+  QX_HIP(launch_sumsq(p, 64 * (int64_t)lat->geo.hv, part, kMdBlocks, part + kMdBlocks, stream),
+         "qx_md_kinetic");
+  double sum = 0.0;
+  int rc = md_sum(part, &sum, stream);
+  if (rc) return rc;
+  *K = 0.5 * sum;
+  return QX_OK;
+}
+
+extern "C" int qx_md_workspace_bytes(const qx_lattice_t* lat, const qx_md_params_t* p,
+                                     size_t* bytes) {
+  if (!lat || !p || !bytes) return fail(QX_EINVAL, "qx_md_workspace_bytes: bad argument");
+  size_t f = 0;
+  int rc = qx_force_workspace_bytes(lat, &p->cg, 1, &f);
+  if (rc) return rc;
+  *bytes = md_reduce_bytes() + align_up((size_t)lat->V * 4 * 9 * 16, 256) + f;
+  return QX_OK;
+}
+
+extern "C" int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_params_t* p,
+                                void* U, double* mom, const void* phi, void* ws, size_t ws_bytes,
+                                double* H_start, double* H_end, int* cg_iters,
+                                hipStream_t stream) {
+  if (!g64 || !p || !U || !mom || !ws || !H_start || !H_end || p->nsteps < 1)
+    return fail(QX_EINVAL, "qx_md_trajectory: bad argument");
+  if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "qx_md_trajectory: g64 must be FP64");
+  if (g64->recon == QX_RECON_NAIK || (glo && glo->recon == QX_RECON_NAIK))
+    return fail(QX_EINVAL, "qx_md_trajectory: the force is implemented for the one-hop operator");
+  if (glo && !same_lattice(g64, glo))
+    return fail(QX_EINVAL, "qx_md_trajectory: g64 and glo are on different lattices");
+  qx_lattice lat{};
+  memcpy(lat.dims, g64->dims, sizeof lat.dims);
+  lat.flags = g64->flags;
+  lat.geo = g64->geo;
+  lat.V = 2 * (int64_t)g64->geo.hv;
+  size_t need = 0;
+  int rc = qx_md_workspace_bytes(&lat, p, &need);
+  if (rc) return rc;
+  if (ws_bytes < need) return fail(QX_ENOMEM, "qx_md_trajectory: workspace of %zu bytes, %zu needed",
+                                   ws_bytes, need);
+  char* w = (char*)ws;
+  double* red = (double*)w;
+  void* grad = w + md_reduce_bytes();
+  void* fws = w + md_reduce_bytes() + align_up((size_t)lat.V * 4 * 9 * 16, 256);
+  const size_t fws_bytes = need - (md_reduce_bytes() + align_up((size_t)lat.V * 4 * 9 * 16, 256));
+  int iters = 0;
+  // gradient of S_g + S_f at the current links into grad; S_f to *Sf
+  auto force = [&](double* Sf) -> int {
+    *Sf = 0.0;
+    if (phi) {
+      qx_cg_stats_t st{};
+      int r = qx_force(g64, glo, &p->cg, 1, p->mass, phi, grad, Sf, nullptr, fws, fws_bytes, &st,
+                       stream);
+      iters += st.iters;
+      if (r) return r;
+    }
+    QX_HIP(launch_gauge_grad(lat.geo, U, p->beta, grad, phi ? 1 : 0, stream), "md: gauge force");
+    return QX_OK;
+  };
+  auto energy = [&](double Sf, double* H) -> int {
+    double K = 0.0, Sg = 0.0;
+    int r = qx_md_kinetic(&lat, mom, red, md_reduce_bytes(), &K, stream);
+    if (!r) r = qx_gauge_action(&lat, U, p->beta, red, md_reduce_bytes(), &Sg, stream);
+    *H = K + Sg + Sf;
+    return r;
+  };
+  auto repack = [&]() -> int {
+    QX_HIP(launch_pack_gauge(g64->geo, U, g64->prec, g64->recon, const_cast<void*>(g64->packed), nullptr, stream),
+           "md: repack FP64 links");
+    if (glo)
+      QX_HIP(launch_pack_gauge(glo->geo, U, glo->prec, glo->recon, const_cast<void*>(glo->packed), nullptr, stream),
+             "md: repack inner links");
+    return QX_OK;
+  };
+  double Sf = 0.0;
+  rc = repack();
+  if (!rc) rc = force(&Sf);
+  if (!rc) rc = energy(Sf, H_start);
+  if (rc) return rc;
+  QX_HIP(launch_mom_update(lat.geo, U, grad, 0.5 * p->eps, mom, stream), "md: momenta");
+  for (int i = 0; i < p->nsteps; ++i) {
+    QX_HIP(launch_link_update(lat.geo, mom, p->eps, U, stream), "md: links");
+    rc = repack();
+    if (!rc) rc = force(&Sf);
+    if (rc) return rc;
+    const double e = i + 1 < p->nsteps ? p->eps : 0.5 * p->eps;
+    QX_HIP(launch_mom_update(lat.geo, U, grad, e, mom, stream), "md: momenta");
+  }
+  rc = energy(Sf, H_end);
+  if (rc) return rc;
+  if (cg_iters) *cg_iters = iters;
+  return QX_OK;
+}
+
 namespace {
 
 // Average device time (ms) of one of `reps` back-to-back launches made by

@@ -90,6 +90,24 @@ hipError_t launch_su3_force(const Geo& g, const void* U, const void* G, double* 
 hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials, int nblk,
                         double* out, hipStream_t s);
 
+// ----------------------------------------------------- molecular dynamics
+// (canonical FP64 layouts: U [4][V][3][3] complex, p [4][V][8] real)
+
+// out = sum_{x, mu<nu} (1 - Re tr P_munu(x) / 3), nblk partial sums.
+hipError_t launch_plaquette_sum(const Geo& g, const void* U, double* partials, int nblk,
+                                double* out, hipStream_t s);
+// G (+)= -(beta/3) A^dag (A: the six staples of every link).
+hipError_t launch_gauge_grad(const Geo& g, const void* U, double beta, void* G, int accumulate,
+                             hipStream_t s);
+// p^a -= eps Re[i tr(T_a U G^dag)].
+hipError_t launch_mom_update(const Geo& g, const void* U, const void* G, double eps, double* p,
+                             hipStream_t s);
+// U <- exp(i eps sum_a p^a T_a) U.
+hipError_t launch_link_update(const Geo& g, const double* p, double eps, void* U, hipStream_t s);
+// out = sum v^2 over n doubles.
+hipError_t launch_sumsq(const double* v, int64_t n, double* partials, int nblk, double* out,
+                        hipStream_t s);
+
 // Read bytes (a multiple of 16) once; out: 8192 unsigned words of scratch.
 hipError_t launch_read(const void* src, size_t bytes, unsigned* out, hipStream_t s);
 // dst = src, bytes a multiple of 16.

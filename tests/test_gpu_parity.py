@@ -716,3 +716,92 @@ def test_naik_apply_A_and_rejections(qx):
     g32 = qx.Gauge(lat, Ud, "f32", 18)
     with pytest.raises(qx.QXError):
         qx.cg(gn, to_dev(v[:1]), [0.1], glo=g32)
+
+
+# ------------------------------------------------- HMC molecular dynamics (f3)
+
+def _md_start(dims, seed):
+    from oracle import hmc  # noqa: F401  (oracle package imported by the tests only)
+    U = synth.weak_gauge(dims, 0.3, seed)
+    p = np.random.default_rng(seed + 1).standard_normal((4, U.shape[1], 8))
+    return U, p
+
+
+def test_gauge_action_and_force_parity(qx):
+    from oracle import hmc
+    dims = (6, 4, 4, 8)
+    lat = qx.Lattice(dims)
+    U = synth.haar_gauge(dims, 41)
+    beta = 5.6
+    S = qx.gauge_action(lat, to_dev(U), beta)
+    ref = hmc.gauge_action(dims, U, beta)
+    assert abs(S - ref) <= 1e-13 * abs(ref)
+    G = to_host(qx.gauge_force(lat, to_dev(U), beta))
+    Gr = hmc.gauge_grad(dims, U, beta)
+    assert np.abs(G - Gr).max() <= 1e-13 * np.abs(Gr).max()
+    # accumulate onto a given gradient
+    G0 = synth.haar_gauge(dims, 42)
+    Ga = to_host(qx.gauge_force(lat, to_dev(U), beta, G=to_dev(G0), accumulate=True))
+    assert np.abs(Ga - (G0 + Gr)).max() <= 1e-13 * np.abs(Gr).max()
+
+
+def test_md_updates_parity(qx):
+    from oracle import hmc
+    dims = (4, 4, 6, 4)
+    lat = qx.Lattice(dims)
+    U, p = _md_start(dims, 43)
+    G = synth.haar_gauge(dims, 44)
+    pd = to_dev(p)
+    qx.md_update_momenta(lat, to_dev(U), to_dev(G), 0.07, pd)
+    assert np.abs(to_host(pd) - (p - 0.07 * oracle.su3_force(U, G))).max() <= 1e-13
+    Ud = to_dev(U)
+    big = 3.0 * p  # large steps exercise the scaling and squaring
+    for eps in (0.05, 0.9):
+        Ud = to_dev(U)
+        qx.md_update_links(lat, to_dev(big), eps, Ud)
+        assert np.abs(to_host(Ud) - hmc.link_update(U, big, eps)).max() <= 1e-13
+    assert abs(qx.md_kinetic(lat, to_dev(p)) - hmc.kinetic(p)) <= 1e-12 * hmc.kinetic(p)
+
+
+@pytest.mark.parametrize("fermions", [False, True])
+def test_md_trajectory_parity(qx, fermions):
+    """Four leapfrog steps (beta 5.5, m 0.2, eps 0.05) against the oracle trajectory:
+    links, momenta and the energy change."""
+    from oracle import hmc
+    dims = (4, 4, 4, 8)
+    lat = qx.Lattice(dims)
+    U, p = _md_start(dims, 45)
+    phi = synth.gauss_source(1, lat.hv, 46)[0] if fermions else None
+    Ur, pr, H0r, H1r = hmc.md_trajectory(dims, U, p, phi, 5.5, 0.2, 0.05, 4, tol=1e-13)
+    Ud, pd = to_dev(U), to_dev(p)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    H0, H1, iters = qx.md_trajectory(g64, Ud, pd, 5.5, 0.05, 4,
+                                     phi=to_dev(phi) if fermions else None, mass=0.2, tol=1e-12)
+    assert abs(H0 - H0r) <= 1e-10 * abs(H0r)
+    assert abs((H1 - H0) - (H1r - H0r)) <= 1e-7, (H1 - H0, H1r - H0r)
+    assert np.abs(to_host(Ud) - Ur).max() <= 1e-10
+    assert np.abs(to_host(pd) - pr).max() <= 1e-9
+    assert (iters > 0) == fermions
+
+
+def test_md_trajectory_mixed_reversible(qx):
+    """Mixed-precision force solves: the same trajectory as with FP64 solves (both to
+    1e-12), and run back with -p it returns to the start."""
+    dims = (4, 4, 4, 8)
+    lat = qx.Lattice(dims)
+    U, p = _md_start(dims, 47)
+    phi = to_dev(synth.gauss_source(1, lat.hv, 48)[0])
+    Uf, pf = to_dev(U), to_dev(p)
+    g64f = qx.Gauge(lat, Uf, "f64")
+    F0, F1, _ = qx.md_trajectory(g64f, Uf, pf, 5.5, 0.05, 6, phi=phi, mass=0.2, tol=1e-12)
+    Ud, pd = to_dev(U), to_dev(p)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    H0, H1, _ = qx.md_trajectory(g64, Ud, pd, 5.5, 0.05, 6, phi=phi, mass=0.2, glo=g32, tol=1e-12)
+    assert abs(H0 - F0) <= 1e-10 * abs(F0) and abs((H1 - H0) - (F1 - F0)) <= 1e-7
+    assert np.abs(to_host(Ud) - to_host(Uf)).max() <= 1e-10
+    pd.neg_()
+    H2, H3, _ = qx.md_trajectory(g64, Ud, pd, 5.5, 0.05, 6, phi=phi, mass=0.2, glo=g32, tol=1e-12)
+    assert np.abs(to_host(Ud) - U).max() <= 1e-9
+    assert np.abs(-to_host(pd) - p).max() <= 1e-8
+    assert abs(H3 - H0) <= 1e-9 * abs(H0)
