@@ -261,6 +261,36 @@ def naik_cg(torch, qx, synth):
     return out
 
 
+def hmc_md(torch, qx, synth):
+    """One HMC molecular-dynamics trajectory on 16^4 (weak-field start eps=0.3,
+    Gaussian momenta and pseudofermion, beta 5.5, m 0.1): ten leapfrog steps
+    of 0.02 with mixed-precision force solves to 1e-10."""
+    dims, beta, m, eps, nsteps = (16, 16, 16, 16), 5.5, 0.1, 0.02, 10
+    lat = qx.Lattice(dims)
+    U0 = torch.from_numpy(synth.weak_gauge(dims, 0.3, 0)).cuda()
+    p0 = torch.from_numpy(np.random.default_rng(5).standard_normal((4, lat.V, 8))).cuda()
+    phi = torch.from_numpy(synth.gauss_source(1, lat.hv, 6)[0]).cuda()
+    U = U0.clone()
+    g64 = qx.Gauge(lat, U, "f64")
+    g32 = qx.Gauge(lat, U, "f32", 12)
+    g32.tune(1)
+    out = {"workload": "16^4 HMC trajectory: beta 5.5, m 0.1, 10 leapfrog steps of 0.02, "
+                       "mixed force solves to 1e-10"}
+    for rep in range(2):  # the first run warms up
+        U.copy_(U0)
+        p = p0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H0, H1, it = qx.md_trajectory(g64, U, p, beta, eps, nsteps, phi=phi, mass=m, glo=g32,
+                                      tol=1e-10)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    out.update({"trajectory_ms": round(t * 1e3, 2), "ms_per_step": round(t * 1e3 / nsteps, 3),
+                "cg_iters_per_force": round(it / (nsteps + 1), 1), "dH": H1 - H0, "H_start": H0})
+    log(f"16^4 HMC: {out}")
+    return out
+
+
 def multi_rhs(torch, qx, synth):
     """32^4 Haar links, 12 Gaussian sources, m = 0.02, tol 1e-10: the twelve
     sources solved together (FP32 12-real inner iteration, FP64 reliable
@@ -424,6 +454,7 @@ def main():
 
     multi = None if args.no_multi else multi_rhs(torch, qx, synth)
     naik = naik_cg(torch, qx, synth)
+    md = hmc_md(torch, qx, synth)
 
 
     # ------------------------------------------------------------ CPU oracle
@@ -492,6 +523,7 @@ def main():
         "dslash_sweep": d32,
         "multi_rhs_32^4": multi,
         "naik_cg_16^4": naik,
+        "hmc_md_16^4": md,
         "copy_probe_gbs": round(copy_gbs, 1),
         "read_probe_gbs": round(read_gbs, 1),
         "cpu_baseline": cpu,
