@@ -337,6 +337,23 @@ int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_params_t* par
                      double* p, const void* phi, void* ws, size_t ws_bytes, double* H_start,
                      double* H_end, int* cg_iters, hipStream_t stream);
 
+/* -------------------------------------------------------------- mesons */
+
+/* Staggered meson correlators from a point source at the even site src[4]
+   (x, y, z, t): per source colour the propagator G = M^-1 delta, M = m + D,
+   is m A^-1 b on even sites and -D_oe A^-1 b on odd sites (the three colour
+   sources solved together, params as for qx_cg_solve, one mass); then
+     C_k(t) = sum_{x with x_t = src_t + t (mod L_t)} s_k(x) sum_{a,c} |G_ac(x)|^2,
+     s_k(x) = (-1)^(sum of x_mu over the directions mu set in masks[k] (bit mu)),
+   mask 0 being the Goldstone pion.  The paper lists spectrum measurements
+   among the framework's uses (Sec. 4).  C: host [nmask][L_t], 1 <= nmask <= 16;
+   stats: host array of 3.  QX_EINVAL for an odd source site.  Synchronises. */
+int qx_meson_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params,
+                             size_t* bytes);
+int qx_meson_correlators(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_cg_params_t* params,
+                         double mass, const int src[4], int nmask, const int* masks, double* C,
+                         void* ws, size_t ws_bytes, qx_cg_stats_t* stats, hipStream_t stream);
+
 /* ------------------------------------------------------------- tuning */
 
 /* Pick the launch shape of the stencil kernels for this gauge handle and nrhs

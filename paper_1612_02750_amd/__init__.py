@@ -111,6 +111,9 @@ def load():
         "qx_md_update_links": ([_P, _P, ctypes.c_double, _P, _P], _I),
         "qx_md_kinetic": ([_P, _P, _P, _SZ, _P, _P], _I),
         "qx_md_workspace_bytes": ([_P, _P, _P], _I),
+        "qx_meson_workspace_bytes": ([_P, _P, _P], _I),
+        "qx_meson_correlators": ([_P, _P, _P, ctypes.c_double, _P, _I, _P, _P, _P, _SZ, _P, _P],
+                                 _I),
         "qx_md_trajectory": ([_P, _P, _P, _P, _P, _P, _P, _SZ, _P, _P, _P, _P], _I),
         "qx_time_dslash": ([_P, _I, _I, _P, _P, _I, _P, _P], _I),
         "qx_get_launch": ([_P, _I, _P, _P, _P], _I),
@@ -480,6 +483,30 @@ def md_trajectory(g64: Gauge, U, p, beta: float, eps: float, nsteps: int, phi=No
                               ws.numel(), ctypes.byref(h0), ctypes.byref(h1), ctypes.byref(it),
                               _stream(stream)))
     return h0.value, h1.value, it.value
+
+
+def meson_correlators(g64: Gauge, mass: float, src, masks=(0,), glo: Optional[Gauge] = None,
+                      tol=1e-10, max_iter=100000, mode=None, delta=0.1, stream=None):
+    """Point-source staggered meson correlators C[k][t] (numpy (nmask, L_t)) for the
+    direction masks (mask 0: Goldstone pion); src: even site (x, y, z, t)."""
+    import numpy as np
+
+    L = load()
+    if mode is None:
+        mode = CG_MIXED_F32 if glo is not None else CG_FP64
+    p = _params(tol, max_iter, mode, delta, 0, 0)
+    n = ctypes.c_size_t()
+    _check(L.qx_meson_workspace_bytes(g64.lat._h, ctypes.byref(p), ctypes.byref(n)))
+    ws = _bytes(n.value)
+    srcs = (ctypes.c_int * 4)(*[int(v) for v in src])
+    mk = (ctypes.c_int * len(masks))(*[int(v) for v in masks])
+    Lt = g64.lat.dims[3]
+    C = (ctypes.c_double * (len(masks) * Lt))()
+    st = (_Stats * 3)()
+    _check(L.qx_meson_correlators(g64._h, glo._h if glo is not None else None, ctypes.byref(p),
+                                  float(mass), srcs, len(masks), mk, C, _ptr(ws), ws.numel(), st,
+                                  _stream(stream)))
+    return np.array(C[:]).reshape(len(masks), Lt), _stats(st, 3)
 
 
 def force_from_fields(g64: Gauge, x, lam, stream=None):

@@ -1102,6 +1102,80 @@ extern "C" int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_pa
   return QX_OK;
 }
 
+// ------------------------------------------------------------------ mesons
+
+namespace {
+size_t meson_extra_bytes(const Geo& g) {
+  // b and x canonical, x and y packed (three sources each), C
+  return 4 * align_up(field_bytes(g, 3, QX_PREC_F64), 256) +
+         align_up(sizeof(double) * 16 * (size_t)g.L3, 256);
+}
+}  // namespace
+
+extern "C" int qx_meson_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params,
+                                        size_t* bytes) {
+  if (!lat || !params || !bytes) return fail(QX_EINVAL, "qx_meson_workspace_bytes: bad argument");
+  size_t b = 0;
+  int rc = qx_cg_workspace_bytes(lat, params, 3, &b);
+  if (rc) return rc;
+  *bytes = align_up(b, 256) + meson_extra_bytes(lat->geo);
+  return QX_OK;
+}
+
+extern "C" int qx_meson_correlators(const qx_gauge_t* g64, const qx_gauge_t* glo,
+                                    const qx_cg_params_t* params, double mass, const int src[4],
+                                    int nmask, const int* masks, double* C, void* ws,
+                                    size_t ws_bytes, qx_cg_stats_t* stats, hipStream_t stream) {
+  if (!g64 || !params || !src || !masks || !C || !ws || nmask < 1 || nmask > 16)
+    return fail(QX_EINVAL, "qx_meson_correlators: bad argument");
+  const Geo& g = g64->geo;
+  const int L[4] = {g.L0, g.L1, g.L2, g.L3};
+  for (int mu = 0; mu < 4; ++mu)
+    if (src[mu] < 0 || src[mu] >= L[mu])
+      return fail(QX_EINVAL, "qx_meson_correlators: source outside the lattice");
+  if ((src[0] + src[1] + src[2] + src[3]) & 1)
+    return fail(QX_EINVAL, "qx_meson_correlators: the source must be on an even site");
+  for (int k = 0; k < nmask; ++k)
+    if (masks[k] < 0 || masks[k] > 15) return fail(QX_EINVAL, "qx_meson_correlators: bad mask");
+  qx_lattice lat{};
+  memcpy(lat.dims, g64->dims, sizeof lat.dims);
+  lat.flags = g64->flags;
+  lat.geo = g;
+  lat.V = 2 * (int64_t)g.hv;
+  size_t need = 0;
+  int rc = qx_meson_workspace_bytes(&lat, params, &need);
+  if (rc) return rc;
+  if (ws_bytes < need)
+    return fail(QX_ENOMEM, "qx_meson_correlators: workspace of %zu bytes, %zu needed", ws_bytes, need);
+  size_t solver = 0;
+  rc = qx_cg_workspace_bytes(&lat, params, 3, &solver);
+  if (rc) return rc;
+  char* w = (char*)ws;
+  const size_t fb = align_up(field_bytes(g, 3, QX_PREC_F64), 256);
+  char* sws = w;
+  char* b = w + align_up(solver, 256);
+  char* x = b + fb;
+  char* xp = x + fb;
+  char* yp = xp + fb;
+  double* Cd = (double*)(yp + fb);
+  const int64_t lex = src[0] + (int64_t)L[0] * (src[1] + (int64_t)L[1] * (src[2] + (int64_t)L[2] * src[3]));
+  QX_HIP(launch_point_source(g, (int)(lex >> 1), b, stream), "qx_meson_correlators: sources");
+  const double ms[3] = {mass, mass, mass};
+  rc = qx_cg_solve(g64, glo, params, 3, ms, b, x, sws, solver, stats, stream);
+  if (rc) return rc;
+  QX_HIP(launch_pack_field(g, 3, QX_PREC_F64, x, xp, stream), "qx_meson_correlators: pack");
+  QX_HIP(launch_dslash(g, QX_PREC_F64, g64->recon, g64->packed, 1, xp, yp, 3, 0.5,
+                       shape_for(g64, 3), stream),
+         "qx_meson_correlators: D_oe");
+  QX_HIP(launch_meson_contract(g, xp, yp, mass, src[3], nmask, masks, Cd, stream),
+         "qx_meson_correlators: contraction");
+  QX_HIP(hipMemcpyAsync(C, Cd, sizeof(double) * nmask * (size_t)g.L3, hipMemcpyDeviceToHost,
+                        stream),
+         "qx_meson_correlators: readback");
+  QX_HIP(hipStreamSynchronize(stream), "qx_meson_correlators: synchronise");
+  return QX_OK;
+}
+
 namespace {
 
 // Average device time (ms) of one of `reps` back-to-back launches made by

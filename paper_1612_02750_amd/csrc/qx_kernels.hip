@@ -384,6 +384,88 @@ hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials
   return hipGetLastError();
 }
 
+// ================================================================ mesons
+
+// Canonical point sources: b[c][cb][a] = (a == c && cb == cb_src) for the three
+// colours c.
+__global__ void __launch_bounds__(256) k_point_source(int hv, int cb_src,
+                                                      cplx<double>* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 9 * (int64_t)hv) return;
+  const int c = (int)(i / (3 * (int64_t)hv));
+  const int64_t r = i - c * 3 * (int64_t)hv;
+  const int cb = (int)(r / 3), a = (int)(r % 3);
+  b[i] = {(a == c && cb == cb_src) ? 1.0 : 0.0, 0.0};
+}
+
+constexpr int kMaxMasks = 16;
+struct Masks16 {
+  int m[kMaxMasks];
+};
+
+// One block per timeslice x3: C[k][(x3 - t_src) mod L3] = sum over the sites of
+// the timeslice of s_k(x) |G(x)|^2, with |G|^2 = m^2 |x|^2 on even sites and
+// |y|^2 on odd sites (x, y packed [3 sources][3 colours][cb]), s_k(x) =
+// (-1)^(sum of x_mu over the bits of mask k).  Fixed summation order.
+__global__ void __launch_bounds__(256) k_meson_contract(Geo g, const cplx<double>* __restrict__ xp,
+                                                        const cplx<double>* __restrict__ yp,
+                                                        double m2, int t_src, int nmask, Masks16 mk,
+                                                        double* __restrict__ C) {
+  __shared__ double sh[kMaxMasks * 16];
+  const int x3 = blockIdx.x;
+  const int per = g.s3;  // checkerboard sites of one parity per timeslice
+  const size_t hv = g.hv;
+  double acc[kMaxMasks];
+#pragma unroll
+  for (int k = 0; k < kMaxMasks; ++k) acc[k] = 0.0;
+  for (int j = threadIdx.x; j < 2 * per; j += blockDim.x) {
+    const int p = j >= per ? 1 : 0;
+    const int cb = x3 * per + (j - p * per);
+    Site s;
+    site_geometry(g, p, cb, s);
+    const cplx<double>* f = p ? yp : xp;
+    double d = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {  // three sources x three colours
+      const cplx<double> v = f[(size_t)e * hv + cb];
+      d += v.re * v.re + v.im * v.im;
+    }
+    if (!p) d *= m2;
+    const int xs[4] = {s.x0, s.x1, s.x2, s.x3};
+#pragma unroll
+    for (int k = 0; k < kMaxMasks; ++k) {
+      if (k >= nmask) break;
+      int e = 0;
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu)
+        if (mk.m[k] >> mu & 1) e += xs[mu];
+      acc[k] += (e & 1) ? -d : d;
+    }
+  }
+  block_sum<kMaxMasks>(acc, sh);
+  if (threadIdx.x == 0) {
+    const int t = (x3 - t_src + g.L3) % g.L3;
+    for (int k = 0; k < nmask; ++k) C[(size_t)k * g.L3 + t] = acc[k];
+  }
+}
+
+hipError_t launch_point_source(const Geo& g, int cb_src, void* b, hipStream_t s) {
+  const size_t n = 9 * (size_t)g.hv;
+  hipLaunchKernelGGL(k_point_source, dim3(grid_for(n, 256)), dim3(256), 0, s, g.hv, cb_src,
+                     (cplx<double>*)b);
+  return hipGetLastError();
+}
+
+hipError_t launch_meson_contract(const Geo& g, const void* xp, const void* yp, double mass,
+                                 int t_src, int nmask, const int* masks, double* C, hipStream_t s) {
+  if (nmask < 1 || nmask > kMaxMasks) return hipErrorInvalidValue;
+  Masks16 mk{};
+  for (int k = 0; k < nmask; ++k) mk.m[k] = masks[k];
+  hipLaunchKernelGGL(k_meson_contract, dim3(g.L3), dim3(256), 0, s, g, (const cplx<double>*)xp,
+                     (const cplx<double>*)yp, mass * mass, t_src, nmask, mk, C);
+  return hipGetLastError();
+}
+
 // ================================================================ probe
 
 // Plain copy with 16-byte accesses, four independent loads in flight per

@@ -108,6 +108,14 @@ hipError_t launch_link_update(const Geo& g, const double* p, double eps, void* U
 hipError_t launch_sumsq(const double* v, int64_t n, double* partials, int nblk, double* out,
                         hipStream_t s);
 
+// ------------------------------------------------------------------ mesons
+
+// Three canonical point sources (one per colour) at even checkerboard site cb_src.
+hipError_t launch_point_source(const Geo& g, int cb_src, void* b, hipStream_t s);
+// C[k][t] (device) from packed x (even) and y = D_oe x (odd) of three sources.
+hipError_t launch_meson_contract(const Geo& g, const void* xp, const void* yp, double mass,
+                                 int t_src, int nmask, const int* masks, double* C, hipStream_t s);
+
 // Read bytes (a multiple of 16) once; out: 8192 unsigned words of scratch.
 hipError_t launch_read(const void* src, size_t bytes, unsigned* out, hipStream_t s);
 // dst = src, bytes a multiple of 16.

@@ -805,3 +805,32 @@ def test_md_trajectory_mixed_reversible(qx):
     assert np.abs(to_host(Ud) - U).max() <= 1e-9
     assert np.abs(-to_host(pd) - p).max() <= 1e-8
     assert abs(H3 - H0) <= 1e-9 * abs(H0)
+
+
+# ------------------------------------------------------- meson correlators (f4)
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_meson_correlators_parity(qx, mixed):
+    """Point-source correlators of six direction masks against the oracle."""
+    from oracle import meson
+    dims = (4, 6, 4, 8)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=61)
+    src = (2, 1, 3, 2)
+    masks = [0, 1, 2, 4, 8, 7, 15]
+    ref = meson.correlators(dims, meson.point_propagator(dims, U, 0.15, src), src, masks)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    glo = qx.Gauge(lat, Ud, "f32", 12) if mixed else None
+    C, st = qx.meson_correlators(g64, 0.15, src, masks, glo=glo, tol=1e-12)
+    assert all(s.status == 0 for s in st)
+    scale = np.abs(ref).max()
+    assert np.abs(C - ref).max() <= 1e-9 * scale, np.abs(C - ref).max() / scale
+
+
+def test_meson_rejects_odd_source(qx):
+    dims = (4, 4, 4, 4)
+    lat = qx.Lattice(dims)
+    g64 = qx.Gauge(lat, to_dev(gauge(dims, seed=62)), "f64")
+    with pytest.raises(qx.QXError):
+        qx.meson_correlators(g64, 0.1, (1, 0, 0, 0))
