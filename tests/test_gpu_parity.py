@@ -834,3 +834,46 @@ def test_meson_rejects_odd_source(qx):
     g64 = qx.Gauge(lat, to_dev(gauge(dims, seed=62)), "f64")
     with pytest.raises(qx.QXError):
         qx.meson_correlators(g64, 0.1, (1, 0, 0, 0))
+
+
+def test_naik_uneven_batch(qx):
+    """Improved-operator systems of different lattice sizes in one batch (mixed), to 1e-10."""
+    import torch
+
+    shapes = [(4, 4, 4, 4), (8, 4, 4, 6), (6, 6, 6, 6)]
+    systems, keep = [], []
+    for k, dims in enumerate(shapes):
+        U = synth.weak_gauge(dims, 0.3, 70 + k)
+        lat = qx.Lattice(dims)
+        Ud = to_dev(U)
+        g64 = qx.Gauge(lat, Ud, "f64", qx.RECON_NAIK)
+        g32 = qx.Gauge(lat, Ud, "f32", qx.RECON_NAIK)
+        nrhs = 1 + k % 2
+        b = synth.gauss_source(nrhs, lat.hv, 80 + k)
+        masses = [0.05 + 0.04 * j for j in range(nrhs)]
+        bd = to_dev(b)
+        xd = torch.empty_like(bd)
+        systems.append((g64, g32, bd, masses, xd))
+        keep.append((dims, U, b, masses, xd))
+    stats = qx.Batch(systems, tol=1e-10).solve()
+    j = 0
+    for dims, U, b, masses, xd in keep:
+        x = to_host(xd)
+        for s in range(b.shape[0]):
+            rr = oracle.true_residual(dims, U, masses[s], b[s], x[s], oracle.NAIK)
+            assert rr <= 1e-10 and stats[j].status == 0, (dims, s, rr)
+            j += 1
+
+
+def test_naik_meson_correlators(qx):
+    from oracle import meson
+    dims = (4, 4, 6, 8)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, seed=63)
+    src = (0, 2, 2, 4)
+    masks = [0, 8, 7]
+    ref = meson.correlators(dims, meson.point_propagator(dims, U, 0.2, src, flags=oracle.NAIK), src,
+                            masks)
+    g64 = qx.Gauge(lat, to_dev(U), "f64", qx.RECON_NAIK)
+    C, _ = qx.meson_correlators(g64, 0.2, src, masks, tol=1e-12)
+    assert np.abs(C - ref).max() <= 1e-9 * np.abs(ref).max()
