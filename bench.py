@@ -171,7 +171,10 @@ def dslash_sweep(torch, qx, tune=True, plain=False):
     from paper_1612_02750_amd import synth
 
     res = {}
-    variants = (("f32", 12, 384, 24), ("f64", 18, 1152, 48))
+    # (precision, link storage, link bytes and colour-vector bytes per site);
+    # an FP16 vector is 12 bytes of pairs and a 4-byte scale
+    variants = (("f32", 12, 384, 24), ("f64", 18, 1152, 48), ("f16", 12, 192, 16))
+    naik = (("f32", 1152, 24), ("f64", 2304, 48), ("f16", 576, 16))
     dims32 = (32, 32, 32, 32)
     lat32 = qx.Lattice(dims32)
     U32 = torch.from_numpy(synth.haar_gauge(dims32, 0)).cuda()
@@ -183,7 +186,7 @@ def dslash_sweep(torch, qx, tune=True, plain=False):
             _dslash_point(torch, qx, g, lat32, nrhs, 2, link_b, vec_b, 50, plain,
                           f"32^4-{prec}-{recon}-nrhs{nrhs}", res)
         del g
-    for prec, link_b, vec_b in (("f32", 1152, 24), ("f64", 2304, 48)):
+    for prec, link_b, vec_b in naik:
         g = qx.Gauge(lat32, U32, prec, qx.RECON_NAIK)
         if tune:
             g.tune(1)
@@ -203,7 +206,7 @@ def dslash_sweep(torch, qx, tune=True, plain=False):
         _dslash_point(torch, qx, g, lat48, 1, 3, link_b, vec_b, 30, plain,
                       f"48^4-{prec}-{recon}-nrhs1", res)
         del g
-    for prec, link_b, vec_b in (("f32", 1152, 24), ("f64", 2304, 48)):
+    for prec, link_b, vec_b in naik:
         g = qx.Gauge(lat48, U48, prec, qx.RECON_NAIK)
         if tune:
             g.tune(1)

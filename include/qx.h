@@ -73,8 +73,14 @@ enum {
 /* lattice flags */
 enum { QX_BC_T_ANTIPERIODIC = 1 };
 
-/* storage precision of packed fields */
-enum { QX_PREC_F64 = 0, QX_PREC_F32 = 1 };
+/* Storage precision of packed fields.  QX_PREC_F16 (storage below the
+   single and double precision the paper measures, Sec. 4): links as IEEE binary16 pairs; colour vectors as
+   binary16 pairs scaled per site by one FP32 number, the largest |re| or |im|
+   of the site's three colours (16 bytes per site and source); every
+   arithmetic step in FP32.  F16 handles and fields serve qx_field_pack /
+   qx_field_unpack, qx_dslash, qx_apply_A and the launch-shape calls; the
+   solver, force, molecular-dynamics and meson calls reject them. */
+enum { QX_PREC_F64 = 0, QX_PREC_F32 = 1, QX_PREC_F16 = 2 };
 
 /* link storage: 18 reals, or 12 reals (rows 0-1, row 2 rebuilt in-kernel as
    sign * conj(row0 x row1); exact for SU(3) links) */
@@ -251,6 +257,25 @@ int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg_params_t* 
 /* Solve every system of the batch; stats: host array with one entry per
    source, systems in order.  Synchronises the stream. */
 int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream);
+
+/* As qx_batch_solve without any host synchronisation (for callers that keep
+   enqueueing dependent work): enqueues the start of the solve, exactly
+   `nchunks` (>= 1) chunks of inner-iteration slots with their reliable-update
+   checks (qx_batch_info gives the chunk length; slots after a source has
+   finished do no work for it, so nchunks is an upper bound chosen by the
+   caller), the unpacking of every x, and the per-source statistics into
+   d_stats, a device array of one qx_cg_stats_t per source (seconds = 0).  A
+   source still running after the last chunk reports QX_ENOTCONVERGED and its
+   x is the solution of its last reliable update.  Returns QX_OK once the work
+   is enqueued; results are valid when the stream reaches its end.  The work
+   of two calls on one batch must not overlap (they share the workspace). */
+int qx_batch_solve_async(qx_batch_t* batch, int nchunks, qx_cg_stats_t* d_stats,
+                         hipStream_t stream);
+
+/* Number of sources (over all systems) and inner-iteration slots per chunk
+   (with QX_ENGINE_PERSISTENT a chunk also ends at the first reliable update
+   that any source asks for). */
+int qx_batch_info(const qx_batch_t* batch, int* nsources, int* chunk);
 int qx_batch_destroy(qx_batch_t* batch);
 
 /* -------------------------------------------------------------- force */
@@ -373,6 +398,18 @@ int qx_meson_correlators(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_
    precision, link storage, nrhs) in the process and in the JSON file named by
    QX_TUNE_CACHE if set.  Synchronises the stream. */
 int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream);
+
+/* The process-wide launch-shape cache that qx_tune_dslash fills (keys: device,
+   lattice extents, precision, link storage, source count; values: nbt, lps,
+   xcd_order), as the flat JSON object {"key": [nbt, lps, xcd_order], ...}.
+   qx_tune_cache_load merges the entries of the file at `path` into it (an
+   entry replaces the one of the same key; malformed entries and shapes that
+   are not compiled are skipped; QX_EINVAL if the file cannot be read);
+   qx_tune_cache_save writes the whole cache to `path` (QX_EINVAL if it cannot
+   be written).  Handles use a cached shape for every (handle, nrhs) that has
+   not been tuned or set on the handle itself.  Host only, no device work. */
+int qx_tune_cache_load(const char* path);
+int qx_tune_cache_save(const char* path);
 
 /* Average device time, in ms, of one half-Dslash launch (as qx_dslash, with
    the handle's launch shape for nrhs): `reps` (1..10000) launches are captured

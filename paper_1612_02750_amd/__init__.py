@@ -22,11 +22,12 @@ LIB_PATH = os.path.join(_HERE, "libqx.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTUNITARY, ENOTCONVERGED, EBREAKDOWN, ENOLIB = range(8)
 BC_T_ANTIPERIODIC = 1
-PREC_F64, PREC_F32 = 0, 1
+PREC_F64, PREC_F32, PREC_F16 = 0, 1, 2
 CG_FP64, CG_MIXED_F32 = 0, 1
 ENGINE_AUTO, ENGINE_LAUNCH, ENGINE_PERSISTENT, ENGINE_FUSED = 0, 1, 2, 3
 
-_PREC = {"f64": PREC_F64, "f32": PREC_F32, PREC_F64: PREC_F64, PREC_F32: PREC_F32}
+_PREC = {"f64": PREC_F64, "f32": PREC_F32, "f16": PREC_F16, PREC_F64: PREC_F64,
+         PREC_F32: PREC_F32, PREC_F16: PREC_F16}
 
 
 class QXError(RuntimeError):
@@ -99,6 +100,10 @@ def load():
         "qx_batch_workspace_bytes": ([_I, _P, _P, _P], _I),
         "qx_batch_create": ([_I, _P, _P, _P, _SZ, _P, _P], _I),
         "qx_batch_solve": ([_P, _P, _P], _I),
+        "qx_batch_solve_async": ([_P, _I, _P, _P], _I),
+        "qx_batch_info": ([_P, _P, _P], _I),
+        "qx_tune_cache_load": ([ctypes.c_char_p], _I),
+        "qx_tune_cache_save": ([ctypes.c_char_p], _I),
         "qx_batch_destroy": ([_P], _I),
         "qx_force_from_fields": ([_P, _I, _P, _P, _P, _P, _P], _I),
         "qx_force_workspace_bytes": ([_P, _P, _I, _P], _I),
@@ -253,6 +258,16 @@ class Gauge:
         _check(load().qx_set_launch(self._h, nrhs, nbt, lps, xcd_order))
 
 
+def tune_cache_load(path: str):
+    """Merge the launch shapes of a JSON cache file into the process cache."""
+    _check(load().qx_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_save(path: str):
+    """Write the process cache of launch shapes to a JSON file."""
+    _check(load().qx_tune_cache_save(os.fsencode(path)))
+
+
 # ------------------------------------------------------------------ fields
 
 def pack(lat: Lattice, canon, prec="f64", stream=None):
@@ -384,6 +399,25 @@ class Batch:
         if raise_on_fail:
             _check(rc)
         return _stats(st, self.nsrc)
+
+    def chunk(self) -> int:
+        c = ctypes.c_int()
+        _check(load().qx_batch_info(self._h, None, ctypes.byref(c)))
+        return c.value
+
+    def solve_async(self, nchunks: int, stats=None, stream=None):
+        """Enqueue a whole solve of at most nchunks chunks with no host
+        synchronisation; returns the device buffer the statistics land in
+        (decode with stats_from_device once the stream has reached it)."""
+        if stats is None:
+            stats = _bytes(ctypes.sizeof(_Stats) * self.nsrc)
+        _check(load().qx_batch_solve_async(self._h, int(nchunks), _ptr(stats), _stream(stream)))
+        return stats
+
+    def stats_from_device(self, stats):
+        host = stats.cpu().numpy().tobytes()
+        arr = (_Stats * self.nsrc).from_buffer_copy(host)
+        return _stats(arr, self.nsrc)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

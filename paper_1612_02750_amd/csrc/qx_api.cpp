@@ -106,14 +106,12 @@ std::string tune_key(const qx_gauge* g, int nrhs) {
   return buf;
 }
 
-// The cache file is a flat JSON object {"key": [nbt, lps, xcd], ...}.
-void tune_load_locked() {
-  if (g_tune_loaded) return;
-  g_tune_loaded = true;
-  const char* path = getenv("QX_TUNE_CACHE");
-  if (!path || !*path) return;
+// The cache file is a flat JSON object {"key": [nbt, lps, xcd], ...}.  Entries
+// read from a file replace those of the same key; malformed entries and
+// shapes that are not compiled are skipped.
+bool tune_read_file_locked(const char* path) {
   FILE* f = fopen(path, "r");
-  if (!f) return;
+  if (!f) return false;
   std::string s;
   char buf[4096];
   size_t n;
@@ -130,20 +128,32 @@ void tune_load_locked() {
       g_tune[key] = LaunchShape{nbt, lps, x < 0 ? 0 : x > 3 ? 3 : x};
     i = j + 1;
   }
+  return true;
 }
 
-void tune_save_locked() {
-  const char* path = getenv("QX_TUNE_CACHE");
-  if (!path || !*path) return;
+bool tune_write_file_locked(const char* path) {
   FILE* f = fopen(path, "w");
-  if (!f) return;
+  if (!f) return false;
   fprintf(f, "{\n");
   size_t k = 0;
   for (const auto& kv : g_tune)
     fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.nbt, kv.second.lps,
             kv.second.xcd, ++k < g_tune.size() ? "," : "");
   fprintf(f, "}\n");
-  fclose(f);
+  return fclose(f) == 0;
+}
+
+// The file named by QX_TUNE_CACHE is read once, before the first lookup.
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = getenv("QX_TUNE_CACHE");
+  if (path && *path) tune_read_file_locked(path);
+}
+
+void tune_save_locked() {
+  const char* path = getenv("QX_TUNE_CACHE");
+  if (path && *path) tune_write_file_locked(path);
 }
 
 LaunchShape shape_for(const qx_gauge* g, int nrhs) {
@@ -205,16 +215,14 @@ extern "C" int qx_debug_index_maps(const qx_lattice_t* lat, int32_t* lex_of_eo, 
 // ------------------------------------------------------------------- gauge
 
 namespace {
-bool prec_ok(int p) { return p == QX_PREC_F64 || p == QX_PREC_F32; }
+bool prec_ok(int p) { return p == QX_PREC_F64 || p == QX_PREC_F32 || p == QX_PREC_F16; }
 bool recon_ok(int r) { return r == QX_RECON_18 || r == QX_RECON_12 || r == QX_RECON_NAIK; }
 // recon / 2 complex numbers per (site, direction): 6, 9, or 9 + 9 for the
 // improved operator's one-hop and three-hop links
 size_t gauge_bytes(const Geo& g, int prec, int recon) {
-  return (size_t)8 * g.hv * (recon / 2) * cplx_bytes(prec);
+  return (size_t)8 * g.hv * (recon / 2) * link_cplx_bytes(prec);
 }
-size_t field_bytes(const Geo& g, int nrhs, int prec) {
-  return (size_t)nrhs * 3 * g.hv * cplx_bytes(prec);
-}
+size_t field_bytes(const Geo& g, int nrhs, int prec) { return (size_t)nrhs * source_bytes(g, prec); }
 }  // namespace
 
 extern "C" int qx_gauge_bytes(const qx_lattice_t* lat, int prec, int recon, size_t* bytes) {
@@ -432,6 +440,7 @@ struct qx_batch {
   std::vector<SysDesc> sys;
   std::vector<SrcState> st0;
   SrcState* h_st = nullptr;  // pinned mirror of the workspace from the states to the barrier word
+  SrcState* h_st0 = nullptr;  // pinned initial states (written once, at create)
   GridSync* h_gs = nullptr;  // inside h_st's buffer
   char* ws = nullptr;
   int chunk = 16, ru_every = 4;
@@ -444,6 +453,7 @@ struct qx_batch {
   ~qx_batch() {
     if (graph) hipGraphExecDestroy(graph);
     if (h_st) hipHostFree(h_st);
+    if (h_st0) hipHostFree(h_st0);
   }
 };
 
@@ -548,6 +558,10 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   if (!engine_supported(B->cfg)) return fail(QX_EINVAL, "solver: unsupported configuration");
   const size_t mirror = B->layout.gs_off - B->layout.st_off + sizeof(GridSync);
   if (!B->h_st) QX_HIP(hipHostMalloc((void**)&B->h_st, mirror), "solver: hipHostMalloc");
+  if (!B->h_st0)
+    QX_HIP(hipHostMalloc((void**)&B->h_st0, sizeof(SrcState) * B->st0.size()),
+           "solver: hipHostMalloc");
+  memcpy(B->h_st0, B->st0.data(), sizeof(SrcState) * B->st0.size());
   B->h_gs = (GridSync*)((char*)B->h_st + (B->layout.gs_off - B->layout.st_off));
   // engine: launch per pass unless the persistent kernel is asked for
   B->persistent = false;
@@ -638,12 +652,12 @@ int capture_graph(qx_batch* B, hipStream_t s) {
   return QX_OK;
 }
 
-int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
-  const auto t0 = std::chrono::steady_clock::now();
+// Enqueue the start of a solve: initial states, b (and x0) packed, the
+// engine's initialisation and the initial residual; the chunk graph is
+// captured again if the stream differs from the one it was captured on.
+int enqueue_start(qx_batch* B, hipStream_t s) {
   const qx_cg_params_t& p = B->params;
-  // initial states
-  memcpy(B->h_st, B->st0.data(), sizeof(SrcState) * B->st0.size());
-  QX_HIP(hipMemcpyAsync(B->cfg.d_st, B->h_st, sizeof(SrcState) * B->st0.size(),
+  QX_HIP(hipMemcpyAsync(B->cfg.d_st, B->h_st0, sizeof(SrcState) * B->st0.size(),
                         hipMemcpyHostToDevice, s),
          "solver: state upload");
   for (size_t i = 0; i < B->specs.size(); ++i) {
@@ -663,15 +677,37 @@ int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
     int rc = capture_graph(B, s);
     if (rc != QX_OK) return rc;
   }
+  return QX_OK;
+}
+
+int enqueue_one_chunk(qx_batch* B, hipStream_t s) {
+  if (B->graph) {
+    QX_HIP(hipGraphLaunch(B->graph, s), "solver: graph launch");
+    return QX_OK;
+  }
+  return enqueue_chunk(B, s);
+}
+
+// Unpack the FP64 solutions into the callers' x buffers.
+int enqueue_finish(qx_batch* B, hipStream_t s) {
+  for (size_t i = 0; i < B->specs.size(); ++i) {
+    const SysDesc& d = B->sys[i];
+    QX_HIP(launch_unpack_field(d.g, d.nsrc, QX_PREC_F64, d.vhi, B->specs[i].x, s),
+           "solver: unpack x");
+  }
+  return QX_OK;
+}
+
+int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const qx_cg_params_t& p = B->params;
+  int rc = enqueue_start(B, s);
+  if (rc != QX_OK) return rc;
   const long max_chunks = (long)p.max_iter + 64;
   bool done = false;
   for (long c = 0; c < max_chunks && !done; ++c) {
-    if (B->graph) {
-      QX_HIP(hipGraphLaunch(B->graph, s), "solver: graph launch");
-    } else {
-      int rc = enqueue_chunk(B, s);
-      if (rc != QX_OK) return rc;
-    }
+    rc = enqueue_one_chunk(B, s);
+    if (rc != QX_OK) return rc;
     QX_HIP(hipStreamSynchronize(s), "solver: chunk");
     if (B->persistent && B->h_gs->error)
       return fail(QX_EHIP, "solver: a grid barrier of the persistent kernel timed out");
@@ -680,15 +716,11 @@ int run_plan(qx_batch* B, qx_cg_stats_t* stats, hipStream_t s) {
       if (B->h_st[k].phase != PH_DONE) done = false;
   }
   if (!done) return fail(QX_EHIP, "solver: the state machine did not terminate");
-  for (size_t i = 0; i < B->specs.size(); ++i) {
-    const SysDesc& d = B->sys[i];
-    QX_HIP(launch_unpack_field(d.g, d.nsrc, QX_PREC_F64, d.vhi, B->specs[i].x, s),
-           "solver: unpack x");
-  }
+  rc = enqueue_finish(B, s);
+  if (rc != QX_OK) return rc;
   QX_HIP(hipStreamSynchronize(s), "solver: finish");
   const double secs =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  int rc = QX_OK;
   for (int k = 0; k < B->cfg.nsrc_total; ++k) {
     const SrcState& q = B->h_st[k];
     if (stats) {
@@ -802,6 +834,29 @@ extern "C" int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg
 extern "C" int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream) {
   if (!batch) return fail(QX_EINVAL, "qx_batch_solve: NULL batch");
   return run_plan(batch, stats, stream);
+}
+
+extern "C" int qx_batch_solve_async(qx_batch_t* batch, int nchunks, qx_cg_stats_t* d_stats,
+                                    hipStream_t stream) {
+  if (!batch || !d_stats || nchunks < 1)
+    return fail(QX_EINVAL, "qx_batch_solve_async: bad argument");
+  qx_batch* B = batch;
+  int rc = enqueue_start(B, stream);
+  for (int c = 0; rc == QX_OK && c < nchunks; ++c) rc = enqueue_one_chunk(B, stream);
+  if (rc == QX_OK) rc = enqueue_finish(B, stream);
+  if (rc != QX_OK) return rc;
+  QX_HIP(launch_batch_stats(B->cfg.d_st, B->cfg.nsrc_total,
+                            B->persistent ? (const void*)(B->ws + B->layout.gs_off) : nullptr,
+                            d_stats, stream),
+         "qx_batch_solve_async: statistics");
+  return QX_OK;
+}
+
+extern "C" int qx_batch_info(const qx_batch_t* batch, int* nsources, int* chunk) {
+  if (!batch) return fail(QX_EINVAL, "qx_batch_info: NULL batch");
+  if (nsources) *nsources = batch->cfg.nsrc_total;
+  if (chunk) *chunk = batch->chunk;
+  return QX_OK;
 }
 
 extern "C" int qx_batch_destroy(qx_batch_t* batch) {
@@ -1034,6 +1089,8 @@ extern "C" int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_pa
   if (!g64 || !p || !U || !mom || !ws || !H_start || !H_end || p->nsteps < 1)
     return fail(QX_EINVAL, "qx_md_trajectory: bad argument");
   if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "qx_md_trajectory: g64 must be FP64");
+  if (glo && glo->prec == QX_PREC_F16)
+    return fail(QX_EINVAL, "qx_md_trajectory: the solver takes no FP16 gauge handle");
   if (g64->recon == QX_RECON_NAIK || (glo && glo->recon == QX_RECON_NAIK))
     return fail(QX_EINVAL, "qx_md_trajectory: the force is implemented for the one-hop operator");
   if (glo && !same_lattice(g64, glo))
@@ -1224,6 +1281,22 @@ int time_launches(const char* what, hipStream_t caller, int reps, F&& enqueue, f
 }
 
 }  // namespace
+
+extern "C" int qx_tune_cache_load(const char* path) {
+  if (!path || !*path) return fail(QX_EINVAL, "qx_tune_cache_load: no path");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  if (!tune_read_file_locked(path)) return fail(QX_EINVAL, "qx_tune_cache_load: cannot read %s", path);
+  return QX_OK;
+}
+
+extern "C" int qx_tune_cache_save(const char* path) {
+  if (!path || !*path) return fail(QX_EINVAL, "qx_tune_cache_save: no path");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  if (!tune_write_file_locked(path)) return fail(QX_EINVAL, "qx_tune_cache_save: cannot write %s", path);
+  return QX_OK;
+}
 
 extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipStream_t stream) {
   if (!g || nrhs < 1 || !scratch) return fail(QX_EINVAL, "qx_tune_dslash: bad argument");

@@ -4,6 +4,10 @@
 // reductions.
 #pragma once
 
+#include <hip/hip_fp16.h>
+
+#include <type_traits>
+
 #include "qx_internal.h"
 
 // Dynamic LDS of the stencil kernels (16-byte aligned).
@@ -199,6 +203,27 @@ __device__ __forceinline__ cplx<R> ld_cplx(const cplx<R>* __restrict__ base, uns
   }
 }
 
+// Element idx of an array of complex numbers stored as S, returned in the
+// compute type R (FP16 storage widens to FP32).
+template <bool NT, typename R, typename S>
+__device__ __forceinline__ cplx<R> ld_cplx_as(const cplx<S>* __restrict__ base, unsigned idx) {
+  if constexpr (std::is_same_v<S, __half>) {
+    const unsigned* p = reinterpret_cast<const unsigned*>(reinterpret_cast<const char*>(base) +
+                                                          idx * (unsigned)sizeof(cplx<S>));
+    unsigned w;
+    if constexpr (NT)
+      w = __builtin_nontemporal_load(p);
+    else
+      w = *p;
+    __half2 h;
+    __builtin_memcpy(&h, &w, sizeof w);
+    const float2 f = __half22float2(h);
+    return {(R)f.x, (R)f.y};
+  } else {
+    return ld_cplx<NT>(base, idx);
+  }
+}
+
 // Wave index of the calling thread, as a scalar.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
@@ -208,12 +233,13 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // Links are read once per half-Dslash: when they cannot stay in the Infinity
 // Cache anyway they are loaded non-temporally (NT), so that the caches keep
 // the colour vectors, each read by eight neighbouring sites.
-template <typename R, int RECON, bool NT>
-__device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<R>* __restrict__ base,
+// LS: the storage type of the links (R, or FP16 widened to R = float).
+template <typename R, int RECON, bool NT, typename LS>
+__device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<LS>* __restrict__ base,
                                           unsigned idx, size_t hv, int sign) {
   constexpr int E = RECON == 12 ? 6 : 9;
 #pragma unroll
-  for (int e = 0; e < E; ++e) u[e] = ld_cplx<NT>(base + e * hv, idx);
+  for (int e = 0; e < E; ++e) u[e] = ld_cplx_as<NT, R>(base + e * hv, idx);
   if constexpr (RECON == 12) {
     // For W = s U with U in SU(3), s = +-1: row2(W) = s * conj(row0(W) x row1(W)).
     const R s = (R)sign;
@@ -248,13 +274,45 @@ struct FieldIn {
   }
 };
 
+// FP16 colour vectors: per source [3][hv] half-precision complex numbers
+// followed by [hv] FP32 scales (16 bytes per site); element = half * scale.
+struct FieldInH {
+  const char* __restrict__ p;  // first source of the thread
+  size_t hv;
+  __device__ __forceinline__ cplx<float> operator()(int j, int c, int site) const {
+    const char* b = p + (size_t)j * 16 * hv;
+    const cplx<float> v = ld_cplx_as<false, float>(reinterpret_cast<const cplx<__half>*>(b) + c * hv,
+                                                   (unsigned)site);
+    const float sc = reinterpret_cast<const float*>(b + 12 * hv)[site];
+    return {v.re * sc, v.im * sc};
+  }
+};
+
+// Store the colour vector v of site cb into an FP16 source (layout of
+// FieldInH): scale = the largest |re| or |im| of v, pairs = v / scale.
+__device__ __forceinline__ void st_field_h(char* __restrict__ src, size_t hv, int cb,
+                                           const cplx<float> (&v)[3]) {
+  float m = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+  const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const __half2 h = __floats2half2_rn(v[c].re * inv, v[c].im * inv);
+    unsigned w;
+    __builtin_memcpy(&w, &h, sizeof w);
+    reinterpret_cast<unsigned*>(src + (size_t)c * 4 * hv)[cb] = w;
+  }
+  reinterpret_cast<float*>(src + 12 * hv)[cb] = m;
+}
+
 // acc[j] += hop H applied to in_j, j < NBT (bit j of act).
 // Hops 8..15 (RECON == 36) are the three-hop terms, with the links at lf3/lb3.
-template <int H, typename R, int RECON, int NBT, bool NT, typename In>
-__device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restrict__ lf,
-                                            const cplx<R>* __restrict__ lb,
-                                            const cplx<R>* __restrict__ lf3,
-                                            const cplx<R>* __restrict__ lb3, int cb, const Site& s,
+template <int H, typename R, int RECON, int NBT, bool NT, typename In, typename LS>
+__device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __restrict__ lf,
+                                            const cplx<LS>* __restrict__ lb,
+                                            const cplx<LS>* __restrict__ lf3,
+                                            const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
                                             const In& in, unsigned act, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   constexpr int mu = H & 3;
@@ -272,7 +330,7 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
   }
   const int nb = s.template nbr<H>();
   cplx<R> u[9];
-  const cplx<R>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
+  const cplx<LS>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
   load_link<R, RECON, NT>(u, base + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv, sign);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
@@ -298,11 +356,11 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<R>* __restr
 
 // acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT (bit j of act).
 // Each hop is its own instantiation, guarded by a wavefront-uniform test.
-template <typename R, int RECON, int NBT, int LPS, bool NT, typename In>
-__device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<R>* __restrict__ lf,
-                                             const cplx<R>* __restrict__ lb,
-                                             const cplx<R>* __restrict__ lf3,
-                                             const cplx<R>* __restrict__ lb3, int cb, const Site& s,
+template <typename R, int RECON, int NBT, int LPS, bool NT, typename In, typename LS>
+__device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __restrict__ lf,
+                                             const cplx<LS>* __restrict__ lb,
+                                             const cplx<LS>* __restrict__ lf3,
+                                             const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
                                              int dp, const In& in, unsigned act,
                                              cplx<R> (&acc)[NBT][3]) {
 #define QX_HOP(H)                               \
@@ -331,18 +389,18 @@ __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<R>* __rest
 
 // The same for the links of output parity pout; whether the links stream past
 // the caches is decided once per launch (Geo::stream_links).
-template <typename R, int RECON, int NBT, int LPS, typename In>
-__device__ __forceinline__ void stencil_part(const Geo& g, const cplx<R>* __restrict__ links,
+template <typename R, int RECON, int NBT, int LPS, typename In, typename LS>
+__device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __restrict__ links,
                                              int pout, int cb, const Site& s, int dp, const In& in,
                                              unsigned act, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   const size_t hv = (size_t)g.hv;
   // links [parity][mu][e][cb]; the improved operator's three-hop links follow
   // the one-hop ones in the same layout
-  const cplx<R>* lf = links + (size_t)pout * 4 * E * hv;
-  const cplx<R>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
-  const cplx<R>* lf3 = links + (size_t)(2 + pout) * 4 * E * hv;
-  const cplx<R>* lb3 = links + (size_t)(3 - pout) * 4 * E * hv;
+  const cplx<LS>* lf = links + (size_t)pout * 4 * E * hv;
+  const cplx<LS>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
+  const cplx<LS>* lf3 = links + (size_t)(2 + pout) * 4 * E * hv;
+  const cplx<LS>* lb3 = links + (size_t)(3 - pout) * 4 * E * hv;
   if constexpr (RECON == 36) {
     Site s3 = s;
     three_hop_geometry(g, cb, s3);
@@ -402,6 +460,45 @@ __device__ __forceinline__ void for_each_item(const cplx<R> (&acc)[NBT][3], cplx
         }
         f(j, c, t);
       }
+    }
+  }
+}
+
+// As for_each_item, but all three colours of a source slot meet in one
+// wavefront (part j % LPS), for outputs that need the whole colour vector of
+// a site at once (FP16 storage with a per-site scale): f(j, v[3]).
+template <typename R, int NBT, int LPS, typename F>
+__device__ __forceinline__ void for_each_slot(const cplx<R> (&acc)[NBT][3], cplx<R>* red, int dp,
+                                              int grp, int lane, F&& f) {
+  if constexpr (LPS == 1) {
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      const cplx<R> v[3] = {acc[j][0], acc[j][1], acc[j][2]};
+      f(j, v);
+    }
+  } else {
+    cplx<R>* mine = red + (size_t)(grp * LPS + dp) * 3 * 64;
+    const cplx<R>* base = red + (size_t)grp * LPS * 3 * 64;
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (j > 0) __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mine[c * 64 + lane] = acc[j][c];
+      __syncthreads();
+      if (j % LPS != dp) continue;
+      cplx<R> v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cplx<R> t = {(R)0, (R)0};
+#pragma unroll
+        for (int q = 0; q < LPS; ++q) {
+          const cplx<R> w = base[((size_t)q * 3 + c) * 64 + lane];
+          t.re += w.re;
+          t.im += w.im;
+        }
+        v[c] = t;
+      }
+      f(j, v);
     }
   }
 }

@@ -21,6 +21,14 @@ hipError_t with_prec_recon(int prec, int recon, F&& f) {
 }
 
 template <typename F>
+hipError_t with_recon(int recon, F&& f) {
+  if (recon == 18) return f.template operator()<18>();
+  if (recon == 12) return f.template operator()<12>();
+  if (recon == 36) return f.template operator()<36>();
+  return hipErrorInvalidValue;
+}
+
+template <typename F>
 hipError_t with_prec(int prec, F&& f) {
   if (prec == 0) return f.template operator()<double>();
   if (prec == 1) return f.template operator()<float>();

@@ -41,6 +41,39 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const c
   });
 }
 
+// As k_dslash for FP16 storage (links and colour vectors with per-site
+// scales), FP32 arithmetic; each output site is written with its own scale.
+template <int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_dslash_h(
+    Geo g, const cplx<__half>* __restrict__ links, int pout, const char* __restrict__ in,
+    char* __restrict__ out, int nsrc, float scale, int xcd) {
+  cplx<float>* red = reinterpret_cast<cplx<float>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int dp = w % LPS, grp = w / LPS;
+  const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
+  const size_t hv = g.hv, ss = 16 * hv;
+  const int k0 = grp * NBT;
+  unsigned act = 0;
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
+  cplx<float> acc[NBT][3];
+  zero_acc<float, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(g, pout, cb, s);
+    stencil_part<float, RECON, NBT, LPS>(g, links, pout, cb, s, dp, FieldInH{in + k0 * ss, hv},
+                                         act, acc);
+  }
+  for_each_slot<float, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, const cplx<float>(&v)[3]) {
+    if (!(act >> j & 1u)) return;
+    const cplx<float> o[3] = {{scale * v[0].re, scale * v[0].im},
+                              {scale * v[1].re, scale * v[1].im},
+                              {scale * v[2].re, scale * v[2].im}};
+    st_field_h(out + (k0 + j) * ss, hv, cb, o);
+  });
+}
+
 struct Masses16 {
   double m2[16];
 };
@@ -79,6 +112,40 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_deo_axpy(Geo g, const
   }
 }
 
+// As k_deo_axpy for FP16 storage, FP32 arithmetic.
+template <int RECON, int NBT>
+__global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_deo_axpy_h(
+    Geo g, const cplx<__half>* __restrict__ links, const char* __restrict__ t,
+    const char* __restrict__ p, char* __restrict__ out, int nsrc, Masses16 m, int xcd) {
+  const int lane = threadIdx.x & 63, grp = wave_id();
+  const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
+  const size_t hv = g.hv, ss = 16 * hv;
+  const int k0 = grp * NBT;
+  unsigned act = 0;
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
+  if (!act) return;
+  cplx<float> acc[NBT][3];
+  zero_acc<float, NBT>(acc);
+  Site s;
+  site_geometry(g, 0, cb, s);
+  stencil_part<float, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldInH{t + k0 * ss, hv}, act, acc);
+  const FieldInH pin{p + k0 * ss, hv};
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    if (!(act >> j & 1u)) continue;
+    const float m2 = (float)m.m2[k0 + j];
+    cplx<float> o[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cplx<float> pv = pin(j, c, cb);
+      o[c] = {m2 * pv.re - 0.25f * acc[j][c].re, m2 * pv.im - 0.25f * acc[j][c].im};
+    }
+    st_field_h(out + (k0 + j) * ss, hv, cb, o);
+  }
+}
+
 namespace {
 // Most sources one launch of this shape can take.
 int sources_per_pass(const LaunchShape& sh, size_t csz) {
@@ -93,10 +160,10 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
                          hipStream_t s) {
   const size_t csz = cplx_bytes(prec);
   if (!nbt_lps_instantiated(sh.nbt, sh.lps) || !shape_ok(sh, 1, csz)) return hipErrorInvalidValue;
-  const size_t field = (size_t)3 * g.hv * csz;
+  const size_t field = source_bytes(g, prec);
   const int per = sources_per_pass(sh, csz);
   const unsigned grid = grid_for(g.hv, kTile);
-  const size_t link_bytes = (size_t)8 * g.hv * (recon / 2) * csz;
+  const size_t link_bytes = (size_t)8 * g.hv * (recon / 2) * link_cplx_bytes(prec);
   for (int k0 = 0; k0 < nsrc; k0 += per) {
     const int n = std::min(per, nsrc - k0);
     const int threads = 64 * sh.lps * shape_groups(sh, n);
@@ -105,6 +172,17 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
     const size_t lds = shape_lds(sh, n, csz);
     const char* pin = (const char*)in + k0 * field;
     char* po = (char*)out + k0 * field;
+    if (prec == 2) {
+      hipError_t e = with_recon(recon, [&]<int RECON>() {
+        return with_nbt_lps(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
+          hipLaunchKernelGGL((k_dslash_h<RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, gl,
+                             (const cplx<__half>*)links, pout, pin, po, n, (float)scale, sh.xcd);
+          return hipGetLastError();
+        });
+      });
+      if (e != hipSuccess) return e;
+      continue;
+    }
     hipError_t e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
       return with_nbt_lps(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
         hipLaunchKernelGGL((k_dslash<R, RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, gl,
@@ -123,7 +201,7 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
                           hipStream_t s) {
   hipError_t e = launch_dslash(g, prec, recon, links, 1, in, tmp, nrhs, 1.0, sh, s);
   if (e != hipSuccess) return e;
-  const size_t field = (size_t)3 * g.hv * cplx_bytes(prec);
+  const size_t field = source_bytes(g, prec);
   const int per = 16;  // Masses16 holds one pass
   const unsigned grid = grid_for(g.hv, kTile);
   for (int k0 = 0; k0 < nrhs; k0 += per) {
@@ -131,6 +209,18 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
     Masses16 m{};
     for (int k = 0; k < n; ++k) m.m2[k] = m2[k0 + k];
     const int threads = 64 * ((n + sh.nbt - 1) / sh.nbt);
+    if (prec == 2) {
+      e = with_recon(recon, [&]<int RECON>() {
+        return with_nbt(sh.nbt, [&]<int NBT>() {
+          hipLaunchKernelGGL((k_deo_axpy_h<RECON, NBT>), dim3(grid), dim3(threads), 0, s, g,
+                             (const cplx<__half>*)links, (const char*)tmp + k0 * field,
+                             (const char*)in + k0 * field, (char*)out + k0 * field, n, m, sh.xcd);
+          return hipGetLastError();
+        });
+      });
+      if (e != hipSuccess) return e;
+      continue;
+    }
     e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
       return with_nbt(sh.nbt, [&]<int NBT>() {
         hipLaunchKernelGGL((k_deo_axpy<R, RECON, NBT>), dim3(grid), dim3(threads), 0, s, g,

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 
+#include "../../include/qx.h"
 #include "qx_device.h"
 #include "qx_dispatch.h"
 #include "qx_launch.h"
@@ -19,6 +20,15 @@
 namespace qx {
 
 // =================================================================== packing
+
+// An FP64 value in the storage type S (FP16 rounds through FP32).
+template <typename S>
+__device__ __forceinline__ S to_store(double x) {
+  if constexpr (std::is_same_v<S, __half>)
+    return __float2half_rn((float)x);
+  else
+    return (S)x;
+}
 
 // Canonical complex128 [4][V][3][3] -> packed [parity][mu][e][cb] with the
 // staggered phase and boundary sign folded in.  With 12-real storage the FP64
@@ -50,7 +60,8 @@ __global__ void __launch_bounds__(256) k_pack_gauge(Geo g, const cplx<double>* _
     for (int e = 0; e < 9; ++e) v[e] = u[e];
     cplx<R>* o = out + (size_t)(p * 4 + mu) * E * g.hv + cb;
 #pragma unroll
-    for (int e = 0; e < E; ++e) o[(size_t)e * g.hv] = {(R)(sg * v[e].re), (R)(sg * v[e].im)};
+    for (int e = 0; e < E; ++e)
+      o[(size_t)e * g.hv] = {to_store<R>(sg * v[e].re), to_store<R>(sg * v[e].im)};
     if constexpr (RECON == 12) {
       // row 2 against conj(row0 x row1)
       const cplx<double> a0 = cmul(v[1], v[5]), b0 = cmul(v[2], v[4]);
@@ -99,6 +110,50 @@ __global__ void __launch_bounds__(256) k_unpack_field(int hv, int nsrc,
   for (int c = 0; c < 3; ++c) {
     const cplx<R> v = in[(s * 3 + c) * hv + cb];
     out[i * 3 + c] = {(double)v.re, (double)v.im};
+  }
+}
+
+// canonical complex128 [nsrc][hv][3] -> FP16 packed: per source [3][hv]
+// binary16 pairs, then [hv] FP32 scales.  The scale of a site is the largest
+// |re| or |im| of its three colours (as FP32); the stored pairs are the
+// components divided by it (zero where the scale is zero).
+__global__ void __launch_bounds__(256) k_pack_field_h(int hv, int nsrc,
+                                                      const cplx<double>* __restrict__ in,
+                                                      char* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nsrc * hv) return;
+  const int64_t s = i / hv, cb = i - s * hv;
+  cplx<double> v[3];
+  double m = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    v[c] = in[i * 3 + c];
+    m = fmax(m, fmax(fabs(v[c].re), fabs(v[c].im)));
+  }
+  const float sc = (float)m;
+  const double inv = sc > 0.0f ? 1.0 / (double)sc : 0.0;
+  char* b = out + s * 16 * (int64_t)hv;
+  cplx<__half>* h = reinterpret_cast<cplx<__half>*>(b);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    h[c * (int64_t)hv + cb] = {__float2half_rn((float)(v[c].re * inv)),
+                               __float2half_rn((float)(v[c].im * inv))};
+  reinterpret_cast<float*>(b + 12 * (int64_t)hv)[cb] = sc;
+}
+
+__global__ void __launch_bounds__(256) k_unpack_field_h(int hv, int nsrc,
+                                                        const char* __restrict__ in,
+                                                        cplx<double>* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nsrc * hv) return;
+  const int64_t s = i / hv, cb = i - s * hv;
+  const char* b = in + s * 16 * (int64_t)hv;
+  const cplx<__half>* h = reinterpret_cast<const cplx<__half>*>(b);
+  const double sc = (double)reinterpret_cast<const float*>(b + 12 * (int64_t)hv)[cb];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cplx<__half> v = h[c * (int64_t)hv + cb];
+    out[i * 3 + c] = {(double)__half2float(v.re) * sc, (double)__half2float(v.im) * sc};
   }
 }
 
@@ -160,7 +215,8 @@ __global__ void __launch_bounds__(256) k_pack_gauge_naik(Geo g, const cplx<doubl
       cplx<R>* o = out + (size_t)(p * 4 + mu) * 9 * g.hv + cb;
       const double c = 1.125 * eta * sgn;
 #pragma unroll
-      for (int e = 0; e < 9; ++e) o[(size_t)e * g.hv] = {(R)(c * P[e].re), (R)(c * P[e].im)};
+      for (int e = 0; e < 9; ++e)
+        o[(size_t)e * g.hv] = {to_store<R>(c * P[e].re), to_store<R>(c * P[e].im)};
     } else {
       cplx<double> Q[9];
 #pragma unroll
@@ -184,12 +240,26 @@ __global__ void __launch_bounds__(256) k_pack_gauge_naik(Geo g, const cplx<doubl
   cplx<R>* o = out + (size_t)(8 + p * 4 + mu) * 9 * g.hv + cb;
   const double c = (-1.0 / 24.0) * eta * sgn;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) o[(size_t)e * g.hv] = {(R)(c * P[e].re), (R)(c * P[e].im)};
+  for (int e = 0; e < 9; ++e) o[(size_t)e * g.hv] = {to_store<R>(c * P[e].re), to_store<R>(c * P[e].im)};
 }
 
 hipError_t launch_pack_gauge(const Geo& g, const void* U, int prec, int recon, void* packed,
                              unsigned long long* err_bits, hipStream_t s) {
   const size_t n = 8 * (size_t)g.hv;
+  if (prec == 2) {
+    const unsigned grid = grid_for(n, 256);
+    const cplx<double>* u = (const cplx<double>*)U;
+    cplx<__half>* o = (cplx<__half>*)packed;
+    if (recon == 36)
+      hipLaunchKernelGGL(k_pack_gauge_naik<__half>, dim3(grid), dim3(256), 0, s, g, u, o);
+    else if (recon == 18)
+      hipLaunchKernelGGL((k_pack_gauge<__half, 18>), dim3(grid), dim3(256), 0, s, g, u, o, err_bits);
+    else if (recon == 12)
+      hipLaunchKernelGGL((k_pack_gauge<__half, 12>), dim3(grid), dim3(256), 0, s, g, u, o, err_bits);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (recon == 36)
     return with_prec(prec, [&]<typename R>() {
       hipLaunchKernelGGL(k_pack_gauge_naik<R>, dim3(grid_for(n, 256)), dim3(256), 0, s, g,
@@ -210,7 +280,10 @@ hipError_t launch_pack_gauge(const Geo& g, const void* U, int prec, int recon, v
 hipError_t launch_pack_field(const Geo& g, int nrhs, int prec, const void* canon, void* packed,
                              hipStream_t s) {
   const size_t n = (size_t)nrhs * g.hv;
-  if (prec == 0)
+  if (prec == 2)
+    hipLaunchKernelGGL(k_pack_field_h, dim3(grid_for(n, 256)), dim3(256), 0, s, g.hv, nrhs,
+                       (const cplx<double>*)canon, (char*)packed);
+  else if (prec == 0)
     hipLaunchKernelGGL(k_pack_field<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, g.hv, nrhs,
                        (const cplx<double>*)canon, (cplx<double>*)packed);
   else
@@ -222,12 +295,40 @@ hipError_t launch_pack_field(const Geo& g, int nrhs, int prec, const void* canon
 hipError_t launch_unpack_field(const Geo& g, int nrhs, int prec, const void* packed, void* canon,
                                hipStream_t s) {
   const size_t n = (size_t)nrhs * g.hv;
-  if (prec == 0)
+  if (prec == 2)
+    hipLaunchKernelGGL(k_unpack_field_h, dim3(grid_for(n, 256)), dim3(256), 0, s, g.hv, nrhs,
+                       (const char*)packed, (cplx<double>*)canon);
+  else if (prec == 0)
     hipLaunchKernelGGL(k_unpack_field<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, g.hv,
                        nrhs, (const cplx<double>*)packed, (cplx<double>*)canon);
   else
     hipLaunchKernelGGL(k_unpack_field<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, g.hv,
                        nrhs, (const cplx<float>*)packed, (cplx<double>*)canon);
+  return hipGetLastError();
+}
+
+// Per-source statistics of a solve from the device states (no host copy): a
+// source that has not finished reports QX_ENOTCONVERGED, and a timed-out grid
+// barrier of the persistent engine QX_EHIP for every source.
+__global__ void __launch_bounds__(256) k_batch_stats(const SrcState* __restrict__ st, int n,
+                                                     const GridSync* __restrict__ gs,
+                                                     qx_cg_stats_t* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const SrcState q = st[k];
+  qx_cg_stats_t r;
+  r.status = q.phase == PH_DONE ? q.status : QX_ENOTCONVERGED;
+  if (gs && gs->error) r.status = QX_EHIP;
+  r.iters = q.iters;
+  r.reliable_updates = q.updates;
+  r.true_rel_residual = q.relres;
+  r.seconds = 0.0;
+  out[k] = r;
+}
+
+hipError_t launch_batch_stats(const void* st, int n, const void* gs, void* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_stats, dim3(grid_for((size_t)n, 256)), dim3(256), 0, s,
+                     (const SrcState*)st, n, (const GridSync*)gs, (qx_cg_stats_t*)out);
   return hipGetLastError();
 }
 

@@ -33,8 +33,16 @@ inline bool shape_ok(const LaunchShape& s, int nsrc, size_t cplx_sz) {
   return waves <= max_waves(s.nbt, cplx_sz) && shape_lds(s, nsrc, cplx_sz) <= 64 * 1024;
 }
 
-// Bytes of one complex number of the given precision (QX_PREC_F64 = 0 -> 16, F32 -> 8).
+// Bytes of one complex number of the arithmetic of the given precision
+// (QX_PREC_F64 = 0 -> 16; F32 and F16, which computes in FP32 -> 8).
 inline size_t cplx_bytes(int prec) { return prec == 0 ? 16 : 8; }
+// Bytes of one stored complex link element (F16 = 2 -> 4).
+inline size_t link_cplx_bytes(int prec) { return prec == 0 ? 16 : prec == 1 ? 8 : 4; }
+// Bytes of one packed source of a half-lattice field: [3][hv] complex, or for
+// F16 [3][hv] binary16 pairs and [hv] FP32 scales.
+inline size_t source_bytes(const Geo& g, int prec) {
+  return prec == 2 ? (size_t)16 * g.hv : (size_t)3 * g.hv * cplx_bytes(prec);
+}
 
 hipError_t launch_pack_gauge(const Geo& g, const void* U, int prec, int recon, void* packed,
                              unsigned long long* err_bits, hipStream_t s);
@@ -43,6 +51,9 @@ hipError_t launch_pack_field(const Geo& g, int nrhs, int prec, const void* canon
 hipError_t launch_unpack_field(const Geo& g, int nrhs, int prec, const void* packed, void* canon,
                                hipStream_t s);
 hipError_t launch_index_maps(const Geo& g, int32_t* lex_of_eo, int32_t* nbr_eo, hipStream_t s);
+// st: n SrcState (device); gs: the persistent engine's GridSync or nullptr;
+// out: n qx_cg_stats_t (device).
+hipError_t launch_batch_stats(const void* st, int n, const void* gs, void* out, hipStream_t s);
 
 // out = scale * (2D) in, from parity 1 - pout to pout, nsrc sources (any count;
 // passes of at most 16 * nbt sources).

@@ -55,3 +55,39 @@ def test_host_only_calls(lib):
     assert lib.qx_field_bytes(h, 3, 0, ctypes.byref(n)) == 0
     assert n.value == 3 * 3 * 256 * 16
     lib.qx_lattice_destroy(h)
+
+
+def test_f16_sizes(lib):
+    """FP16 storage: 4-byte link elements; 16 bytes per site and source (three
+    binary16 pairs and one FP32 scale)."""
+    h = ctypes.c_void_p()
+    assert lib.qx_lattice_create((ctypes.c_int32 * 4)(4, 4, 4, 8), 0, ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert lib.qx_gauge_bytes(h, 2, 12, ctypes.byref(n)) == 0
+    assert n.value == 8 * 256 * 6 * 4
+    assert lib.qx_gauge_bytes(h, 2, 36, ctypes.byref(n)) == 0
+    assert n.value == 8 * 256 * 18 * 4
+    assert lib.qx_field_bytes(h, 3, 2, ctypes.byref(n)) == 0
+    assert n.value == 3 * 256 * 16
+    assert lib.qx_field_bytes(h, 1, 3, ctypes.byref(n)) == 1  # no such precision
+    lib.qx_lattice_destroy(h)
+
+
+def test_tune_cache_roundtrip(lib, tmp_path):
+    """Entries loaded from a file come back from a save; malformed entries and
+    shapes that are not compiled are skipped; unreadable files are errors."""
+    src = tmp_path / "in.json"
+    src.write_text('{\n  "gfx950:4x4x4x8:p1:r12:n3": [2, 2, 1],\n'
+                   '  "gfx950:4x4x4x8:p0:r18:n1": [4, 8, 0],\n'
+                   '  "gfx950:8x8x8x8:p2:r36:n1": [1, 8, 7],\n'
+                   '  "broken": [1, 2]\n}\n')
+    assert lib.qx_tune_cache_load(str(src).encode()) == 0
+    out = tmp_path / "out.json"
+    assert lib.qx_tune_cache_save(str(out).encode()) == 0
+    txt = out.read_text()
+    assert '"gfx950:4x4x4x8:p1:r12:n3": [2, 2, 1]' in txt
+    assert '"gfx950:8x8x8x8:p2:r36:n1": [1, 8, 3]' in txt  # order clamped to 0..3
+    assert "p0:r18:n1" not in txt and "broken" not in txt
+    assert lib.qx_tune_cache_load(str(tmp_path / "missing.json").encode()) == 1
+    assert lib.qx_tune_cache_save(str(tmp_path / "no" / "dir.json").encode()) == 1
+    assert lib.qx_tune_cache_load(None) == 1
