@@ -58,6 +58,7 @@ _D = ctypes.c_double
 
 
 def _declare(L):
+    L.oracle_threads.argtypes = []
     L.oracle_index_maps.argtypes = [_P, _P, _P]
     L.oracle_dslash_full.argtypes = [_P, _I, _P, _P, _P]
     L.oracle_dslash_eo.argtypes = [_P, _I, _P, _I, _P, _P]
@@ -92,6 +93,11 @@ def _check(st, what):
 
 def volume(dims) -> int:
     return int(np.prod(np.asarray(dims, dtype=np.int64)))
+
+
+def threads() -> int:
+    """OpenMP threads of the oracle's parallel loops."""
+    return int(lib().oracle_threads())
 
 
 def index_maps(dims):

@@ -52,6 +52,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -112,6 +113,9 @@ static int dims_ok(const int L[4]) {
  * nbr_eo[8*eo + k] is the eo index of x + mu (k = mu) and x - mu (k = 4 + mu)
  * with periodic wrap.
  */
+/* Threads an OpenMP loop of the oracle runs on. */
+int oracle_threads(void) { return omp_get_max_threads(); }
+
 int oracle_index_maps(const int L[4], int32_t* lex_of_eo, int32_t* nbr_eo) {
   if (!dims_ok(L)) return ORACLE_EINVAL;
   const int64_t V = vol4(L), hv = V / 2;
