@@ -89,24 +89,24 @@ BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colou
 # From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
 # launch shape "nbt,lps,order".
 TRAFFIC = {
-    "sha": "0d938a97f6c83fe7",
+    "sha": "7e0258174f87e9fb",
     "bytes": {
-        "1,1,0": 16657408,
-        "1,1,1": 15084544,
-        "1,1,2": 14887936,
-        "1,1,3": 14887936,
-        "1,2,0": 16677888,
-        "1,2,1": 15105024,
-        "1,2,2": 14908416,
-        "1,2,3": 14908416,
-        "1,4,0": 16648192,
-        "1,4,1": 15075328,
-        "1,4,2": 14886912,
-        "1,4,3": 14886912,
-        "1,8,0": 16690176,
-        "1,8,1": 15117312,
-        "1,8,2": 14920704,
-        "1,8,3": 14920704
+        "1,1,0": 16251904,
+        "1,1,1": 15072256,
+        "1,1,2": 14875648,
+        "1,1,3": 14875648,
+        "1,2,0": 16271360,
+        "1,2,1": 15091712,
+        "1,2,2": 14895104,
+        "1,2,3": 14895104,
+        "1,4,0": 16267264,
+        "1,4,1": 15087616,
+        "1,4,2": 14891008,
+        "1,4,3": 14891008,
+        "1,8,0": 16287744,
+        "1,8,1": 15108096,
+        "1,8,2": 14911488,
+        "1,8,3": 14911552
     },
 }
 KERNEL_SOURCES = ("qx_dslash.hip", "qx_device.h", "qx_internal.h", "qx_launch.h", "qx_dispatch.h")

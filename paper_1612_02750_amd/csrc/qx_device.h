@@ -227,19 +227,89 @@ __device__ __forceinline__ cplx<R> ld_cplx_as(const cplx<S>* __restrict__ base, 
 // Wave index of the calling thread, as a scalar.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
-// Packed links: [parity][mu][element][cb], element e = 3 * row + column, E = 9
-// (18 reals) or 6 (12 reals: rows 0 and 1).  base points at element 0 of
-// direction mu of one parity; idx is the checkerboard index of the link.
-// Links are read once per half-Dslash: when they cannot stay in the Infinity
-// Cache anyway they are loaded non-temporally (NT), so that the caches keep
-// the colour vectors, each read by eight neighbouring sites.
+// Packed links: one region per (parity, mu) of E elements (e = 3 * row +
+// column; E = 9 for 18 reals, 6 for 12 reals: rows 0 and 1) for each of the
+// hv links, E * C * hv bytes for C-byte complex numbers.  Inside a region the
+// elements are grouped in chunks of W = 16 / C consecutive elements (FP64 1,
+// FP32 2, FP16 4); chunk J occupies bytes [16 J hv, 16 (J + 1) hv) (or less for
+// a last, partial chunk) as [cb][elements of the chunk], so that a link is read
+// with 16-byte loads in every precision.  FP64 keeps the plain [e][cb] order.
+template <typename LS, int E>
+__host__ __device__ constexpr size_t link_elem_offset(int e, size_t hv, size_t cb) {
+  constexpr int C = (int)sizeof(cplx<LS>), K = 16, W = K / C;
+  const int J = e / W, n = (E - J * W) < W ? (E - J * W) : W;
+  return (size_t)J * K * hv + cb * (size_t)(n * C) + (size_t)(e % W) * C;
+}
+
+// NW 32-bit words at base + off (off formed in 32 bits, as in ld_cplx).
+template <int NW, bool NT>
+__device__ __forceinline__ void ld_words(const char* __restrict__ base, unsigned off,
+                                         unsigned (&w)[NW]) {
+  if constexpr (NW == 1) {
+    const unsigned* q = reinterpret_cast<const unsigned*>(base + off);
+    if constexpr (NT)
+      w[0] = __builtin_nontemporal_load(q);
+    else
+      w[0] = *q;
+  } else {
+    typedef unsigned vw __attribute__((ext_vector_type(NW)));
+    const vw* q = reinterpret_cast<const vw*>(base + off);
+    vw t;
+    if constexpr (NT)
+      t = __builtin_nontemporal_load(q);
+    else
+      t = *q;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = t[i];
+  }
+}
+
+// The complex number stored as LS in words w[0 .. sizeof(cplx<LS>) / 4), as R.
+template <typename R, typename LS>
+__device__ __forceinline__ cplx<R> cplx_from_words(const unsigned* w) {
+  if constexpr (std::is_same_v<LS, __half>) {
+    __half2 h;
+    __builtin_memcpy(&h, w, sizeof h);
+    const float2 f = __half22float2(h);
+    return {(R)f.x, (R)f.y};
+  } else {
+    cplx<LS> v;
+    __builtin_memcpy(&v, w, sizeof v);
+    return {(R)v.re, (R)v.im};
+  }
+}
+
+// Elements of chunks J, J + 1, ... of one link (layout above).
+template <typename R, typename LS, bool NT, int E, int J>
+__device__ __forceinline__ void load_link_chunks(cplx<R> (&u)[9], const char* __restrict__ region,
+                                                 unsigned idx, size_t hv) {
+  constexpr int C = (int)sizeof(cplx<LS>), K = 16, W = K / C;
+  if constexpr (J * W < E) {
+    constexpr int N = (E - J * W) < W ? (E - J * W) : W;
+    unsigned w[N * C / 4];
+    ld_words<N * C / 4, NT>(region + (size_t)J * K * hv, idx * (unsigned)(N * C), w);
+#pragma unroll
+    for (int n = 0; n < N; ++n) u[J * W + n] = cplx_from_words<R, LS>(w + n * (C / 4));
+    load_link_chunks<R, LS, NT, E, J + 1>(u, region, idx, hv);
+  }
+}
+
+// Link idx of the region that starts at base (element 0 of direction mu of one
+// parity).  Links are read once per half-Dslash: when they cannot stay in the
+// Infinity Cache anyway they are loaded non-temporally (NT), so that the
+// caches keep the colour vectors, each read by eight neighbouring sites.
 // LS: the storage type of the links (R, or FP16 widened to R = float).
 template <typename R, int RECON, bool NT, typename LS>
 __device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<LS>* __restrict__ base,
                                           unsigned idx, size_t hv, int sign) {
   constexpr int E = RECON == 12 ? 6 : 9;
+  if constexpr (sizeof(cplx<LS>) == 16) {
+    // one element per chunk: the plain [e][cb] order
 #pragma unroll
-  for (int e = 0; e < E; ++e) u[e] = ld_cplx_as<NT, R>(base + e * hv, idx);
+    for (int e = 0; e < E; ++e) u[e] = ld_cplx<NT>(base + e * hv, idx);
+  } else {
+    load_link_chunks<R, LS, NT, E, 0>(u, reinterpret_cast<const char*>(base), idx, hv);
+  }
   if constexpr (RECON == 12) {
     // For W = s U with U in SU(3), s = +-1: row2(W) = s * conj(row0(W) x row1(W)).
     const R s = (R)sign;
@@ -395,7 +465,7 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __res
                                              unsigned act, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   const size_t hv = (size_t)g.hv;
-  // links [parity][mu][e][cb]; the improved operator's three-hop links follow
+  // link regions [parity][mu] (link_elem_offset); the improved operator's three-hop links follow
   // the one-hop ones in the same layout
   const cplx<LS>* lf = links + (size_t)pout * 4 * E * hv;
   const cplx<LS>* lb = links + (size_t)(1 - pout) * 4 * E * hv;

@@ -30,8 +30,9 @@ __device__ __forceinline__ S to_store(double x) {
     return (S)x;
 }
 
-// Canonical complex128 [4][V][3][3] -> packed [parity][mu][e][cb] with the
-// staggered phase and boundary sign folded in.  With 12-real storage the FP64
+// Canonical complex128 [4][V][3][3] -> packed links (one region per parity
+// and mu, elements in 16-byte chunks, link_elem_offset) with the staggered
+// phase and boundary sign folded in.  With 12-real storage the FP64
 // reconstruction error of the canonical link is max-reduced into err_bits.
 template <typename R, int RECON>
 __global__ void __launch_bounds__(256) k_pack_gauge(Geo g, const cplx<double>* __restrict__ U,
@@ -58,10 +59,11 @@ __global__ void __launch_bounds__(256) k_pack_gauge(Geo g, const cplx<double>* _
     cplx<double> v[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) v[e] = u[e];
-    cplx<R>* o = out + (size_t)(p * 4 + mu) * E * g.hv + cb;
+    char* o = reinterpret_cast<char*>(out + (size_t)(p * 4 + mu) * E * g.hv);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      o[(size_t)e * g.hv] = {to_store<R>(sg * v[e].re), to_store<R>(sg * v[e].im)};
+      *reinterpret_cast<cplx<R>*>(o + link_elem_offset<R, E>(e, g.hv, cb)) = {
+          to_store<R>(sg * v[e].re), to_store<R>(sg * v[e].im)};
     if constexpr (RECON == 12) {
       // row 2 against conj(row0 x row1)
       const cplx<double> a0 = cmul(v[1], v[5]), b0 = cmul(v[2], v[4]);
@@ -177,8 +179,9 @@ __global__ void __launch_bounds__(256) k_index_maps(Geo g, int32_t* __restrict__
 // Links of the improved operator (one-hop and Naik three-hop terms): for
 // every (mu, site x) the one-hop link 9/8 eta bc U_mu(x) and the three-hop
 // transporter -1/24 eta bc(x) bc(x+mu) bc(x+2mu) U_mu(x) U_mu(x+mu) U_mu(x+2mu)
-// (eta_mu is the same at the three sites), products in FP64.  Layout
-// [kind][parity][mu][9][cb]: kind 0 the one-hop links, kind 1 the three-hop.
+// (eta_mu is the same at the three sites), products in FP64.  Regions
+// [kind][parity][mu] of 9-element links (link_elem_offset): kind 0 the
+// one-hop links, kind 1 the three-hop.
 template <typename R>
 __global__ void __launch_bounds__(256) k_pack_gauge_naik(Geo g, const cplx<double>* __restrict__ U,
                                                          cplx<R>* __restrict__ out) {
@@ -212,11 +215,12 @@ __global__ void __launch_bounds__(256) k_pack_gauge_naik(Geo g, const cplx<doubl
     if (step == 0) {
 #pragma unroll
       for (int e = 0; e < 9; ++e) P[e] = u[e];
-      cplx<R>* o = out + (size_t)(p * 4 + mu) * 9 * g.hv + cb;
+      char* o = reinterpret_cast<char*>(out + (size_t)(p * 4 + mu) * 9 * g.hv);
       const double c = 1.125 * eta * sgn;
 #pragma unroll
       for (int e = 0; e < 9; ++e)
-        o[(size_t)e * g.hv] = {to_store<R>(c * P[e].re), to_store<R>(c * P[e].im)};
+        *reinterpret_cast<cplx<R>*>(o + link_elem_offset<R, 9>(e, g.hv, cb)) = {
+            to_store<R>(c * P[e].re), to_store<R>(c * P[e].im)};
     } else {
       cplx<double> Q[9];
 #pragma unroll
@@ -237,10 +241,12 @@ __global__ void __launch_bounds__(256) k_pack_gauge_naik(Geo g, const cplx<doubl
     }
     y[mu] = y[mu] + 1 == L[mu] ? 0 : y[mu] + 1;
   }
-  cplx<R>* o = out + (size_t)(8 + p * 4 + mu) * 9 * g.hv + cb;
+  char* o = reinterpret_cast<char*>(out + (size_t)(8 + p * 4 + mu) * 9 * g.hv);
   const double c = (-1.0 / 24.0) * eta * sgn;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) o[(size_t)e * g.hv] = {to_store<R>(c * P[e].re), to_store<R>(c * P[e].im)};
+  for (int e = 0; e < 9; ++e)
+    *reinterpret_cast<cplx<R>*>(o + link_elem_offset<R, 9>(e, g.hv, cb)) = {
+        to_store<R>(c * P[e].re), to_store<R>(c * P[e].im)};
 }
 
 hipError_t launch_pack_gauge(const Geo& g, const void* U, int prec, int recon, void* packed,
