@@ -19,6 +19,8 @@ Reported beside it (same run):
   * the improved operator (Naik term): Dslash at 32^4 / 48^4 and a 16^4 CG;
   * one HMC molecular-dynamics trajectory on 16^4 and point-source meson
     correlators on 16^3 x 32;
+  * the uneven batch (8^4 ... 24^4, four sources each) replayed as one graph
+    against its systems solved one at a time, and the 16^4 fermion force;
   * the CPU oracle (FP64 CG on the host cores) on the same system, whole
     solves repeated for about 10 s.
 
@@ -379,6 +381,85 @@ def multi_rhs(torch, qx, synth):
     return out
 
 
+def uneven_batch(torch, qx, synth):
+    """Lattices 8^4, 12^4, 16^4, 16^3 x 32 and 24^4 with weak-field links
+    (eps in [0.2, 0.5] by seed), four Gaussian sources each, masses from
+    {0.01, 0.05, 0.1}, FP32 12-real inner / FP64 reliable updates to 1e-10:
+    the whole batch replayed from its HIP graph against the same systems
+    solved one after another (each as its own batch)."""
+    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (16, 16, 16, 32), (24, 24, 24, 24)]
+    mlist = [0.01, 0.05, 0.1]
+    systems = []
+    for k, dims in enumerate(shapes):
+        eps = float(np.random.Generator(np.random.PCG64(1000 + k)).uniform(0.2, 0.5))
+        lat = qx.Lattice(dims)
+        Ud = torch.from_numpy(synth.weak_gauge(dims, eps, k)).cuda()
+        g64 = qx.Gauge(lat, Ud, "f64", 18)
+        g32 = qx.Gauge(lat, Ud, "f32", 12)
+        g32.tune(4)
+        bd = torch.from_numpy(synth.gauss_source(4, lat.hv, 100 + k)).cuda()
+        systems.append((g64, g32, bd, [mlist[(k + j) % 3] for j in range(4)], torch.empty_like(bd)))
+    batch = qx.Batch(systems, tol=1e-10, mode=qx.CG_MIXED_F32)
+    singles = [qx.Batch([s], tol=1e-10, mode=qx.CG_MIXED_F32) for s in systems]
+    batch.solve()
+    for b in singles:
+        b.solve()
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = batch.solve()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st1 = [x for b in singles for x in b.solve()]
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    out = {
+        "workload": "8^4, 12^4, 16^4, 16^3x32, 24^4 weak fields, 4 sources each, mixed to 1e-10",
+        "batch_ms": round(t_batch * 1e3, 3),
+        "one_system_at_a_time_ms": round(t_single * 1e3, 3),
+        "speedup": round(t_single / t_batch, 3),
+        "iters_max": max(x.iters for x in st),
+        "max_true_rel_residual": max(max(x.true_rel_residual for x in st),
+                                     max(x.true_rel_residual for x in st1)),
+        "all_converged": all(x.status == qx.OK for x in st + st1),
+    }
+    log(f"uneven batch: {out}")
+    return out
+
+
+def force_16(torch, qx, synth):
+    """Fermion force of S = phi^dag A^-1 phi on 16^4 Haar links, m = 0.1: the
+    solve (FP32 12-real inner, FP64 reliable updates, to 1e-10), D_oe of the
+    solution and the per-link outer products, as one call."""
+    dims, m = (16, 16, 16, 16), 0.1
+    lat = qx.Lattice(dims)
+    Ud = torch.from_numpy(synth.haar_gauge(dims, 0)).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", 18)
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    g32.tune(1)
+    phi = torch.from_numpy(synth.gauss_source(1, lat.hv, 1)).cuda()
+    qx.force(g64, phi, m, glo=g32)
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S, G, x, st = qx.force(g64, phi, m, glo=g32)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    out = {
+        "workload": "16^4 Haar links, Gaussian phi, m=0.1, mixed solve to 1e-10 + force",
+        "ms": round(t * 1e3, 3),
+        "cg_iters": st[0].iters,
+        "true_rel_residual": st[0].true_rel_residual,
+        "action": float(S),
+    }
+    log(f"16^4 force: {out}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -486,6 +567,8 @@ def main():
     naik = naik_cg(torch, qx, synth)
     md = hmc_md(torch, qx, synth)
     mes = mesons(torch, qx, synth)
+    uneven = uneven_batch(torch, qx, synth)
+    frc = force_16(torch, qx, synth)
 
 
     # ------------------------------------------------------------ CPU oracle
@@ -564,6 +647,8 @@ def main():
         "naik_cg_16^4": naik,
         "hmc_md_16^4": md,
         "mesons_16^3x32": mes,
+        "uneven_batch": uneven,
+        "force_16^4": frc,
         "copy_probe_gbs": round(copy_gbs, 1),
         "read_probe_gbs": round(read_gbs, 1),
         "cpu_baseline": cpu,
