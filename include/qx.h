@@ -105,17 +105,24 @@ typedef struct qx_batch qx_batch_t;
 
 /* engines of the CG iteration */
 enum {
-  QX_ENGINE_AUTO = 0,       /* QX_ENGINE_FUSED when every system of the batch has at most
-                               1024 stencil blocks (V/2 <= 65536), else QX_ENGINE_LAUNCH */
+  QX_ENGINE_AUTO = 0,       /* when every system of the batch has at most 1024 stencil blocks
+                               (V/2 <= 65536): QX_ENGINE_FUSED2 if also 4 * sources * blocks
+                               <= 4096 for each system, else QX_ENGINE_FUSED; otherwise
+                               QX_ENGINE_LAUNCH */
   QX_ENGINE_LAUNCH = 1,     /* six kernel launches per iteration, five per reliable update
                                (graph-captured in chunks) */
   QX_ENGINE_PERSISTENT = 2, /* one cooperative launch runs many iterations with grid barriers;
                                slower on MI355X, where every barrier costs each block an
                                agent-scope release (L2 writeback) */
-  QX_ENGINE_FUSED = 3       /* four launches per iteration, three per reliable update: the
+  QX_ENGINE_FUSED = 3,      /* three launches per iteration, three per reliable update: the
                                reductions are finished redundantly by every block of the
-                               next vector pass (cheap while partials per source are few) */
-  /* all engines give the same results bit for bit */
+                               next pass (cheap while partials per source are few) */
+  QX_ENGINE_FUSED2 = 4      /* as QX_ENGINE_FUSED with two launches per iteration: the D_eo
+                               pass also sums Re<r, Ap>, |Ap|^2 and |r|^2, so the next D_oe
+                               pass takes the alpha step, updates x and r and gets the new
+                               |r|^2 as |r|^2 - 2 alpha Re<r, Ap> + alpha^2 |Ap|^2 without a
+                               pass of its own; same mathematics, different rounding */
+  /* LAUNCH, PERSISTENT and FUSED give the same results bit for bit */
 };
 
 /* Solver parameters.  tol: relative residual |b - A x| / |b| to reach, measured

@@ -24,7 +24,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOTUNITARY, ENOTCONVERGED, EBREAKDOWN, ENOLIB = range
 BC_T_ANTIPERIODIC = 1
 PREC_F64, PREC_F32, PREC_F16 = 0, 1, 2
 CG_FP64, CG_MIXED_F32 = 0, 1
-ENGINE_AUTO, ENGINE_LAUNCH, ENGINE_PERSISTENT, ENGINE_FUSED = 0, 1, 2, 3
+ENGINE_AUTO, ENGINE_LAUNCH, ENGINE_PERSISTENT, ENGINE_FUSED, ENGINE_FUSED2 = 0, 1, 2, 3, 4
 
 _PREC = {"f64": PREC_F64, "f32": PREC_F32, "f16": PREC_F16, PREC_F64: PREC_F64,
          PREC_F32: PREC_F32, PREC_F16: PREC_F16}

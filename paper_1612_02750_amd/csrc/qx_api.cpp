@@ -340,6 +340,8 @@ namespace {
 constexpr int kMaxSrcPerSys = 12;
 constexpr double kStopFactor = 0.9;  // stop at an FP64 residual of 0.9 tol
 constexpr int kFuseMaxBlocks = 1024;  // AUTO engine: fused sequence up to V/2 = 65536 per system
+constexpr bool kAutoTwo = true;       // AUTO engine: the two-launch form of the fused sequence
+constexpr int kTwoMaxPartials = 4096;
 
 struct SysSpec {
   const qx_gauge* g64;
@@ -352,13 +354,30 @@ struct SysSpec {
 
 struct Layout {
   size_t sys_off = 0, st_off = 0, gs_off = 0, total = 0;
-  std::vector<size_t> partial_off, partial_v_off, vlo_off, vhi_off;
+  std::vector<size_t> partial_off, partial_x_off, partial_v_off, vlo_off, vhi_off;
 };
 
 int lo_prec(const qx_cg_params_t* p) { return p->mode == QX_CG_FP64 ? QX_PREC_F64 : QX_PREC_F32; }
 
-Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
+// Does the batch run the two-launch fused sequence (its r' slot and extra
+// partials)?  Under AUTO only while every block of its D_oe pass reads at most
+// kTwoMaxPartials partial sums (four per source and stencil block): beyond
+// that the redundant sums cost more than the launch they save (a 16^3 x 32
+// lattice with three sources ran 20 % slower than the three-launch sequence,
+// a 16^4 lattice with one source 10 % faster).
+bool uses_two(const std::vector<SysSpec>& specs, int engine) {
+  if (engine == QX_ENGINE_FUSED2) return true;
+  if (engine != QX_ENGINE_AUTO || !kAutoTwo) return false;
+  for (const auto& s : specs) {
+    const int nblk = (s.g64->geo.hv + kTile - 1) / kTile;
+    if (nblk > kFuseMaxBlocks || 4 * s.nrhs * nblk > kTwoMaxPartials) return false;
+  }
+  return true;
+}
+
+Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo, int engine) {
   Layout L;
+  const bool two = uses_two(specs, engine);
   size_t off = 0;
   L.sys_off = off;
   off = align_up(off + sizeof(SysDesc) * specs.size(), 256);
@@ -374,10 +393,12 @@ Layout plan_layout(const std::vector<SysSpec>& specs, int prec_lo) {
     const int vtiles = (3 * g.hv + kVTile - 1) / kVTile;
     L.partial_off.push_back(off);
     off = align_up(off + sizeof(double) * s.nrhs * nblk, 256);
+    L.partial_x_off.push_back(off);
+    if (two) off = align_up(off + 3 * sizeof(double) * s.nrhs * nblk, 256);
     L.partial_v_off.push_back(off);
     off = align_up(off + sizeof(double) * s.nrhs * vtiles, 256);
     L.vlo_off.push_back(off);
-    off = align_up(off + 6 * field_bytes(g, s.nrhs, prec_lo), 256);
+    off = align_up(off + (two ? 7 : 6) * field_bytes(g, s.nrhs, prec_lo), 256);
     L.vhi_off.push_back(off);
     off = align_up(off + 4 * field_bytes(g, s.nrhs, QX_PREC_F64), 256);
   }
@@ -393,7 +414,7 @@ int check_params(const qx_cg_params_t* p) {
   if (p->mode == QX_CG_MIXED_F32 && !(p->delta > 0.0 && p->delta < 1.0))
     return fail(QX_EINVAL, "solver: delta must be in (0, 1) for the mixed mode");
   if (p->chunk < 0) return fail(QX_EINVAL, "solver: chunk must be >= 0");
-  if (p->engine < QX_ENGINE_AUTO || p->engine > QX_ENGINE_FUSED)
+  if (p->engine < QX_ENGINE_AUTO || p->engine > QX_ENGINE_FUSED2)
     return fail(QX_EINVAL, "solver: unknown engine %d", p->engine);
   return QX_OK;
 }
@@ -462,7 +483,7 @@ namespace {
 int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   const qx_cg_params_t& p = B->params;
   const int prec_lo = lo_prec(&p);
-  B->layout = plan_layout(B->specs, prec_lo);
+  B->layout = plan_layout(B->specs, prec_lo, p.engine);
   if (!ws) return fail(QX_EINVAL, "solver: NULL workspace");
   if (ws_bytes < B->layout.total)
     return fail(QX_ENOMEM, "solver: workspace of %zu bytes, %zu needed", ws_bytes, B->layout.total);
@@ -535,6 +556,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
     d.vlo = B->ws + B->layout.vlo_off[i];
     d.vhi = B->ws + B->layout.vhi_off[i];
     d.partials = (double*)(B->ws + B->layout.partial_off[i]);
+    d.partials_x = (double*)(B->ws + B->layout.partial_x_off[i]);
     d.partials_v = (double*)(B->ws + B->layout.partial_v_off[i]);
     blk += d.nblk;
     vblk += d.nsrc * d.vtiles;
@@ -580,9 +602,10 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   if (!B->persistent) {
     int max_nblk = 0;
     for (const auto& d : B->sys) max_nblk = std::max(max_nblk, d.nblk);
-    B->cfg.fused = p.engine == QX_ENGINE_FUSED ||
+    B->cfg.fused = p.engine == QX_ENGINE_FUSED || p.engine == QX_ENGINE_FUSED2 ||
                    (p.engine == QX_ENGINE_AUTO && max_nblk <= kFuseMaxBlocks);
   }
+  B->cfg.two = B->cfg.fused && uses_two(B->specs, p.engine);
   if (B->persistent) {
     B->chunk = p.chunk > 0 ? p.chunk : 512;
     B->ru_every = B->chunk;
@@ -755,7 +778,7 @@ extern "C" int qx_cg_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params
   std::vector<SysSpec> specs;
   std::vector<double> m(nrhs, 0.0);
   add_specs(specs, &tmp, &tmp, params, nrhs, m.data(), nullptr, nullptr);
-  *bytes = plan_layout(specs, lo_prec(params)).total;
+  *bytes = plan_layout(specs, lo_prec(params), params->engine).total;
   return QX_OK;
 }
 
@@ -791,7 +814,7 @@ extern "C" int qx_batch_workspace_bytes(int nsys, const qx_system_t* systems,
     if (!s.g64 || s.nrhs < 1 || !s.masses) return fail(QX_EINVAL, "batch: bad system %d", i);
     add_specs(specs, s.g64, s.glo ? s.glo : s.g64, params, s.nrhs, s.masses, s.b, s.x);
   }
-  *bytes = plan_layout(specs, lo_prec(params)).total;
+  *bytes = plan_layout(specs, lo_prec(params), params->engine).total;
   return QX_OK;
 }
 
@@ -930,7 +953,7 @@ extern "C" int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_c
   void* xdst = x_out;
   std::vector<SysSpec> probe;
   add_specs(probe, g64, glo, params, nrhs, masses.data(), phi, x_out);
-  const size_t solver_bytes = align_up(plan_layout(probe, lo_prec(params)).total, 256);
+  const size_t solver_bytes = align_up(plan_layout(probe, lo_prec(params), params->engine).total, 256);
   if (ws_bytes < solver_bytes + force_extra_bytes(g, nrhs))
     return fail(QX_ENOMEM, "qx_force: workspace too small");
   char* extra = (char*)ws + solver_bytes;

@@ -150,6 +150,32 @@ __device__ __forceinline__ double canon_sum(const double* __restrict__ a, int n,
   return t;
 }
 
+// canon_sum of N arrays of n values at once (one pass over the arrays, one
+// set of butterflies); out[k] is what canon_sum(a[k], n, .) would return.
+// sh: 4 * N doubles.
+template <int N>
+__device__ __forceinline__ void canon_sum_n(const double* const (&a)[N], int n, double* sh,
+                                            double (&out)[N]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  for (int vw = w; vw < 4; vw += nw) {
+    double v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = 0.0;
+    for (int i = vw * 64 + lane; i < n; i += 256)
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k] += a[k][i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double t = wave_sum(v[k]);
+      if (lane == 0) sh[k * 4 + vw] = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[k] = ((sh[k * 4] + sh[k * 4 + 1]) + sh[k * 4 + 2]) + sh[k * 4 + 3];
+  __syncthreads();
+}
+
 }  // namespace
 
 // =================================================================== init
@@ -719,6 +745,246 @@ __global__ void __launch_bounds__(256) k_fru_finish(const SysDesc* __restrict__ 
   }
 }
 
+// ------------------------------------------ two-launch fused sequence
+//
+// k_f2_doe (states slot 0 -> 1) and k_f2_deo (slot 1 -> 0).  The D_eo pass
+// leaves four partial sums per source: <p, Ap>, Re<r, Ap>, |Ap|^2 and |r|^2
+// of the stored r.  The next D_oe pass adds them in every block, takes the
+// alpha step with that |r|^2, forms
+// |r - alpha Ap|^2 = |r|^2 - 2 alpha Re<r, Ap> + alpha^2 |Ap|^2 and takes the
+// beta step from it (the expansion is taken one step at a time from the
+// stored r's norm, so its cancellation error does not accumulate); each block then updates x, r and p at its own even sites
+// (r and p alternate between two vector slots each, so that the neighbours
+// read the old values while a block writes the new ones) and computes
+// t = 2 D_oe p_new with p_new formed on the fly at the neighbours.  The x/r
+// pass and its reduction of the three-launch sequence disappear; |r|^2 comes
+// from the expansion instead of a sum over the stored r, so the rounding (not
+// the mathematics) differs from the other engines.  Reliable updates are the
+// fused sequence's.
+
+// Stencil input of k_f2_doe: p_new = (r - alpha Ap) + beta p at the
+// neighbours for sources whose step is due (bit j of upd), else p; the same
+// arithmetic as the own-site updates.
+template <typename R, int NBT>
+struct StepIn {
+  const cplx<R>* __restrict__ r;  // first source of the thread
+  const cplx<R>* __restrict__ ap;
+  const cplx<R>* __restrict__ p;
+  size_t ss, hv;
+  unsigned upd;
+  R alpha[NBT], beta[NBT];
+  __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
+    const cplx<R> pv = ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
+    if (!(upd >> j & 1u)) return pv;
+    const cplx<R> rv = ld_cplx<false>(r + j * ss + c * hv, (unsigned)site);
+    const cplx<R> av = ld_cplx<false>(ap + j * ss + c * hv, (unsigned)site);
+    const cplx<R> rn = {fma(-alpha[j], av.re, rv.re), fma(-alpha[j], av.im, rv.im)};
+    return {fma(beta[j], pv.re, rn.re), fma(beta[j], pv.im, rn.im)};
+  }
+};
+
+// |r - alpha Ap|^2 from |r|^2 = rho and the partial sums of Re<r, Ap> and
+// |Ap|^2; a value rounded below zero (a residual that vanished) is zero.
+__device__ __forceinline__ double next_rho(double rho, double alpha, double rap, double apap) {
+  const double t = rho - 2.0 * alpha * rap + alpha * alpha * apap;
+  return t < 0.0 ? 0.0 : t;
+}
+
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>))
+    k_f2_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* __restrict__ st_in,
+             SrcState* __restrict__ st_out, int pin, int pout, int rin, int rout, int xcd) {
+  __shared__ double sh[16];
+  __shared__ double al_sh[64], be_sh[64], pap_sh[64], t_sh[64], rho_sh[64];
+  __shared__ int code_sh[64];
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  const SrcState* q0 = st_in + d.src0;
+  // decisions, the same in every block: run (stencil), step (x and r
+  // updated), upd (p = r_new + beta p), keep (p and r copied)
+  unsigned long long run = 0, step = 0, upd = 0, keep = 0;
+  for (int k = 0; k < d.nsrc; ++k) {
+    const SrcState& q = q0[k];
+    const unsigned long long bit = 1ull << k;
+    double al = 0.0, be = 0.0, pap = 0.0, t = 0.0, rho = q.rho;
+    int code = 0;  // 1: the alpha step failed (breakdown), 2: alpha and beta steps taken
+    if (q.phase == PH_RUN && q.have_rr) {
+      const double* const parts[4] = {d.partials + (size_t)k * d.nblk,
+                                      d.partials_x + (size_t)k * d.nblk,
+                                      d.partials_x + (size_t)(d.nsrc + k) * d.nblk,
+                                      d.partials_x + (size_t)(2 * d.nsrc + k) * d.nblk};
+      double sums[4];
+      canon_sum_n<4>(parts, d.nblk, sh, sums);
+      pap = sums[0];
+      const double rap = sums[1], apap = sums[2];
+      rho = sums[3];
+      const AlphaStep as = alpha_step(rho, pap);
+      if (as.ok) {
+        al = as.alpha;
+        t = next_rho(rho, al, rap, apap);
+        const BetaStep bs = beta_step(t, q.iters + 1, q.max_iter, q.rmax, q.stop2, q.delta, rho);
+        code = 2;
+        step |= bit;
+        if (bs.outcome == BETA_GO) {
+          run |= bit;
+          upd |= bit;
+          be = bs.beta;
+        } else {
+          keep |= bit;
+        }
+      } else {
+        code = 1;
+        keep |= bit;
+      }
+    } else if (q.phase == PH_RUN) {
+      run |= bit;
+      keep |= bit;
+    } else if (q.phase == PH_RU) {
+      keep |= bit;
+    }
+    if (threadIdx.x == 0) {
+      al_sh[k] = al;
+      be_sh[k] = be;
+      pap_sh[k] = pap;
+      t_sh[k] = t;
+      rho_sh[k] = rho;
+      code_sh[k] = code;
+    }
+  }
+  __syncthreads();
+  if (b == d.blk0)
+    for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x) {
+      SrcState q = q0[k];
+      if (code_sh[k] >= 1) q.rho = rho_sh[k];  // |r|^2 of the stored r
+      if (code_sh[k] >= 1) finalize_source<false>(FIN_ALPHA, q, pap_sh[k]);
+      if (code_sh[k] == 2) finalize_source<false>(FIN_BETA, q, t_sh[k]);
+      q.pend = 0;
+      q.have_rr = (run >> k & 1ull) ? 1 : 0;  // the D_eo pass leaves its partial sums
+      st_out[d.src0 + k] = q;
+    }
+  if (!(run | step | keep)) return;
+  const int cb = tile_block(b - d.blk0, d.g, xcd) * kTile + lane;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  const int k0 = grp * NBT;
+  const bool in_range = cb < d.g.hv;
+  const cplx<R>* r_in = slot<R>(d.vlo, rin, vs);
+  const cplx<R>* ap = slot<R>(d.vlo, 3, vs);
+  const cplx<R>* p_in = slot<R>(d.vlo, pin, vs);
+  StepIn<R, NBT> src{r_in + k0 * ss, ap + k0 * ss, p_in + k0 * ss, ss, hv, group_bits<NBT>(upd, k0),
+                     {}, {}};
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) {
+    src.alpha[j] = k0 + j < d.nsrc ? (R)al_sh[k0 + j] : (R)0;
+    src.beta[j] = k0 + j < d.nsrc ? (R)be_sh[k0 + j] : (R)0;
+  }
+  // x, r and p at the block's own even sites
+  if (dp == 0 && in_range) {
+    cplx<R>* x = slot<R>(d.vlo, 0, vs);
+    cplx<R>* r_out = slot<R>(d.vlo, rout, vs);
+    cplx<R>* p_out = slot<R>(d.vlo, pout, vs);
+    const unsigned gs = group_bits<NBT>(step, k0), gu = group_bits<NBT>(upd, k0);
+    const unsigned gk = group_bits<NBT>(keep, k0);
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (!((gs | gk) >> j & 1u)) continue;
+      const R al = src.alpha[j], be = src.beta[j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const size_t i = (k0 + j) * ss + c * hv + cb;
+        const cplx<R> pv = p_in[i];
+        cplx<R> rv = r_in[i];
+        if (gs >> j & 1u) {
+          const cplx<R> av = ap[i];
+          cplx<R> xv = x[i];
+          xv.re = fma(al, pv.re, xv.re);
+          xv.im = fma(al, pv.im, xv.im);
+          x[i] = xv;
+          rv = {fma(-al, av.re, rv.re), fma(-al, av.im, rv.im)};
+        }
+        r_out[i] = rv;
+        p_out[i] = (gu >> j & 1u) ? cplx<R>{fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)} : pv;
+      }
+    }
+  }
+  if (!run) return;
+  const unsigned act = in_range ? group_bits<NBT>(run, k0) : 0u;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(d.g, 1, cb, s);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp, src, act, acc);
+  }
+  cplx<R>* t = slot<R>(d.vlo, 4, vs);
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+    if (act >> j & 1u) t[(k0 + j) * ss + c * hv + cb] = v;
+  });
+}
+
+// Ap = m^2 p - 1/4 (2D_eo) t and the partials of <p, Ap>, Re<r, Ap>, |Ap|^2
+// and |r|^2 for running sources; the system's first block copies the states
+// from slot 1 (st_in) to slot 0.
+template <typename R, int RECON, int NBT, int LPS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>))
+    k_f2_deo(const SysDesc* __restrict__ sys, int nsys, const SrcState* __restrict__ st_in,
+             SrcState* __restrict__ st_out, int pslot, int rslot, int xcd) {
+  __shared__ double sh[16 * 64];
+  __shared__ double tot[4][64];
+  cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
+  const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_block(sys, nsys, b);
+  const SrcState* q0 = st_in + d.src0;
+  if (b == d.blk0)
+    for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x) st_out[d.src0 + k] = q0[k];
+  const unsigned long long run = phase_bits<false>(q0, d.nsrc, PH_RUN);
+  if (!run) return;
+  const int bl = tile_block(b - d.blk0, d.g, xcd), cb = bl * kTile + lane;
+  const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
+  const int k0 = grp * NBT;
+  const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
+  cplx<R> acc[NBT][3];
+  zero_acc<R, NBT>(acc);
+  if (act) {
+    Site s;
+    site_geometry(d.g, 0, cb, s);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 0, cb, s, dp,
+                                     FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
+  }
+  double dpa[NBT], dra[NBT], daa[NBT], drr[NBT];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j) dpa[j] = dra[j] = daa[j] = drr[j] = 0.0;
+  const cplx<R>* p = slot<R>(d.vlo, pslot, vs);
+  const cplx<R>* r = slot<R>(d.vlo, rslot, vs);
+  cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+    if (!(act >> j & 1u)) return;
+    const R m2 = (R)q0[k0 + j].m2;
+    const size_t i = (k0 + j) * ss + c * hv + cb;
+    const cplx<R> pv = p[i], rv = r[i];
+    const cplx<R> a = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
+    Ap[i] = a;
+    dpa[j] += (double)pv.re * (double)a.re + (double)pv.im * (double)a.im;
+    dra[j] += (double)rv.re * (double)a.re + (double)rv.im * (double)a.im;
+    daa[j] += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
+    drr[j] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+  });
+  const int G = (int)(blockDim.x >> 6) / LPS;
+  group_sum<NBT>(dpa, LPS, grp, dp, G, sh, tot[0]);
+  group_sum<NBT>(dra, LPS, grp, dp, G, sh, tot[1]);
+  group_sum<NBT>(daa, LPS, grp, dp, G, sh, tot[2]);
+  group_sum<NBT>(drr, LPS, grp, dp, G, sh, tot[3]);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < d.nsrc; ++k) {
+      d.partials[(size_t)k * d.nblk + bl] = tot[0][k];
+      d.partials_x[(size_t)k * d.nblk + bl] = tot[1][k];
+      d.partials_x[(size_t)(d.nsrc + k) * d.nblk + bl] = tot[2][k];
+      d.partials_x[(size_t)(2 * d.nsrc + k) * d.nblk + bl] = tot[3][k];
+    }
+}
+
 // ------------------------------------------------------- persistent kernel
 //
 // One cooperative launch runs up to `iters` iterations of every system: each
@@ -895,8 +1161,11 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
   }
   const int G = (int)(blockDim.x >> 6);
   group_sum<NBT>(rr, 1, grp, 0, G, sh, tot);
+  // only the updating sources' entries: the two-launch sequence keeps the
+  // <p, Ap> partials of the running ones across the update
   if (threadIdx.x == 0)
-    for (int k = 0; k < d.nsrc; ++k) d.partials[(size_t)k * d.nblk + bl] = tot[k];
+    for (int k = 0; k < d.nsrc; ++k)
+      if (ru >> k & 1ull) d.partials[(size_t)k * d.nblk + bl] = tot[k];
 }
 
 // R3: r = lo(r_hi), p = r + beta p for sources whose update did not converge.
@@ -944,6 +1213,18 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   const dim3 sgrid(c.nblk_total), sblock(64 * c.shape.lps * G);
   const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
+  if (c.fused && c.two) {
+    // p alternates between slots 2 and 5, r between 1 and 6
+    const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
+    const int rin = parity ? 6 : 1, rout = parity ? 1 : 6;
+    return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+      hipLaunchKernelGGL((k_f2_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+                         c.d_st, c.d_st1, pin, pout, rin, rout, c.shape.xcd);
+      hipLaunchKernelGGL((k_f2_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+                         c.d_st1, c.d_st, pout, rout, c.shape.xcd);
+      return hipGetLastError();
+    });
+  }
   if (c.fused) {
     // p alternates between slots 2 and 5; the states between the two slots
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;

@@ -75,10 +75,11 @@ struct SysDesc {
   int vblk0, vtiles;
   const void* links_lo;
   const void* links_hi;
-  void* vlo;        // inner precision: x_lo, r, p, Ap (even), t (odd); each [nsrc][3][hv]
+  void* vlo;        // inner precision: x_lo, r, p, Ap (even), t (odd), p', r'; each [nsrc][3][hv]
   void* vhi;        // FP64: x_hi, r_hi, b (even), t_hi (odd); each [nsrc][3][hv]
   double* partials;    // per-block partial sums of the stencil passes: [nsrc][nblk]
   double* partials_v;  // per-tile partial sums of the vector passes: [nsrc][vtiles]
+  double* partials_x;  // two-launch sequence: Re<r, Ap>, |Ap|^2, |r|^2 partials, [3][nsrc][nblk]
 };
 
 // Grid barrier of the persistent solver kernel (zeroed before first use).

@@ -78,7 +78,8 @@ struct EngineCfg {
   const SysDesc* d_sys = nullptr;
   SrcState* d_st = nullptr;   // the source states (slot 0)
   SrcState* d_st1 = nullptr;  // second slot of the fused launch sequence
-  bool fused = false;         // four launches per iteration (redundant reductions), see the engine
+  bool fused = false;         // three launches per iteration (redundant reductions), see the engine
+  bool two = false;           // with fused: two launches per iteration (x/r step folded into D_oe)
 };
 
 bool engine_supported(const EngineCfg& c);

@@ -29,7 +29,7 @@ def _systems(qx, torch):
     return systems, keep
 
 
-@pytest.mark.parametrize("engine", ["FUSED", "LAUNCH", "PERSISTENT"])
+@pytest.mark.parametrize("engine", ["FUSED", "LAUNCH", "PERSISTENT", "FUSED2"])
 def test_batch_solve_async_matches_sync(qx, engine):
     import torch
 

@@ -542,7 +542,8 @@ def test_engines_agree_bitwise(qx, mixed, dims):
     """The launch-per-pass engine, the fused launch sequence (reductions
     finished redundantly in every block, two state slots) and the persistent
     kernel (grid barriers) run the same reductions in the same order and
-    update at the same iterations.  The second lattice has 1152 stencil blocks
+    update at the same iterations; AUTO is one of them or the two-launch
+    sequence, bit for bit.  The second lattice has 1152 stencil blocks
     and 864 vector tiles per source, so the block-size-independent sums span
     several rounds of their 256 lanes, and AUTO picks the launch-per-pass
     engine there (more than 1024 blocks)."""
@@ -555,16 +556,23 @@ def test_engines_agree_bitwise(qx, mixed, dims):
     masses = [0.05, 0.2, 0.1]
     b = synth.gauss_source(3, lat.hv, 11)
     runs = [qx.cg(g64, to_dev(b), masses, glo=glo, engine=e)
-            for e in (qx.ENGINE_LAUNCH, qx.ENGINE_FUSED, qx.ENGINE_PERSISTENT, qx.ENGINE_AUTO)]
+            for e in (qx.ENGINE_LAUNCH, qx.ENGINE_FUSED, qx.ENGINE_PERSISTENT)]
     xa, sa = runs[0]
     for xb, sb in runs[1:]:
         assert np.array_equal(to_host(xa), to_host(xb))
         assert [s.iters for s in sa] == [s.iters for s in sb]
         assert [s.reliable_updates for s in sa] == [s.reliable_updates for s in sb]
     _check_solution(dims, U, masses, b, to_host(xa), sa, flags=oracle.BC_T_ANTIPERIODIC)
+    # AUTO: the two-launch sequence while 4 * sources * blocks <= 4096, the
+    # three-launch one up to 1024 blocks, else launch-per-pass
+    xauto, _ = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_AUTO)
+    nblk = (lat.hv + 63) // 64
+    if nblk <= 1024 and 4 * 3 * nblk <= 4096:
+        xa = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED2)[0]
+    assert np.array_equal(to_host(xauto), to_host(xa))
 
 
-@pytest.mark.parametrize("engine", ["PERSISTENT", "FUSED", "LAUNCH"])
+@pytest.mark.parametrize("engine", ["PERSISTENT", "FUSED", "LAUNCH", "FUSED2"])
 def test_engine_edge_cases(qx, engine):
     """Zero source, max_iter, a non-finite source (breakdown), m = 0 on the free
     field (singular A), and a plain solve, under each engine."""
@@ -611,7 +619,7 @@ def test_engines_uneven_batch(qx):
         xd = torch.empty_like(bd)
         systems.append((g64, g32, bd, masses, xd))
         keep.append((dims, U, b, masses, xd))
-    for engine in (qx.ENGINE_PERSISTENT, qx.ENGINE_LAUNCH, qx.ENGINE_FUSED):
+    for engine in (qx.ENGINE_PERSISTENT, qx.ENGINE_LAUNCH, qx.ENGINE_FUSED, qx.ENGINE_FUSED2):
         stats = qx.Batch(systems, tol=1e-10, engine=engine).solve()
         j = 0
         for dims, U, b, masses, xd in keep:
@@ -620,6 +628,52 @@ def test_engines_uneven_batch(qx):
                 rr = oracle.true_residual(dims, U, masses[s], b[s], x[s])
                 assert rr <= 1e-10 and stats[j].status == 0, (engine, dims, s, rr)
                 j += 1
+
+
+@pytest.mark.parametrize("dims", [(8, 4, 6, 8), (16, 16, 16, 16)])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fused2_solves(qx, mixed, dims):
+    """The two-launch sequence (|r|^2 from Re<r, Ap> and |Ap|^2): solutions to
+    1e-10 measured by the oracle, iteration counts next to the three-launch
+    sequence's, bitwise reproducible, and independent of the block order
+    (partial sums stored at checkerboard-block positions)."""
+    dims = tuple(dims)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    U = gauge(dims, seed=9)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    glo = qx.Gauge(lat, Ud, "f32", 12) if mixed else None
+    masses = [0.05, 0.2, 0.1]
+    b = synth.gauss_source(3, lat.hv, 11)
+    x2, s2 = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED2)
+    _check_solution(dims, U, masses, b, to_host(x2), s2, flags=oracle.BC_T_ANTIPERIODIC)
+    x1, s1 = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED)
+    for a, c in zip(s2, s1):
+        assert abs(a.iters - c.iters) <= max(3, c.iters // 20), (a.iters, c.iters)
+    x2b, _ = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED2)
+    assert np.array_equal(to_host(x2), to_host(x2b))
+    if glo is not None:
+        glo.set_launch(3, 1, 4, 2)
+        x2c, _ = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED2)
+        glo.set_launch(3, 1, 4, 1)
+        x2d, _ = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED2)
+        assert np.array_equal(to_host(x2c), to_host(x2d))
+
+
+def test_fused2_naik(qx):
+    """The two-launch sequence on the improved operator, mixed and FP64."""
+    dims = (8, 4, 6, 8)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    flags = oracle.NAIK | oracle.BC_T_ANTIPERIODIC
+    U = gauge(dims, seed=35)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64", qx.RECON_NAIK)
+    g32 = qx.Gauge(lat, Ud, "f32", qx.RECON_NAIK)
+    masses = [0.05, 0.2, 0.1]
+    b = synth.gauss_source(3, lat.hv, 36)
+    for glo in (None, g32):
+        x, st = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_FUSED2)
+        _check_solution(dims, U, masses, b, to_host(x), st, flags=flags)
 
 
 # ------------------------------------------------------------ Naik term (f1)
