@@ -91,7 +91,7 @@ BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colou
 # From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
 # launch shape "nbt,lps,order".
 TRAFFIC = {
-    "sha": "7e0258174f87e9fb",
+    "sha": "84c183eb9b569d7b",
     "bytes": {
         "1,1,0": 16251904,
         "1,1,1": 15072256,
@@ -108,7 +108,7 @@ TRAFFIC = {
         "1,8,0": 16287744,
         "1,8,1": 15108096,
         "1,8,2": 14911488,
-        "1,8,3": 14911552
+        "1,8,3": 14911488
     },
 }
 KERNEL_SOURCES = ("qx_dslash.hip", "qx_device.h", "qx_internal.h", "qx_launch.h", "qx_dispatch.h")
@@ -381,6 +381,24 @@ def multi_rhs(torch, qx, synth):
     return out
 
 
+def cg_kernels_sample(torch, qx, synth):
+    """A few CG iterations for counter runs: the step's 16^4 mixed solve (the
+    AUTO engine) cut at 32 iterations, and the 32^4 twelve-source mixed solve
+    (launch-per-pass engine) cut at 6."""
+    for dims, seed_kind, nsrc, m, iters in (((16, 16, 16, 16), "weak", 1, 0.05, 32),
+                                            ((32, 32, 32, 32), "haar", 12, 0.02, 6)):
+        lat = qx.Lattice(dims)
+        U = synth.weak_gauge(dims, 0.3, 0) if seed_kind == "weak" else synth.haar_gauge(dims, 0)
+        Ud = torch.from_numpy(U).cuda()
+        g64 = qx.Gauge(lat, Ud, "f64", 18)
+        g32 = qx.Gauge(lat, Ud, "f32", 12)
+        del Ud
+        bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
+        qx.cg(g64, bd, [m] * nsrc, glo=g32, tol=1e-10, max_iter=iters, raise_on_fail=False)
+        torch.cuda.synchronize()
+        del g64, g32, bd
+
+
 def uneven_batch(torch, qx, synth):
     """Lattices 8^4, 12^4, 16^4, 16^3 x 32 and 24^4 with weak-field links
     (eps in [0.2, 0.5] by seed), four Gaussian sources each, masses from
@@ -500,6 +518,7 @@ def main():
                 order.append([1, lps, xo])
         dslash_sweep(torch, qx, tune=False, plain=True)
         copy_probe(torch, qx, timed=False)
+        cg_kernels_sample(torch, qx, synth)
         print(json.dumps({"kernels_only": True, "dominant_shapes_in_order": order}))
         return
     shape32 = g32.tune(1)
