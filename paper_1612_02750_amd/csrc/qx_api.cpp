@@ -636,12 +636,12 @@ int enqueue_chunk(qx_batch* B, hipStream_t s) {
   if (B->persistent) {
     QX_HIP(engine_persistent(B->cfg, B->chunk, (GridSync*)(B->ws + B->layout.gs_off), B->pgrid, s),
            "solver: persistent iterations");
-    QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
+    QX_HIP(engine_reliable_update(B->cfg, true, s), "solver: reliable update");
   } else {
     for (int i = 0; i < B->chunk; ++i) {
       QX_HIP(engine_iteration(B->cfg, i & 1, s), "solver: iteration");
       if ((i + 1) % B->ru_every == 0 || i + 1 == B->chunk)
-        QX_HIP(engine_reliable_update(B->cfg, s), "solver: reliable update");
+        QX_HIP(engine_reliable_update(B->cfg, i + 1 == B->chunk, s), "solver: reliable update");
     }
   }
   const size_t n = B->persistent ? B->layout.gs_off - B->layout.st_off + sizeof(GridSync)
@@ -695,7 +695,7 @@ int enqueue_start(qx_batch* B, hipStream_t s) {
   if (B->persistent)
     QX_HIP(hipMemsetAsync(B->ws + B->layout.gs_off, 0, sizeof(GridSync), s), "solver: barrier reset");
   QX_HIP(engine_init(B->cfg, p.use_x0 ? 0 : 1, s), "solver: init");
-  QX_HIP(engine_reliable_update(B->cfg, s), "solver: initial residual");
+  QX_HIP(engine_reliable_update(B->cfg, true, s), "solver: initial residual");
   if (B->use_graph && B->graph && B->graph_stream != s) {
     int rc = capture_graph(B, s);
     if (rc != QX_OK) return rc;

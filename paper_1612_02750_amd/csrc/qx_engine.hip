@@ -30,9 +30,9 @@ hipError_t engine_iteration(const EngineCfg& c, int parity, hipStream_t s) {
   });
 }
 
-hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s) {
+hipError_t engine_reliable_update(const EngineCfg& c, bool last, hipStream_t s) {
   return with_prec_recon(c.prec_lo, c.recon_hi, [&]<typename R, int RECON>() {
-    return reliable_update_impl<R, RECON>(c, s);
+    return reliable_update_impl<R, RECON>(c, last, s);
   });
 }
 

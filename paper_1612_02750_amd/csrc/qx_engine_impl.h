@@ -15,7 +15,7 @@ hipError_t init_impl(const EngineCfg& c, int zero_xhi, hipStream_t s);
 template <typename R, int RECON>
 hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s);
 template <typename Rlo, int RECON>
-hipError_t reliable_update_impl(const EngineCfg& c, hipStream_t s);
+hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s);
 template <typename R, int RECON>
 int persistent_per_cu_impl(const EngineCfg& c);
 template <typename R, int RECON>

@@ -11,7 +11,7 @@
 namespace qx {
 
 template hipError_t iteration_impl<QX_R, QX_RECON>(const EngineCfg&, int, hipStream_t);
-template hipError_t reliable_update_impl<QX_R, QX_RECON>(const EngineCfg&, hipStream_t);
+template hipError_t reliable_update_impl<QX_R, QX_RECON>(const EngineCfg&, bool, hipStream_t);
 template int persistent_per_cu_impl<QX_R, QX_RECON>(const EngineCfg&);
 template hipError_t persistent_impl<QX_R, QX_RECON>(const EngineCfg&, int, GridSync*, int,
                                                      long long, hipStream_t);

@@ -763,7 +763,8 @@ __global__ void __launch_bounds__(256) k_fru_finish(const SysDesc* __restrict__ 
 // fused sequence's.
 
 // Stencil input of k_f2_doe: p_new = (r - alpha Ap) + beta p at the
-// neighbours for sources whose step is due (bit j of upd), else p; the same
+// neighbours for sources whose step is due (bits j of sub and upd), r + beta p
+// for sources restarting after a reliable update (upd only), else p; the same
 // arithmetic as the own-site updates.
 template <typename R, int NBT>
 struct StepIn {
@@ -771,14 +772,16 @@ struct StepIn {
   const cplx<R>* __restrict__ ap;
   const cplx<R>* __restrict__ p;
   size_t ss, hv;
-  unsigned upd;
+  unsigned upd, sub;
   R alpha[NBT], beta[NBT];
   __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
     const cplx<R> pv = ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
     if (!(upd >> j & 1u)) return pv;
-    const cplx<R> rv = ld_cplx<false>(r + j * ss + c * hv, (unsigned)site);
-    const cplx<R> av = ld_cplx<false>(ap + j * ss + c * hv, (unsigned)site);
-    const cplx<R> rn = {fma(-alpha[j], av.re, rv.re), fma(-alpha[j], av.im, rv.im)};
+    cplx<R> rn = ld_cplx<false>(r + j * ss + c * hv, (unsigned)site);
+    if (sub >> j & 1u) {
+      const cplx<R> av = ld_cplx<false>(ap + j * ss + c * hv, (unsigned)site);
+      rn = {fma(-alpha[j], av.re, rn.re), fma(-alpha[j], av.im, rn.im)};
+    }
     return {fma(beta[j], pv.re, rn.re), fma(beta[j], pv.im, rn.im)};
   }
 };
@@ -803,14 +806,27 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st_in + d.src0;
   // decisions, the same in every block: run (stencil), step (x and r
-  // updated), upd (p = r_new + beta p), keep (p and r copied)
+  // updated), upd (p = r_new + beta p), keep (p and r copied); a source whose
+  // reliable update left its FP64 |r|^2 partials (PH_RU with have_rr) takes
+  // the update's last step here (converged, stopped, or restart with
+  // p = lo(r_hi) + beta p, lo(r_hi) already in the r slot)
   unsigned long long run = 0, step = 0, upd = 0, keep = 0;
   for (int k = 0; k < d.nsrc; ++k) {
     const SrcState& q = q0[k];
     const unsigned long long bit = 1ull << k;
     double al = 0.0, be = 0.0, pap = 0.0, t = 0.0, rho = q.rho;
-    int code = 0;  // 1: the alpha step failed (breakdown), 2: alpha and beta steps taken
-    if (q.phase == PH_RUN && q.have_rr) {
+    int code = 0;  // 1: the alpha step failed (breakdown), 2: alpha and beta steps taken,
+                   // 3: a reliable update finished here
+    if (q.phase == PH_RU && q.have_rr) {
+      t = canon_sum(d.partials + (size_t)k * d.nblk, d.nblk, sh);
+      const RuStep rs = ru_step(t, q.stop2, q.reason, q.rho);
+      code = 3;
+      if (rs.outcome == RU_GO) {
+        run |= bit;
+        upd |= bit;
+        be = rs.beta;
+      }
+    } else if (q.phase == PH_RUN && q.have_rr) {
       const double* const parts[4] = {d.partials + (size_t)k * d.nblk,
                                       d.partials_x + (size_t)k * d.nblk,
                                       d.partials_x + (size_t)(d.nsrc + k) * d.nblk,
@@ -857,8 +873,12 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (b == d.blk0)
     for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x) {
       SrcState q = q0[k];
-      if (code_sh[k] >= 1) q.rho = rho_sh[k];  // |r|^2 of the stored r
-      if (code_sh[k] >= 1) finalize_source<false>(FIN_ALPHA, q, pap_sh[k]);
+      if (code_sh[k] == 3) {
+        finalize_source<false>(FIN_RU, q, t_sh[k]);
+        if (q.phase == PH_RU2) finalize_source<false>(FIN_COMMIT, q, 0.0);
+      }
+      if (code_sh[k] == 1 || code_sh[k] == 2) q.rho = rho_sh[k];  // |r|^2 of the stored r
+      if (code_sh[k] == 1 || code_sh[k] == 2) finalize_source<false>(FIN_ALPHA, q, pap_sh[k]);
       if (code_sh[k] == 2) finalize_source<false>(FIN_BETA, q, t_sh[k]);
       q.pend = 0;
       q.have_rr = (run >> k & 1ull) ? 1 : 0;  // the D_eo pass leaves its partial sums
@@ -873,7 +893,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   const cplx<R>* ap = slot<R>(d.vlo, 3, vs);
   const cplx<R>* p_in = slot<R>(d.vlo, pin, vs);
   StepIn<R, NBT> src{r_in + k0 * ss, ap + k0 * ss, p_in + k0 * ss, ss, hv, group_bits<NBT>(upd, k0),
-                     {}, {}};
+                     group_bits<NBT>(step, k0), {}, {}};
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     src.alpha[j] = k0 + j < d.nsrc ? (R)al_sh[k0 + j] : (R)0;
@@ -888,7 +908,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     const unsigned gk = group_bits<NBT>(keep, k0);
 #pragma unroll
     for (int j = 0; j < NBT; ++j) {
-      if (!((gs | gk) >> j & 1u)) continue;
+      if (!((gs | gk | gu) >> j & 1u)) continue;
       const R al = src.alpha[j], be = src.beta[j];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1105,10 +1125,13 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
 // partials of |r_hi|^2, all in FP64.
 // st_copy (fused sequence, else null): the system's first block copies its
 // source states there.
+// mark (the two-launch sequence between chunk ends): also store lo(r_hi) in
+// the r slot and flag the updating sources (have_rr) for k_f2_doe, which takes
+// the update's last step.
 template <typename Rlo, int RECON, int NBT>
 __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
-    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd,
-                  SrcState* st_copy) {
+    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int xcd,
+                  SrcState* st_copy, int mark) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
   const int lane = threadIdx.x & 63, grp = wave_id();
@@ -1119,6 +1142,9 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
     for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x) st_copy[d.src0 + k] = q0[k];
   const unsigned long long ru = phase_bits<false>(q0, d.nsrc, PH_RU);
   if (!ru) return;
+  if (mark && b == d.blk0)
+    for (int k = threadIdx.x; k < d.nsrc; k += blockDim.x)
+      if (ru >> k & 1ull) st[d.src0 + k].have_rr = 1;
   const int bl = tile_block(b - d.blk0, d.g, xcd), cb = bl * kTile + lane;
   const size_t hv = d.g.hv, ss = 3 * hv, vs = ss * d.nsrc;
   const int k0 = grp * NBT;
@@ -1155,6 +1181,7 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
         const cplx<double> r = {bv.re - (m2 * xv.re - 0.25 * acc[j][c].re),
                                 bv.im - (m2 * xv.im - 0.25 * acc[j][c].im)};
         rhi[i] = r;
+        if (mark) slot<Rlo>(d.vlo, 1, vs)[i] = {(Rlo)r.re, (Rlo)r.im};
         rr[j] += r.re * r.re + r.im * r.im;
       }
     }
@@ -1257,18 +1284,22 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
 
 // RECON: the storage of the FP64 links (the update works on them).
 template <typename Rlo, int RECON>
-hipError_t reliable_update_impl(const EngineCfg& c, hipStream_t s) {
+hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * G);
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
-  SrcState* copy = c.fused ? c.d_st1 : nullptr;
+  // the two-launch sequence leaves an update's last step to its next D_oe
+  // pass, except at the end of a chunk (the host reads the states there)
+  const bool handoff = c.fused && c.two && !last;
+  SrcState* copy = c.fused && !handoff ? c.d_st1 : nullptr;
   hipError_t e = with_nbt(c.shape.nbt, [&]<int NBT>() {
     hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
                        c.shape.xcd);
     hipLaunchKernelGGL((k_ru_residual<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
-                       c.d_st, c.shape.xcd, copy);
+                       c.d_st, c.shape.xcd, copy, handoff ? 1 : 0);
     return hipGetLastError();
   });
+  if (handoff) return e;
   if (c.fused) {
     if (e == hipSuccess) {
       hipLaunchKernelGGL(k_fru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,

@@ -87,7 +87,10 @@ hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s);
 // parity: of the iteration's index in its chunk (the fused sequence alternates
 // two p slots; its chunks hold an even number of iterations).
 hipError_t engine_iteration(const EngineCfg& c, int parity, hipStream_t s);
-hipError_t engine_reliable_update(const EngineCfg& c, hipStream_t s);
+// last: the update ends a chunk (every step done before the host reads the
+// states); otherwise the two-launch sequence leaves its last step to the next
+// D_oe pass.
+hipError_t engine_reliable_update(const EngineCfg& c, bool last, hipStream_t s);
 // Co-resident blocks of the persistent solver kernel on this device (0 if it
 // cannot be launched), and one cooperative launch of up to `iters` iterations.
 int engine_persistent_capacity(const EngineCfg& c);
