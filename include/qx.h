@@ -106,9 +106,9 @@ typedef struct qx_batch qx_batch_t;
 /* engines of the CG iteration */
 enum {
   QX_ENGINE_AUTO = 0,       /* when every system of the batch has at most 1024 stencil blocks
-                               (V/2 <= 65536): QX_ENGINE_FUSED2 if also 4 * sources * blocks
-                               <= 4096 for each system, else QX_ENGINE_FUSED; otherwise
-                               QX_ENGINE_LAUNCH */
+                               (V/2 <= 65536): QX_ENGINE_FUSED2 if also every system has at
+                               most 3 sources and 4 * sources * blocks <= 4096, else
+                               QX_ENGINE_FUSED; otherwise QX_ENGINE_LAUNCH */
   QX_ENGINE_LAUNCH = 1,     /* six kernel launches per iteration, five per reliable update
                                (graph-captured in chunks) */
   QX_ENGINE_PERSISTENT = 2, /* one cooperative launch runs many iterations with grid barriers;

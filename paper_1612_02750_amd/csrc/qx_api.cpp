@@ -342,6 +342,7 @@ constexpr double kStopFactor = 0.9;  // stop at an FP64 residual of 0.9 tol
 constexpr int kFuseMaxBlocks = 1024;  // AUTO engine: fused sequence up to V/2 = 65536 per system
 constexpr bool kAutoTwo = true;       // AUTO engine: the two-launch form of the fused sequence
 constexpr int kTwoMaxPartials = 4096;
+constexpr int kTwoMaxSources = 3;
 
 struct SysSpec {
   const qx_gauge* g64;
@@ -360,17 +361,21 @@ struct Layout {
 int lo_prec(const qx_cg_params_t* p) { return p->mode == QX_CG_FP64 ? QX_PREC_F64 : QX_PREC_F32; }
 
 // Does the batch run the two-launch fused sequence (its r' slot and extra
-// partials)?  Under AUTO only while every block of its D_oe pass reads at most
-// kTwoMaxPartials partial sums (four per source and stencil block): beyond
-// that the redundant sums cost more than the launch they save (a 16^3 x 32
-// lattice with three sources ran 20 % slower than the three-launch sequence,
-// a 16^4 lattice with one source 10 % faster).
+// partials)?  Under AUTO only for systems of at most kTwoMaxSources sources
+// whose D_oe blocks each read at most kTwoMaxPartials partial sums (four per
+// source and stencil block): its D_oe pass loads r, Ap and p at every
+// neighbour and adds each source's sums in turn, which outweighs the launch it
+// saves beyond that (mixed solves against the three-launch sequence: 16^4
+// with 1 / 2 / 3 / 4 / 12 sources 0.85 / 0.96 / 0.99 / 1.09 / 1.19 of its
+// time, 16^3 x 32 with 1 / 3 sources 0.96 / 1.03, 12^4 with 3 / 4 sources
+// 0.98 / 1.02).
 bool uses_two(const std::vector<SysSpec>& specs, int engine) {
   if (engine == QX_ENGINE_FUSED2) return true;
   if (engine != QX_ENGINE_AUTO || !kAutoTwo) return false;
   for (const auto& s : specs) {
     const int nblk = (s.g64->geo.hv + kTile - 1) / kTile;
-    if (nblk > kFuseMaxBlocks || 4 * s.nrhs * nblk > kTwoMaxPartials) return false;
+    if (nblk > kFuseMaxBlocks || s.nrhs > kTwoMaxSources || 4 * s.nrhs * nblk > kTwoMaxPartials)
+      return false;
   }
   return true;
 }

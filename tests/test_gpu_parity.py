@@ -563,8 +563,9 @@ def test_engines_agree_bitwise(qx, mixed, dims):
         assert [s.iters for s in sa] == [s.iters for s in sb]
         assert [s.reliable_updates for s in sa] == [s.reliable_updates for s in sb]
     _check_solution(dims, U, masses, b, to_host(xa), sa, flags=oracle.BC_T_ANTIPERIODIC)
-    # AUTO: the two-launch sequence while 4 * sources * blocks <= 4096, the
-    # three-launch one up to 1024 blocks, else launch-per-pass
+    # AUTO: the two-launch sequence for at most 3 sources while
+    # 4 * sources * blocks <= 4096, the three-launch one up to 1024 blocks,
+    # else launch-per-pass
     xauto, _ = qx.cg(g64, to_dev(b), masses, glo=glo, engine=qx.ENGINE_AUTO)
     nblk = (lat.hv + 63) // 64
     if nblk <= 1024 and 4 * 3 * nblk <= 4096:
