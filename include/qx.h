@@ -121,7 +121,9 @@ enum {
                                pass also sums Re<r, Ap>, |Ap|^2 and |r|^2, so the next D_oe
                                pass takes the alpha step, updates x and r and gets the new
                                |r|^2 as |r|^2 - 2 alpha Re<r, Ap> + alpha^2 |Ap|^2 without a
-                               pass of its own; same mathematics, different rounding */
+                               pass of its own; a reliable update inside a chunk is two
+                               launches, its last step taken by the next D_oe pass; same
+                               mathematics, different rounding */
   /* LAUNCH, PERSISTENT and FUSED give the same results bit for bit */
 };
 
