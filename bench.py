@@ -139,6 +139,20 @@ def dominant_kernel(torch, qx, lat, g32, bd, reps, plain=False):
     return t_k, achieved
 
 
+def launch_floor(torch, qx, synth, reps):
+    """Per-launch time of the same kernel on a 2^4 lattice (8 output sites,
+    one block) with the same graph-replayed timer: the dispatch-to-dispatch
+    floor that every launch pays, whatever its work."""
+    dims = (2, 2, 2, 2)
+    lat = qx.Lattice(dims)
+    g = qx.Gauge(lat, torch.from_numpy(synth.haar_gauge(dims, 0)).cuda(), "f32", 12)
+    pin = qx.pack(lat, torch.from_numpy(synth.gauss_source(1, lat.hv, 1)).cuda(), "f32")
+    out = qx.dslash(g, pin, 0, 1)
+    t = qx.time_dslash(g, pin, 0, 1, out=out, reps=reps)
+    log(f"launch floor (2^4 half-Dslash, graph-replayed): {t * 1e6:.2f} us")
+    return t
+
+
 def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key, out,
                   flops_site=FLOPS_SITE):
     from paper_1612_02750_amd import synth
@@ -572,6 +586,7 @@ def main():
 
     # ---------------------------------------------- dominant kernel vs roofline
     t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
+    t_floor = launch_floor(torch, qx, synth, args.kernel_reps)
     sha = kernel_sha()
     traffic = None
     if TRAFFIC and TRAFFIC["sha"] == sha:
@@ -656,6 +671,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "avg_launch_us": round(t_k * 1e6, 3),
+            "launch_floor_us": round(t_floor * 1e6, 3),
             "launch_shape": list(shape32),
             "kernel_src_sha": sha,
             "bytes_per_site": BYTES_SITE_F32_12,
