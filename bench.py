@@ -340,15 +340,21 @@ def mesons(torch, qx, synth):
 def multi_rhs(torch, qx, synth):
     """32^4 Haar links, 12 Gaussian sources, m = 0.02, tol 1e-10: the twelve
     sources solved together (FP32 12-real inner iteration, FP64 reliable
-    updates, one batch) against plain FP64 CG solving them one after another."""
+    updates, one batch) against plain FP64 CG solving them one after another;
+    the same batch with FP16 12-real inner links, and the first source alone
+    with FP32 and with FP16 inner links."""
     dims, m, nsrc = (32, 32, 32, 32), 0.02, 12
     lat = qx.Lattice(dims)
     Ud = torch.from_numpy(synth.haar_gauge(dims, 0)).cuda()
     g64 = qx.Gauge(lat, Ud, "f64", 18)
     g32 = qx.Gauge(lat, Ud, "f32", 12)
+    g16 = qx.Gauge(lat, Ud, "f16", 12)
     del Ud
     shape12 = g32.tune(nsrc)
     shape1 = g64.tune(1)
+    # FP16 inner links run the FP32-vector engine: the FP32 handle's shapes
+    g16.set_launch(nsrc, *shape12)
+    g16.set_launch(1, *g32.tune(1))
     bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
     x_mx = torch.empty_like(bd)
     mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=1e-10, mode=qx.CG_MIXED_F32)
@@ -358,6 +364,29 @@ def multi_rhs(torch, qx, synth):
     st = mixed.solve()
     torch.cuda.synchronize()
     t_mx = time.perf_counter() - t0
+    x_16 = torch.empty_like(bd)
+    mixed16 = qx.Batch([(g64, g16, bd, [m] * nsrc, x_16)], tol=1e-10, mode=qx.CG_MIXED_F32)
+    mixed16.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st16 = mixed16.solve()
+    torch.cuda.synchronize()
+    t_16 = time.perf_counter() - t0
+    del mixed16, x_16
+    # one source of the same system: FP32 and FP16 inner links
+    one = {}
+    for name, glo in (("f32_links", g32), ("f16_links", g16)):
+        x1 = torch.empty_like(bd[:1])
+        b1 = qx.Batch([(g64, glo, bd[:1], [m], x1)], tol=1e-10, mode=qx.CG_MIXED_F32)
+        b1.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            s1 = b1.solve()
+        torch.cuda.synchronize()
+        one[name] = {"ms": round((time.perf_counter() - t0) / 2 * 1e3, 2), "iters": s1[0].iters,
+                     "true_rel_residual": s1[0].true_rel_residual}
+        del b1, x1
     x_b64 = torch.empty_like(bd)
     batch64 = qx.Batch([(g64, None, bd, [m] * nsrc, x_b64)], tol=1e-10, mode=qx.CG_FP64)
     batch64.solve()
@@ -385,9 +414,14 @@ def multi_rhs(torch, qx, synth):
         "speedup_vs_fp64_batch": round(t_b64 / t_mx, 3),
         "mixed_iters_max": max(s.iters for s in st),
         "fp64_iters_max": max(s.iters for s in st64),
+        "mixed_f16_links_batch_12_ms": round(t_16 * 1e3, 2),
+        "mixed_f16_links_iters_max": max(s.iters for s in st16),
+        "speedup_f16_links": round(t_64 / t_16, 3),
+        "one_source_mixed": one,
         "max_true_rel_residual": max(max(s.true_rel_residual for s in st),
                                      max(s.true_rel_residual for s in st64),
-                                     max(s.true_rel_residual for s in stb)),
+                                     max(s.true_rel_residual for s in stb),
+                                     max(s.true_rel_residual for s in st16)),
         "launch_shape_f32_12src": list(shape12),
         "launch_shape_f64_1src": list(shape1),
     }
@@ -580,6 +614,21 @@ def main():
         engines[name] = {"ms": round((time.perf_counter() - t0) / 3 * 1e3, 3), "iters": se[0].iters}
         del be
     log(f"engines (mixed 16^4): {engines}")
+    # the same mixed solve with FP16 inner links (FP32 vectors), FP32 handle's shape
+    g16 = qx.Gauge(lat, Ud, "f16", 12)
+    g16.set_launch(1, *shape32)
+    x16 = torch.empty_like(bd)
+    b16 = qx.Batch([(g64, g16, bd, [m], x16)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
+    b16.solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        s16 = b16.solve()
+    torch.cuda.synchronize()
+    t_f16 = (time.perf_counter() - t0) / 3
+    log(f"mixed, FP16 inner links: {t_f16 * 1e3:.3f} ms/solve, iters {s16[0].iters}, "
+        f"residual {s16[0].true_rel_residual:.2e}")
+    del b16, x16
 
     flops_mixed = (s_mx.iters * 606 + s_mx.reliable_updates * 582) * V
     value = flops_mixed / t_mixed / 1e9
@@ -656,7 +705,9 @@ def main():
         },
         "cg_time_to_solution_ms": {"mixed_f32_12": round(t_mixed * 1e3, 3),
                                    "fp64": round(t_fp64 * 1e3, 3),
-                                   "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3)},
+                                   "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3),
+                                   "mixed_f16_links_12": round(t_f16 * 1e3, 3),
+                                   "mixed_f16_links_iters": s16[0].iters},
         "cg_engines_mixed_ms": engines,
         "cg_iterations": {"mixed": s_mx.iters, "mixed_reliable_updates": s_mx.reliable_updates,
                           "fp64": s_64.iters},

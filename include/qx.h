@@ -74,12 +74,15 @@ enum {
 enum { QX_BC_T_ANTIPERIODIC = 1 };
 
 /* Storage precision of packed fields.  QX_PREC_F16 (storage below the
-   single and double precision the paper measures, Sec. 4): links as IEEE binary16 pairs; colour vectors as
-   binary16 pairs scaled per site by one FP32 number, the largest |re| or |im|
-   of the site's three colours (16 bytes per site and source); every
-   arithmetic step in FP32.  F16 handles and fields serve qx_field_pack /
-   qx_field_unpack, qx_dslash, qx_apply_A and the launch-shape calls; the
-   solver, force, molecular-dynamics and meson calls reject them. */
+   single and double precision the paper measures, Sec. 4): links as IEEE
+   binary16 pairs (each part its FP64 value rounded once to nearest, ties to
+   even); colour vectors as binary16 pairs scaled per site by one
+   FP32 number, the largest |re| or |im| of the site's three colours (16 bytes
+   per site and source); every arithmetic step in FP32.  F16 handles and
+   fields serve qx_field_pack / qx_field_unpack, qx_dslash, qx_apply_A and the
+   launch-shape calls; an F16 gauge handle also serves as the inner handle
+   (glo) of a mixed solve, force or meson call, whose inner vectors stay FP32.
+   The FP64 handle of those calls, and molecular dynamics, reject it. */
 enum { QX_PREC_F64 = 0, QX_PREC_F32 = 1, QX_PREC_F16 = 2 };
 
 /* link storage: 18 reals, or 12 reals (rows 0-1, row 2 rebuilt in-kernel as
@@ -227,7 +230,9 @@ int qx_cg_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params,
 /* Solve (m_s^2 - D_eo D_oe) x_s = b_s for s < nrhs, every source with its own
    CG recurrence (no block Krylov).  g64: FP64 gauge handle (reliable updates
    and the final residual); glo: the inner-precision handle for
-   QX_CG_MIXED_F32 (FP32 links, 18 or 12 reals) or NULL for QX_CG_FP64.
+   QX_CG_MIXED_F32 (FP32 links, 18 or 12 reals, or FP16 links: the inner
+   iterations then load binary16 links and keep FP32 vectors and arithmetic)
+   or NULL for QX_CG_FP64.
    b, x: canonical complex128 [nrhs][V/2][3] device buffers (x holds the
    initial guess on entry if params->use_x0).  ws: device workspace of at
    least qx_cg_workspace_bytes.  stats: host array of nrhs entries.
@@ -363,8 +368,8 @@ int qx_md_workspace_bytes(const qx_lattice_t* lat, const qx_md_params_t* params,
 
 /* One leapfrog trajectory of nsteps steps: U and p are advanced in place; the
    gauge handles g64 (FP64) and glo (the inner precision of a mixed solve, or
-   NULL) must be loaded from U's lattice and are repacked from U after every
-   link update.  phi NULL: pure gauge.  Returns H at the start and the end and
+   NULL; FP32 only) must be loaded from U's lattice and are repacked from U
+   after every link update.  phi NULL: pure gauge.  Returns H at the start and the end and
    the total CG iterations of the force solves.  One-hop operator only
    (QX_EINVAL for the Naik link storage).  Synchronises the stream. */
 int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_params_t* params, void* U,

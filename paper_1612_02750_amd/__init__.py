@@ -337,7 +337,8 @@ def cg(g64: Gauge, b, masses, glo: Optional[Gauge] = None, tol=1e-10, max_iter=1
        mode=None, delta=0.1, x0=None, chunk=0, ws=None, stream=None, raise_on_fail=True,
        engine=ENGINE_AUTO):
     """Solve (m_s^2 - D_eo D_oe) x_s = b_s; b (nrhs, V/2, 3) complex128.  Returns (x, stats).
-    mode defaults to mixed FP32/FP64 when glo is given, else FP64."""
+    mode defaults to mixed FP32/FP64 when glo (an FP32 or FP16 Gauge: the inner links) is
+    given, else FP64."""
     torch = _torch()
     L = load()
     lat = g64.lat

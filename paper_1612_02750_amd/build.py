@@ -19,9 +19,12 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqx.so")
 # (source, object name, extra flags): the engine's instantiation unit is
-# compiled once per (inner precision, link storage) pair, in parallel
+# compiled once per (inner precision, link storage) pair, in parallel (the
+# binary16 inner links under FP32 vectors are three more pairs)
 UNITS = [("qx_engine_inst.hip", f"qx_engine_{r}_{n}", [f"-DQX_R={r}", f"-DQX_RECON={n}"])
          for r in ("float", "double") for n in (18, 12, 36)] + [
+    ("qx_engine_inst.hip", f"qx_engine_float_{n}_links16", ["-DQX_R=float", f"-DQX_RECON={n}", "-DQX_LINKS16"])
+    for n in (18, 12, 36)] + [
     ("qx_engine.hip", "qx_engine", []),
     ("qx_dslash.hip", "qx_dslash", []),
     ("qx_kernels.hip", "qx_kernels", []),

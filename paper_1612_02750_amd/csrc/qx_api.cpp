@@ -428,8 +428,9 @@ int check_system(const qx_gauge* g64, const qx_gauge* glo, const qx_cg_params_t*
   if (!g64) return fail(QX_EINVAL, "solver: NULL FP64 gauge handle");
   if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "solver: g64 must be an FP64 gauge handle");
   if (p->mode == QX_CG_MIXED_F32) {
-    if (!glo) return fail(QX_EINVAL, "solver: the mixed mode needs an FP32 gauge handle");
-    if (glo->prec != QX_PREC_F32) return fail(QX_EINVAL, "solver: glo must be an FP32 gauge handle");
+    if (!glo) return fail(QX_EINVAL, "solver: the mixed mode needs an FP32 or FP16 gauge handle");
+    if (glo->prec != QX_PREC_F32 && glo->prec != QX_PREC_F16)
+      return fail(QX_EINVAL, "solver: glo must be an FP32 or FP16 gauge handle");
     if (!same_lattice(g64, glo)) return fail(QX_EINVAL, "solver: g64 and glo are on different lattices");
     if ((glo->recon == QX_RECON_NAIK) != (g64->recon == QX_RECON_NAIK))
       return fail(QX_EINVAL, "solver: g64 and glo must both hold the improved (Naik) operator or neither");
@@ -533,8 +534,11 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   B->cfg.prec_lo = prec_lo;
   B->cfg.recon_lo = s0.glo->recon;
   B->cfg.recon_hi = s0.g64->recon;
+  // FP16 inner links: the vectors and the arithmetic stay FP32
+  B->cfg.links16 = s0.glo->prec == QX_PREC_F16;
   for (const auto& s : B->specs) {
-    if (s.glo->recon != B->cfg.recon_lo || s.g64->recon != B->cfg.recon_hi)
+    if (s.glo->recon != B->cfg.recon_lo || s.g64->recon != B->cfg.recon_hi ||
+        s.glo->prec != s0.glo->prec)
       return fail(QX_EINVAL, "batch: all systems must use the same link storage");
   }
   B->cfg.nsrc_max = nb;

@@ -1,6 +1,7 @@
 // CG engine dispatch: picks the (inner precision, link storage) instantiation
 // of the launch sequences (qx_engine_kernels.h, instantiated per pair in
 // qx_engine_inst.hip).  The engine itself is described there.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "qx_dispatch.h"
@@ -9,8 +10,21 @@
 
 namespace qx {
 
+// The iteration's instantiation: inner arithmetic and vectors R, inner links
+// LS (R, or binary16 under FP32 vectors).
+template <typename F>
+hipError_t with_iteration_types(const EngineCfg& c, F&& f) {
+  if (!c.links16)
+    return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
+      return f.template operator()<R, RECON, R>();
+    });
+  if (c.prec_lo != 1) return hipErrorInvalidValue;
+  return with_recon(c.recon_lo,
+                    [&]<int RECON>() { return f.template operator()<float, RECON, __half>(); });
+}
+
 bool engine_supported(const EngineCfg& c) {
-  const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) &&
+  const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) && (!c.links16 || c.prec_lo == 1) &&
                      (c.recon_lo == 18 || c.recon_lo == 12 || c.recon_lo == 36);
   const bool ok_hi = c.recon_hi == 18 || c.recon_hi == 12 || c.recon_hi == 36;
   const bool ok_shape = nbt_lps_instantiated(c.shape.nbt, c.shape.lps) &&
@@ -25,8 +39,8 @@ hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s) {
 }
 
 hipError_t engine_iteration(const EngineCfg& c, int parity, hipStream_t s) {
-  return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
-    return iteration_impl<R, RECON>(c, parity, s);
+  return with_iteration_types(c, [&]<typename R, int RECON, typename LS>() {
+    return iteration_impl<R, RECON, LS>(c, parity, s);
   });
 }
 
@@ -51,8 +65,8 @@ int cu_count() {
 
 int engine_persistent_capacity(const EngineCfg& c) {
   int per_cu = 0;
-  hipError_t e = with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
-    per_cu = persistent_per_cu_impl<R, RECON>(c);
+  hipError_t e = with_iteration_types(c, [&]<typename R, int RECON, typename LS>() {
+    per_cu = persistent_per_cu_impl<R, RECON, LS>(c);
     return hipSuccess;
   });
   if (e != hipSuccess) return 0;
@@ -70,8 +84,8 @@ hipError_t engine_persistent(const EngineCfg& c, int iters, GridSync* gs, int gr
       khz = 100000;
     timeout = 2000LL * khz;
   }
-  return with_prec_recon(c.prec_lo, c.recon_lo, [&]<typename R, int RECON>() {
-    return persistent_impl<R, RECON>(c, iters, gs, grid, timeout, s);
+  return with_iteration_types(c, [&]<typename R, int RECON, typename LS>() {
+    return persistent_impl<R, RECON, LS>(c, iters, gs, grid, timeout, s);
   });
 }
 

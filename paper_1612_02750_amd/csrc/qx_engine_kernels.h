@@ -25,6 +25,10 @@
 // Vector slots: inner precision vlo = {x_lo, r, p, Ap, t(odd), p'}, FP64
 // vhi = {x_hi, r_hi, b, t_hi(odd)}; each slot is [nsrc][3][hv]; p' is the
 // second p slot of the fused sequence.
+//
+// Template parameters of the iteration kernels: R is the inner arithmetic and
+// vector storage (float or double), LS the storage of the inner links (R, or
+// __half under FP32 vectors: the links are converted to R as they are loaded).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -385,7 +389,7 @@ hipError_t finalize(const EngineCfg& c, int kind, hipStream_t s) {
 // kernels and the persistent kernel.
 
 // E1: t = 2 D_oe p for running sources.
-template <typename R, int RECON, int NBT, int LPS, bool FRESH>
+template <typename R, int RECON, int NBT, int LPS, bool FRESH, typename LS>
 __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b, int order) {
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
@@ -403,7 +407,7 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp,
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
                                      FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv}, act, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
@@ -414,7 +418,7 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
 }
 
 // E2: Ap = m^2 p - 1/4 (2D_eo) t and the partials of Re<p, Ap>.
-template <typename R, int RECON, int NBT, int LPS, bool FRESH>
+template <typename R, int RECON, int NBT, int LPS, bool FRESH, typename LS>
 __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b, int order, int pslot,
                                          double* sh, double* tot) {
@@ -433,7 +437,7 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   if (act) {
     Site s;
     site_geometry(d.g, 0, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 0, cb, s, dp,
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
                                      FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
   }
   double dot[NBT];
@@ -523,20 +527,20 @@ __global__ void __launch_bounds__(256) k_iter_p(const SysDesc* __restrict__ sys,
   p_tile<R, false>(sys, nsys, st, logical_block(xcd));
 }
 
-template <typename R, int RECON, int NBT, int LPS>
+template <typename R, int RECON, int NBT, int LPS, typename LS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDesc* __restrict__ sys,
                                                                     int nsys, const SrcState* st,
                                                                     int xcd) {
-  doe_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), xcd);
+  doe_tile<R, RECON, NBT, LPS, false, LS>(sys, nsys, st, logical_block(xcd), xcd);
 }
 
-template <typename R, int RECON, int NBT, int LPS>
+template <typename R, int RECON, int NBT, int LPS, typename LS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDesc* __restrict__ sys,
                                                                     int nsys, const SrcState* st,
                                                                     int pslot, int xcd) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
-  deo_tile<R, RECON, NBT, LPS, false>(sys, nsys, st, logical_block(xcd), xcd, pslot, sh, tot);
+  deo_tile<R, RECON, NBT, LPS, false, LS>(sys, nsys, st, logical_block(xcd), xcd, pslot, sh, tot);
 }
 
 template <typename R>
@@ -603,7 +607,7 @@ struct PendIn {
 // sites into slot pout, and computes t = 2 D_oe p_new for running sources
 // with p_new formed on the fly at the neighbours from slot pin.  The system's
 // first block writes the updated states (slot st_out).
-template <typename R, int RECON, int NBT, int LPS>
+template <typename R, int RECON, int NBT, int LPS, typename LS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     k_fiter_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* __restrict__ st_in,
                 SrcState* __restrict__ st_out, int pin, int pout, int xcd) {
@@ -676,7 +680,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp, src, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp, src, act, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
@@ -793,7 +797,7 @@ __device__ __forceinline__ double next_rho(double rho, double alpha, double rap,
   return t < 0.0 ? 0.0 : t;
 }
 
-template <typename R, int RECON, int NBT, int LPS>
+template <typename R, int RECON, int NBT, int LPS, typename LS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     k_f2_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* __restrict__ st_in,
              SrcState* __restrict__ st_out, int pin, int pout, int rin, int rout, int xcd) {
@@ -935,7 +939,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 1, cb, s, dp, src, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp, src, act, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
@@ -946,7 +950,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
 // Ap = m^2 p - 1/4 (2D_eo) t and the partials of <p, Ap>, Re<r, Ap>, |Ap|^2
 // and |r|^2 for running sources; the system's first block copies the states
 // from slot 1 (st_in) to slot 0.
-template <typename R, int RECON, int NBT, int LPS>
+template <typename R, int RECON, int NBT, int LPS, typename LS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     k_f2_deo(const SysDesc* __restrict__ sys, int nsys, const SrcState* __restrict__ st_in,
              SrcState* __restrict__ st_out, int pslot, int rslot, int xcd) {
@@ -970,7 +974,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (act) {
     Site s;
     site_geometry(d.g, 0, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<R>*)d.links_lo, 0, cb, s, dp,
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
                                      FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
   }
   double dpa[NBT], dra[NBT], daa[NBT], drr[NBT];
@@ -1052,7 +1056,7 @@ __device__ __forceinline__ bool grid_sync(GridSync* gs, unsigned nblocks, long l
   return *ok_sh != 0;
 }
 
-template <typename R, int RECON, int NBT, int LPS>
+template <typename R, int RECON, int NBT, int LPS, typename LS>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     k_cg_persistent(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int nsrc_total,
                     int nblk_total, int nvblk_total, int iters, GridSync* gs,
@@ -1072,10 +1076,10 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     for (int b = blockIdx.x; b < nvblk_total; b += gridDim.x) p_tile<R, true>(sys, nsys, st, b);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
-      doe_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0);
+      doe_tile<R, RECON, NBT, LPS, true, LS>(sys, nsys, st, b, 0);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int b = blockIdx.x; b < nblk_total; b += gridDim.x)
-      deo_tile<R, RECON, NBT, LPS, true>(sys, nsys, st, b, 0, 2, sh, tot);
+      deo_tile<R, RECON, NBT, LPS, true, LS>(sys, nsys, st, b, 0, 2, sh, tot);
     if (!grid_sync(gs, gridDim.x, timeout, &ok)) return;
     for (int g = blockIdx.x; g < nsrc_total; g += gridDim.x)
       finalize_one<true>(sys, nsys, st, g, FIN_ALPHA, sh);
@@ -1234,7 +1238,7 @@ hipError_t init_impl(const EngineCfg& c, int zero_xhi, hipStream_t s) {
   return e;
 }
 
-template <typename R, int RECON>
+template <typename R, int RECON, typename LS>
 hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * c.shape.lps * G);
@@ -1245,9 +1249,9 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
     const int rin = parity ? 6 : 1, rout = parity ? 1 : 6;
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-      hipLaunchKernelGGL((k_f2_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+      hipLaunchKernelGGL((k_f2_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st, c.d_st1, pin, pout, rin, rout, c.shape.xcd);
-      hipLaunchKernelGGL((k_f2_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+      hipLaunchKernelGGL((k_f2_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st1, c.d_st, pout, rout, c.shape.xcd);
       return hipGetLastError();
     });
@@ -1256,9 +1260,9 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     // p alternates between slots 2 and 5; the states between the two slots
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-      hipLaunchKernelGGL((k_fiter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys,
+      hipLaunchKernelGGL((k_fiter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys,
                          c.nsys, c.d_st, c.d_st1, pin, pout, c.shape.xcd);
-      hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+      hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                          c.d_st1, pout, c.shape.xcd);
       hipLaunchKernelGGL(k_fiter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,
                          pout, c.shape.xcd);
@@ -1267,9 +1271,9 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   }
   hipError_t e = with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+    hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                        c.d_st, c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
+    hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
                        c.d_st, 2, c.shape.xcd);
     return hipGetLastError();
   });
@@ -1318,7 +1322,7 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   return e;
 }
 
-template <typename R, int RECON>
+template <typename R, int RECON, typename LS>
 int persistent_per_cu_impl(const EngineCfg& c) {
   const int G = shape_groups(c.shape, c.nsrc_max);
   const int threads = 64 * c.shape.lps * G;
@@ -1326,12 +1330,12 @@ int persistent_per_cu_impl(const EngineCfg& c) {
   int per_cu = 0;
   hipError_t e = with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS>), threads, lds);
+        &per_cu, reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS, LS>), threads, lds);
   });
   return e == hipSuccess ? per_cu : 0;
 }
 
-template <typename R, int RECON>
+template <typename R, int RECON, typename LS>
 hipError_t persistent_impl(const EngineCfg& c, int iters, GridSync* gs, int grid,
                            long long timeout, hipStream_t s) {
   const int G = shape_groups(c.shape, c.nsrc_max);
@@ -1343,7 +1347,7 @@ hipError_t persistent_impl(const EngineCfg& c, int iters, GridSync* gs, int grid
   void* args[] = {&sys, &nsys, &st, &nsrc, &nblk, &nvblk, &iters, &gs, &timeout};
   return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     return hipLaunchCooperativeKernel(
-        reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS>), dim3(grid),
+        reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS, LS>), dim3(grid),
         dim3(threads), args, (unsigned)lds, s);
   });
 }

@@ -21,11 +21,13 @@ namespace qx {
 
 // =================================================================== packing
 
-// An FP64 value in the storage type S (FP16 rounds through FP32).
+// An FP64 value in the storage type S, rounded once to nearest (ties to even).
+// (FP16 is converted straight from FP64: a detour through FP32 would round
+// twice, and differ where the FP32 value lands on a binary16 tie.)
 template <typename S>
 __device__ __forceinline__ S to_store(double x) {
   if constexpr (std::is_same_v<S, __half>)
-    return __float2half_rn((float)x);
+    return __half_raw{static_cast<_Float16>(x)};
   else
     return (S)x;
 }

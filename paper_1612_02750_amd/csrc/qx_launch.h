@@ -72,6 +72,7 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
 // number of sources each thread handles (nb), and the launch shape.
 struct EngineCfg {
   int prec_lo = 0, recon_lo = 18, recon_hi = 18;
+  bool links16 = false;  // inner links stored as binary16 (prec_lo FP32: the vectors stay FP32)
   int nsrc_max = 1;  // most sources of any system (sets the groups of a block)
   LaunchShape shape;
   int nsys = 0, nblk_total = 0, nvblk_total = 0, nsrc_total = 0;

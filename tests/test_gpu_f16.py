@@ -143,7 +143,9 @@ def test_apply_A_f16_parity(qx, recon):
 
 
 def test_f16_rejected_by_solvers(qx):
-    """Solvers, the force and molecular dynamics take no FP16 handle."""
+    """An FP16 handle serves a solve only as its inner links (glo, covered in
+    test_gpu_f16_solve.py): never as the FP64 handle, and molecular dynamics
+    takes none."""
     dims = (4, 4, 4, 4)
     lat = qx.Lattice(dims)
     Ud = to_dev(gauge(dims, seed=50))
@@ -151,14 +153,14 @@ def test_f16_rejected_by_solvers(qx):
     g16 = qx.Gauge(lat, Ud, "f16", 12)
     b = to_dev(synth.gauss_source(1, lat.hv, 51))
     with pytest.raises(qx.QXError) as e:
-        qx.cg(g64, b, [0.1], glo=g16)
+        qx.cg(g16, b, [0.1])
     assert e.value.code == qx.EINVAL
     with pytest.raises(qx.QXError):
-        qx.cg(g16, b, [0.1])
+        qx.cg(g16, b, [0.1], glo=g16)
     with pytest.raises(qx.QXError):
         qx.force(g16, b, 0.1)
     with pytest.raises(qx.QXError):
-        qx.meson_correlators(g64, 0.1, (0, 0, 0, 0), glo=g16)
+        qx.meson_correlators(g16, 0.1, (0, 0, 0, 0), glo=g16)
     U = gauge(dims, seed=50)
     p = np.zeros((4, lat.V, 8))
     Ud2, pd = to_dev(U), to_dev(p)
