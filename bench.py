@@ -91,7 +91,7 @@ BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colou
 # From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
 # launch shape "nbt,lps,order".
 TRAFFIC = {
-    "sha": "4d5ef673eba93951",
+    "sha": "df7db0e2ba0391c3",
     "bytes": {
         "1,1,0": 16251904,
         "1,1,1": 15072256,
