@@ -529,7 +529,7 @@ def force_16(torch, qx, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; run with --gpus 1"}))
         sys.exit(2)
     import torch
 

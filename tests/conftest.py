@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def qx():
-    """The HIP binding, on a GPU machine only; fails loudly if the library is missing."""
+    """The HIP binding, on a machine with a GPU only; fails loudly if the library is missing."""
     import torch
 
     if not torch.cuda.is_available():
