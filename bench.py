@@ -429,6 +429,37 @@ def multi_rhs(torch, qx, synth):
     return out
 
 
+def f16_links_weak32(torch, qx, synth):
+    """32^4 weak-field links (eps 0.3), one source, m = 0.05, tol 1e-10: the
+    mixed solve with FP32 and with FP16 12-real inner links (the FP32
+    handle's tuned launch shape for both)."""
+    dims, m = (32, 32, 32, 32), 0.05
+    lat = qx.Lattice(dims)
+    Ud = torch.from_numpy(synth.weak_gauge(dims, 0.3, 0)).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", 18)
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    g16 = qx.Gauge(lat, Ud, "f16", 12)
+    del Ud
+    g16.set_launch(1, *g32.tune(1))
+    bd = torch.from_numpy(synth.gauss_source(1, lat.hv, 1)).cuda()
+    out = {"workload": "32^4 weak-field links eps=0.3, one source, m=0.05, mixed to 1e-10"}
+    for name, glo in (("f32_links", g32), ("f16_links", g16)):
+        x = torch.empty_like(bd)
+        B = qx.Batch([(g64, glo, bd, [m], x)], tol=1e-10, mode=qx.CG_MIXED_F32)
+        B.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            st = B.solve()
+        torch.cuda.synchronize()
+        out[name] = {"ms": round((time.perf_counter() - t0) / 3 * 1e3, 2), "iters": st[0].iters,
+                     "true_rel_residual": st[0].true_rel_residual}
+        del B, x
+    out["speedup_f16_links"] = round(out["f32_links"]["ms"] / out["f16_links"]["ms"], 3)
+    log(f"32^4 weak field, FP16 inner links: {out}")
+    return out
+
+
 def cg_kernels_sample(torch, qx, synth):
     """A few CG iterations for counter runs: the step's 16^4 mixed solve (the
     AUTO engine) cut at 32 iterations, and the 32^4 twelve-source mixed solve
@@ -647,6 +678,7 @@ def main():
     copy_gbs, read_gbs = copy_probe(torch, qx)
 
     multi = None if args.no_multi else multi_rhs(torch, qx, synth)
+    f16w = None if args.no_multi else f16_links_weak32(torch, qx, synth)
     naik = naik_cg(torch, qx, synth)
     md = hmc_md(torch, qx, synth)
     mes = mesons(torch, qx, synth)
@@ -730,6 +762,7 @@ def main():
         },
         "dslash_sweep": d32,
         "multi_rhs_32^4": multi,
+        "f16_links_32^4_weak": f16w,
         "naik_cg_16^4": naik,
         "hmc_md_16^4": md,
         "mesons_16^3x32": mes,
