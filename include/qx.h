@@ -81,8 +81,8 @@ enum { QX_BC_T_ANTIPERIODIC = 1 };
    per site and source); every arithmetic step in FP32.  F16 handles and
    fields serve qx_field_pack / qx_field_unpack, qx_dslash, qx_apply_A and the
    launch-shape calls; an F16 gauge handle also serves as the inner handle
-   (glo) of a mixed solve, force or meson call, whose inner vectors stay FP32.
-   The FP64 handle of those calls, and molecular dynamics, reject it. */
+   (glo) of a mixed solve, force, molecular-dynamics or meson call, whose
+   inner vectors stay FP32.  The FP64 handle of those calls rejects it. */
 enum { QX_PREC_F64 = 0, QX_PREC_F32 = 1, QX_PREC_F16 = 2 };
 
 /* link storage: 18 reals, or 12 reals (rows 0-1, row 2 rebuilt in-kernel as
@@ -368,8 +368,8 @@ int qx_md_workspace_bytes(const qx_lattice_t* lat, const qx_md_params_t* params,
 
 /* One leapfrog trajectory of nsteps steps: U and p are advanced in place; the
    gauge handles g64 (FP64) and glo (the inner precision of a mixed solve, or
-   NULL; FP32 only) must be loaded from U's lattice and are repacked from U
-   after every link update.  phi NULL: pure gauge.  Returns H at the start and the end and
+   NULL; FP32 or FP16 links) must be loaded from U's lattice and are repacked
+   from U after every link update.  phi NULL: pure gauge.  Returns H at the start and the end and
    the total CG iterations of the force solves.  One-hop operator only
    (QX_EINVAL for the Naik link storage).  Synchronises the stream. */
 int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_params_t* params, void* U,

@@ -1129,8 +1129,6 @@ extern "C" int qx_md_trajectory(qx_gauge_t* g64, qx_gauge_t* glo, const qx_md_pa
   if (!g64 || !p || !U || !mom || !ws || !H_start || !H_end || p->nsteps < 1)
     return fail(QX_EINVAL, "qx_md_trajectory: bad argument");
   if (g64->prec != QX_PREC_F64) return fail(QX_EINVAL, "qx_md_trajectory: g64 must be FP64");
-  if (glo && glo->prec == QX_PREC_F16)
-    return fail(QX_EINVAL, "qx_md_trajectory: the solver takes no FP16 gauge handle");
   if (g64->recon == QX_RECON_NAIK || (glo && glo->recon == QX_RECON_NAIK))
     return fail(QX_EINVAL, "qx_md_trajectory: the force is implemented for the one-hop operator");
   if (glo && !same_lattice(g64, glo))

@@ -144,8 +144,7 @@ def test_apply_A_f16_parity(qx, recon):
 
 def test_f16_rejected_by_solvers(qx):
     """An FP16 handle serves a solve only as its inner links (glo, covered in
-    test_gpu_f16_solve.py): never as the FP64 handle, and molecular dynamics
-    takes none."""
+    test_gpu_f16_solve.py), never as the FP64 handle."""
     dims = (4, 4, 4, 4)
     lat = qx.Lattice(dims)
     Ud = to_dev(gauge(dims, seed=50))
@@ -164,6 +163,7 @@ def test_f16_rejected_by_solvers(qx):
     U = gauge(dims, seed=50)
     p = np.zeros((4, lat.V, 8))
     Ud2, pd = to_dev(U), to_dev(p)
+    g16b = qx.Gauge(lat, Ud2, "f16", 12)
     with pytest.raises(qx.QXError):
-        qx.md_trajectory(g64, Ud2, pd, 5.5, 0.01, 1, glo=g16)
+        qx.md_trajectory(g16b, Ud2, pd, 5.5, 0.01, 1)
     assert np.array_equal(to_host(Ud2), U)  # rejected before any update

@@ -180,3 +180,31 @@ def test_mesons_f16_links(qx):
     assert all(s.status == 0 for s in st)
     scale = np.abs(ref).max()
     assert np.abs(C - ref).max() <= 1e-9 * scale
+
+
+def test_md_trajectory_f16_links(qx):
+    """Molecular dynamics with FP16 inner links in the force solves (the FP16
+    handle repacked from U after every link update): the trajectory of FP64
+    force solves (both to 1e-12), and back to the start under -p."""
+    dims = (4, 4, 4, 8)
+    lat = qx.Lattice(dims)
+    U = gauge(dims, "weak", seed=82, eps=0.2)
+    rng = np.random.default_rng(83)
+    p = rng.standard_normal((4, lat.V, 8))
+    phi = to_dev(synth.gauss_source(1, lat.hv, 84)[0])
+    Uf, pf = to_dev(U), to_dev(p)
+    F0, F1, _ = qx.md_trajectory(qx.Gauge(lat, Uf, "f64"), Uf, pf, 5.5, 0.05, 6, phi=phi,
+                                 mass=0.2, tol=1e-12)
+    Ud, pd = to_dev(U), to_dev(p)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    g16 = qx.Gauge(lat, Ud, "f16", 12)
+    H0, H1, iters = qx.md_trajectory(g64, Ud, pd, 5.5, 0.05, 6, phi=phi, mass=0.2, glo=g16,
+                                     tol=1e-12)
+    assert iters > 0
+    assert abs(H0 - F0) <= 1e-10 * abs(F0) and abs((H1 - H0) - (F1 - F0)) <= 1e-7
+    assert np.abs(to_host(Ud) - to_host(Uf)).max() <= 1e-10
+    pd.neg_()
+    H2, H3, _ = qx.md_trajectory(g64, Ud, pd, 5.5, 0.05, 6, phi=phi, mass=0.2, glo=g16, tol=1e-12)
+    assert np.abs(to_host(Ud) - U).max() <= 1e-9
+    assert np.abs(-to_host(pd) - p).max() <= 1e-8
+    assert abs(H3 - H0) <= 1e-9 * abs(H0)
