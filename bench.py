@@ -16,6 +16,11 @@ Reported beside it (same run):
     Infinity Cache) and 48^4 in FP32-12, FP64-18 and FP16-12 (per-site
     scaled vectors), one and twelve sources;
   * the measured bandwidth of a plain copy kernel;
+  * 32^4 with twelve sources (Haar links, m = 0.02): one mixed batch against
+    plain FP64 solves one after another and an FP64 batch, the same batch with
+    FP16 inner links, and its first source alone with FP32 and FP16 inner
+    links; a 32^4 weak-field solve with FP32 and FP16 inner links; the 16^4
+    step with FP16 inner links;
   * the improved operator (Naik term): Dslash at 32^4 / 48^4 and a 16^4 CG;
   * one HMC molecular-dynamics trajectory on 16^4 and point-source meson
     correlators on 16^3 x 32;
