@@ -344,36 +344,49 @@ struct FieldIn {
   }
 };
 
-// FP16 colour vectors: per source [3][hv] half-precision complex numbers
-// followed by [hv] FP32 scales (16 bytes per site); element = half * scale.
+// FP16 colour vectors: per source [hv] records of 16 bytes, one per site:
+// the three colours as half-precision complex numbers (12 bytes) and the
+// site's FP32 scale; element = half * scale.  A site is one 16-byte load.
+typedef unsigned qx_u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ cplx<float> h2_scaled(unsigned w, float sc) {
+  __half2 h;
+  __builtin_memcpy(&h, &w, sizeof h);
+  const float2 f = __half22float2(h);
+  return {f.x * sc, f.y * sc};
+}
+
 struct FieldInH {
   const char* __restrict__ p;  // first source of the thread
   size_t hv;
   __device__ __forceinline__ cplx<float> operator()(int j, int c, int site) const {
-    const char* b = p + (size_t)j * 16 * hv;
-    const cplx<float> v = ld_cplx_as<false, float>(reinterpret_cast<const cplx<__half>*>(b) + c * hv,
-                                                   (unsigned)site);
-    const float sc = reinterpret_cast<const float*>(b + 12 * hv)[site];
-    return {v.re * sc, v.im * sc};
+    // the three colours of a site read the same record: one load after CSE
+    const qx_u32x4 r =
+        reinterpret_cast<const qx_u32x4*>(p + (size_t)j * 16 * hv)[(unsigned)site];
+    return h2_scaled(c == 0 ? r.x : c == 1 ? r.y : r.z, __uint_as_float(r.w));
   }
 };
 
 // Store the colour vector v of site cb into an FP16 source (layout of
 // FieldInH): scale = the largest |re| or |im| of v, pairs = v / scale.
-__device__ __forceinline__ void st_field_h(char* __restrict__ src, size_t hv, int cb,
+__device__ __forceinline__ void st_field_h(char* __restrict__ src, int cb,
                                            const cplx<float> (&v)[3]) {
   float m = 0.0f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
   const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+  qx_u32x4 r;
+  unsigned w[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const __half2 h = __floats2half2_rn(v[c].re * inv, v[c].im * inv);
-    unsigned w;
-    __builtin_memcpy(&w, &h, sizeof w);
-    reinterpret_cast<unsigned*>(src + (size_t)c * 4 * hv)[cb] = w;
+    __builtin_memcpy(&w[c], &h, sizeof w[c]);
   }
-  reinterpret_cast<float*>(src + 12 * hv)[cb] = m;
+  r.x = w[0];
+  r.y = w[1];
+  r.z = w[2];
+  r.w = __float_as_uint(m);
+  reinterpret_cast<qx_u32x4*>(src)[cb] = r;
 }
 
 // acc[j] += hop H applied to in_j, j < NBT (bit j of act).

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_dslash_h(
     const cplx<float> o[3] = {{scale * v[0].re, scale * v[0].im},
                               {scale * v[1].re, scale * v[1].im},
                               {scale * v[2].re, scale * v[2].im}};
-    st_field_h(out + (k0 + j) * ss, hv, cb, o);
+    st_field_h(out + (k0 + j) * ss, cb, o);
   });
 }
 
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_deo_axpy_h(
       const cplx<float> pv = pin(j, c, cb);
       o[c] = {m2 * pv.re - 0.25f * acc[j][c].re, m2 * pv.im - 0.25f * acc[j][c].im};
     }
-    st_field_h(out + (k0 + j) * ss, hv, cb, o);
+    st_field_h(out + (k0 + j) * ss, cb, o);
   }
 }
 

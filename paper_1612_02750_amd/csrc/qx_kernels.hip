@@ -136,13 +136,15 @@ __global__ void __launch_bounds__(256) k_pack_field_h(int hv, int nsrc,
   }
   const float sc = (float)m;
   const double inv = sc > 0.0f ? 1.0 / (double)sc : 0.0;
-  char* b = out + s * 16 * (int64_t)hv;
-  cplx<__half>* h = reinterpret_cast<cplx<__half>*>(b);
+  // one 16-byte record per site: three half-precision complex numbers (each
+  // part the FP64 quotient rounded once to binary16), the scale
+  char* rec = out + (s * (int64_t)hv + cb) * 16;
+  cplx<__half>* h = reinterpret_cast<cplx<__half>*>(rec);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    h[c * (int64_t)hv + cb] = {__float2half_rn((float)(v[c].re * inv)),
-                               __float2half_rn((float)(v[c].im * inv))};
-  reinterpret_cast<float*>(b + 12 * (int64_t)hv)[cb] = sc;
+    h[c] = {__half_raw{static_cast<_Float16>(v[c].re * inv)},
+            __half_raw{static_cast<_Float16>(v[c].im * inv)}};
+  reinterpret_cast<float*>(rec)[3] = sc;
 }
 
 __global__ void __launch_bounds__(256) k_unpack_field_h(int hv, int nsrc,
@@ -150,13 +152,12 @@ __global__ void __launch_bounds__(256) k_unpack_field_h(int hv, int nsrc,
                                                         cplx<double>* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nsrc * hv) return;
-  const int64_t s = i / hv, cb = i - s * hv;
-  const char* b = in + s * 16 * (int64_t)hv;
-  const cplx<__half>* h = reinterpret_cast<const cplx<__half>*>(b);
-  const double sc = (double)reinterpret_cast<const float*>(b + 12 * (int64_t)hv)[cb];
+  const char* rec = in + i * 16;  // the site's record (source-major, i = s hv + cb)
+  const cplx<__half>* h = reinterpret_cast<const cplx<__half>*>(rec);
+  const double sc = (double)reinterpret_cast<const float*>(rec)[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const cplx<__half> v = h[c * (int64_t)hv + cb];
+    const cplx<__half> v = h[c];
     out[i * 3 + c] = {(double)__half2float(v.re) * sc, (double)__half2float(v.im) * sc};
   }
 }

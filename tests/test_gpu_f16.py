@@ -13,7 +13,7 @@ links); 1e-3 leaves room for the worst of the small lattices.
 
 The pack/unpack format itself is checked bit for bit against a numpy
 transcription of its definition (scale = largest |re| or |im| of the site as
-FP32; pair = FP32 rounding of component / scale, then binary16 rounding).
+FP32; pair = component / scale in FP64, rounded once to binary16).
 """
 import numpy as np
 import pytest
@@ -34,7 +34,7 @@ def _quantise(b):
     m = np.abs(parts).max(axis=(2, 3))
     sc = m.astype(np.float32)
     inv = np.where(sc > 0, 1.0 / np.where(sc > 0, sc, 1).astype(np.float64), 0.0)
-    q = (parts * inv[:, :, None, None]).astype(np.float32).astype(np.float16)
+    q = (parts * inv[:, :, None, None]).astype(np.float16)
     return q, sc
 
 
@@ -47,6 +47,10 @@ def test_field_pack_f16_format(qx):
     b[1, 7] = 0.0
     b[2, 11] *= 1e-6
     b[0, 5] *= 1e4
+    # quotients just above a binary16 tie whose FP32 rounding lands on the tie:
+    # one rounding from FP64 goes up, a detour through FP32 would go to even
+    b[1, 9] = [1.0, 0.5 + 2.0 ** -12 + 2.0 ** -40, -(0.25 + 2.0 ** -13 + 2.0 ** -41) * 1j]
+    b[2, 13] = [-1.0, 1j * (0.75 + 2.0 ** -12 + 2.0 ** -38), 0.125 + 2.0 ** -14 + 2.0 ** -43]
     back = to_host(qx.unpack(lat, qx.pack(lat, to_dev(b), "f16"), 3, "f16"))
     q, sc = _quantise(b)
     deq = q.astype(np.float64) * sc.astype(np.float64)[:, :, None, None]
