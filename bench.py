@@ -96,20 +96,20 @@ BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colou
 # From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
 # launch shape "nbt,lps,order".
 TRAFFIC = {
-    "sha": "df7db0e2ba0391c3",
+    "sha": "d6903850bf97e7ed",
     "bytes": {
-        "1,1,0": 16251904,
-        "1,1,1": 15072256,
-        "1,1,2": 14875648,
-        "1,1,3": 14875648,
-        "1,2,0": 16271360,
-        "1,2,1": 15091712,
-        "1,2,2": 14895104,
-        "1,2,3": 14895104,
-        "1,4,0": 16267264,
-        "1,4,1": 15087616,
-        "1,4,2": 14891008,
-        "1,4,3": 14891008,
+        "1,1,0": 16248832,
+        "1,1,1": 15069184,
+        "1,1,2": 14880768,
+        "1,1,3": 14880768,
+        "1,2,0": 16277504,
+        "1,2,1": 15097856,
+        "1,2,2": 14901248,
+        "1,2,3": 14901248,
+        "1,4,0": 16254976,
+        "1,4,1": 15075328,
+        "1,4,2": 14886912,
+        "1,4,3": 14886912,
         "1,8,0": 16287744,
         "1,8,1": 15108096,
         "1,8,2": 14911488,
