@@ -39,7 +39,7 @@ inline size_t cplx_bytes(int prec) { return prec == 0 ? 16 : 8; }
 // Bytes of one stored complex link element (F16 = 2 -> 4).
 inline size_t link_cplx_bytes(int prec) { return prec == 0 ? 16 : prec == 1 ? 8 : 4; }
 // Bytes of one packed source of a half-lattice field: [3][hv] complex, or for
-// F16 [3][hv] binary16 pairs and [hv] FP32 scales.
+// F16 [hv] records of 16 bytes (three binary16 pairs and an FP32 scale).
 inline size_t source_bytes(const Geo& g, int prec) {
   return prec == 2 ? (size_t)16 * g.hv : (size_t)3 * g.hv * cplx_bytes(prec);
 }
