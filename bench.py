@@ -96,7 +96,7 @@ BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colou
 # From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
 # launch shape "nbt,lps,order".
 TRAFFIC = {
-    "sha": "d6903850bf97e7ed",
+    "sha": "35f119f62d191bfe",
     "bytes": {
         "1,1,0": 16248832,
         "1,1,1": 15069184,
