@@ -43,6 +43,9 @@
  *      link gradient complex128 [4][V][3][3]
  *  - Packed (internal, device) layouts are opaque byte buffers produced by the
  *    pack calls; their sizes come from qx_gauge_bytes / qx_field_bytes.
+ *  - Device buffers (packed, canonical, workspaces) are read and written with
+ *    16-byte accesses: pass 16-byte aligned pointers (hipMalloc and PyTorch
+ *    allocations are 256-byte aligned).
  */
 #ifndef QX_H
 #define QX_H
