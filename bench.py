@@ -364,6 +364,7 @@ def multi_rhs(torch, qx, synth):
     bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
     x_mx = torch.empty_like(bd)
     mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=1e-10, mode=qx.CG_MIXED_F32)
+    tuned = {"mixed_batch_12": list(mixed.tune(2))}
     mixed.solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -395,6 +396,7 @@ def multi_rhs(torch, qx, synth):
         del b1, x1
     x_b64 = torch.empty_like(bd)
     batch64 = qx.Batch([(g64, None, bd, [m] * nsrc, x_b64)], tol=1e-10, mode=qx.CG_FP64)
+    tuned["fp64_batch_12"] = list(batch64.tune(2))
     batch64.solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -405,6 +407,7 @@ def multi_rhs(torch, qx, synth):
     x_64 = torch.empty_like(bd)
     plains = [qx.Batch([(g64, None, bd[k:k + 1], [m], x_64[k:k + 1])], tol=1e-10, mode=qx.CG_FP64)
               for k in range(nsrc)]
+    tuned["fp64_sequential"] = [list(p.tune(1)) for p in plains][0]
     plains[0].solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -430,6 +433,7 @@ def multi_rhs(torch, qx, synth):
                                      max(s.true_rel_residual for s in st16)),
         "launch_shape_f32_12src": list(shape12),
         "launch_shape_f64_1src": list(shape1),
+        "solver_launch_shapes": tuned,
     }
     log(f"32^4 x 12 sources: {out}")
     return out
@@ -614,6 +618,9 @@ def main():
     mixed = qx.Batch([(g64, g32, bd, [m], x_mx)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
     plain = qx.Batch([(g64, None, bd, [m], x_64)], tol=tol, mode=qx.CG_FP64)
 
+    # the solver's own launch-shape tuner, for both solves (outside the timed region)
+    solver_shapes = {"mixed": list(mixed.tune(2)), "fp64": list(plain.tune(2))}
+    log(f"solver launch shapes: {solver_shapes}")
     for _ in range(args.warmup):
         mixed.solve()
     plain.solve()
@@ -747,6 +754,7 @@ def main():
                                    "mixed_f16_links_12": round(t_f16 * 1e3, 3),
                                    "mixed_f16_links_iters": s16[0].iters},
         "cg_engines_mixed_ms": engines,
+        "cg_solver_launch_shapes": solver_shapes,
         "cg_iterations": {"mixed": s_mx.iters, "mixed_reliable_updates": s_mx.reliable_updates,
                           "fp64": s_64.iters},
         "true_rel_residual": {"mixed": s_mx.true_rel_residual, "fp64": s_64.true_rel_residual},

@@ -275,6 +275,19 @@ int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg_params_t* 
    source, systems in order.  Synchronises the stream. */
 int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream);
 
+/* Launch-shape tuner of a batch: times `nchunks` (1..64) chunks of its solve
+   (after one untimed chunk) under every launch shape (sources per thread,
+   wavefronts per site, block order) the batch admits, and keeps the fastest
+   for every later solve of the batch; writes it to *nbt, *lps, *order (each
+   may be NULL).  The Dslash tuner times the stencil kernel alone; the
+   solver's passes read what the previous pass wrote, so their best shape can
+   differ.  A solve's result depends on the shape only through the rounding
+   order of the hop sums.  Uses the batch's workspace, never writes the
+   systems' x, synchronises the stream.  QX_EINVAL for a NULL batch, nchunks
+   outside 1..64 or the persistent engine. */
+int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps, int* order,
+                  hipStream_t stream);
+
 /* As qx_batch_solve without any host synchronisation (for callers that keep
    enqueueing dependent work): enqueues the start of the solve, exactly
    `nchunks` (>= 1) chunks of inner-iteration slots with their reliable-update

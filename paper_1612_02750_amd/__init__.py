@@ -102,6 +102,7 @@ def load():
         "qx_batch_solve": ([_P, _P, _P], _I),
         "qx_batch_solve_async": ([_P, _I, _P, _P], _I),
         "qx_batch_info": ([_P, _P, _P], _I),
+        "qx_batch_tune": ([_P, _I, _P, _P, _P, _P], _I),
         "qx_tune_cache_load": ([ctypes.c_char_p], _I),
         "qx_tune_cache_save": ([ctypes.c_char_p], _I),
         "qx_batch_destroy": ([_P], _I),
@@ -400,6 +401,14 @@ class Batch:
         if raise_on_fail:
             _check(rc)
         return _stats(st, self.nsrc)
+
+    def tune(self, nchunks: int = 2, stream=None):
+        """Time nchunks chunks of this batch's solve under every launch shape
+        it admits and keep the fastest; returns (nbt, lps, order)."""
+        n, l, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().qx_batch_tune(self._h, int(nchunks), ctypes.byref(n), ctypes.byref(l),
+                                    ctypes.byref(o), _stream(stream)))
+        return n.value, l.value, o.value
 
     def chunk(self) -> int:
         c = ctypes.c_int()

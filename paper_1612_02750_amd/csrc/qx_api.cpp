@@ -470,7 +470,10 @@ struct qx_batch {
   SrcState* h_st0 = nullptr;  // pinned initial states (written once, at create)
   GridSync* h_gs = nullptr;  // inside h_st's buffer
   char* ws = nullptr;
+  size_t ws_bytes = 0;
   int chunk = 16, ru_every = 4;
+  bool forced = false;         // launch shape set by qx_batch_tune
+  LaunchShape forced_shape{};
   bool use_graph = false;
   bool persistent = false;
   int pgrid = 0;
@@ -536,6 +539,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   // 2.37 s.  (One source per thread keeps the tuned order: at 32^4 the tuned
   // shapes were within 1-2 % of the best there.)
   if (max_nblk > kFuseMaxBlocks && sh.nbt > 1) sh.xcd = 0;
+  if (B->forced) sh = B->forced_shape;
 
   B->cfg = EngineCfg{};
   B->cfg.prec_lo = prec_lo;
@@ -872,6 +876,7 @@ extern "C" int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg
   }
   const char* env = getenv("QX_GRAPH");
   B->use_graph = !(env && env[0] == '0');
+  B->ws_bytes = ws_bytes;
   rc = build_plan(B, ws, ws_bytes);
   if (!rc) rc = upload_plan(B, stream);
   if (!rc) rc = capture_graph(B, stream);
@@ -880,6 +885,91 @@ extern "C" int qx_batch_create(int nsys, const qx_system_t* systems, const qx_cg
     return rc;
   }
   *out = B;
+  return QX_OK;
+}
+
+// Plan, upload and capture the batch under its current shape choice.
+static int replan(qx_batch* B, hipStream_t s) {
+  int rc = build_plan(B, B->ws, B->ws_bytes);
+  if (!rc) rc = upload_plan(B, s);
+  if (!rc) rc = capture_graph(B, s);
+  return rc;
+}
+
+extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps, int* order,
+                             hipStream_t stream) {
+  if (!batch || nchunks < 1 || nchunks > 64)
+    return fail(QX_EINVAL, "qx_batch_tune: bad argument");
+  qx_batch* B = batch;
+  if (B->persistent) return fail(QX_EINVAL, "qx_batch_tune: the persistent engine is not tuned");
+  int nb = 1;
+  for (const auto& sp : B->specs) nb = std::max(nb, sp.nrhs);
+  const size_t csz = cplx_bytes(lo_prec(&B->params));
+  // batches the fused sequences can serve split the hops of a site over two
+  // wavefronts or more under every engine (the plan's rule, which keeps the
+  // engines' bits equal): no one-wavefront shapes there
+  int max_nblk = 0;
+  for (const auto& d : B->sys) max_nblk = std::max(max_nblk, d.nblk);
+  const bool split = max_nblk <= kFuseMaxBlocks;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QX_HIP(hipEventCreate(&e0), "qx_batch_tune: event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(QX_EHIP, "qx_batch_tune: event");
+  }
+  // time one untimed and then `nchunks` timed chunks of the solve under each
+  // candidate shape (the caller's x is not written: only the finish unpacks)
+  auto time_shape = [&](const LaunchShape& sh, float* ms) -> int {
+    B->forced = true;
+    B->forced_shape = sh;
+    int rc = replan(B, stream);
+    if (rc) return rc;
+    rc = enqueue_start(B, stream);
+    if (!rc) rc = enqueue_one_chunk(B, stream);
+    if (!rc) rc = enqueue_start(B, stream);
+    if (rc) return rc;
+    QX_HIP(hipEventRecord(e0, stream), "qx_batch_tune: event");
+    for (int c = 0; c < nchunks && !rc; ++c) rc = enqueue_one_chunk(B, stream);
+    if (rc) return rc;
+    QX_HIP(hipEventRecord(e1, stream), "qx_batch_tune: event");
+    QX_HIP(hipEventSynchronize(e1), "qx_batch_tune: chunk");
+    QX_HIP(hipEventElapsedTime(ms, e0, e1), "qx_batch_tune: elapsed");
+    return QX_OK;
+  };
+  LaunchShape best{};
+  float best_ms = 1e30f;
+  int rc = QX_OK;
+  for (int nb_t : {1, 2, 4})
+    for (int l : {1, 2, 4, 8})
+      for (int x = 0; x < 4 && rc != QX_EHIP; ++x) {
+        const LaunchShape sh{nb_t, l, x};
+        if (!nbt_lps_instantiated(nb_t, l) || !shape_ok(sh, nb, csz)) continue;
+        if (split && l == 1) continue;
+        float ms = 0.f;
+        rc = time_shape(sh, &ms);
+        if (rc == QX_OK && ms < best_ms) {
+          best_ms = ms;
+          best = sh;
+        }
+      }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc == QX_EHIP) {
+    B->forced = false;
+    return rc;
+  }
+  if (best_ms >= 1e30f) {
+    B->forced = false;
+    replan(B, stream);
+    return fail(QX_EINVAL, "qx_batch_tune: no launch shape could be timed");
+  }
+  B->forced = true;
+  B->forced_shape = best;
+  rc = replan(B, stream);
+  if (rc) return rc;
+  if (nbt) *nbt = best.nbt;
+  if (lps) *lps = best.lps;
+  if (order) *order = best.xcd;
   return QX_OK;
 }
 

@@ -1,0 +1,89 @@
+"""The batch launch-shape tuner: it times chunks of the solve under every
+admissible shape, keeps the fastest, leaves the systems' x untouched, and the
+tuned batch solves to 1e-10 (oracle) with the same bits as a batch planned
+with that shape from the handle."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import gauge, to_dev, to_host
+from paper_1612_02750_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _systems(qx, torch, specs):
+    systems, keep = [], []
+    for k, (dims, nsrc) in enumerate(specs):
+        lat = qx.Lattice(dims, antiperiodic_t=True)
+        U = gauge(dims, seed=90 + k)
+        Ud = to_dev(U)
+        g64 = qx.Gauge(lat, Ud, "f64")
+        g32 = qx.Gauge(lat, Ud, "f32", 12)
+        b = synth.gauss_source(nsrc, lat.hv, 95 + k)
+        masses = [0.05 + 0.05 * j for j in range(nsrc)]
+        xd = torch.zeros_like(to_dev(b))
+        systems.append((g64, g32, to_dev(b), masses, xd))
+        keep.append((dims, U, b, masses, xd))
+    return systems, keep
+
+
+def _check(keep, stats):
+    j = 0
+    for dims, U, b, masses, xd in keep:
+        x = to_host(xd)
+        for k in range(b.shape[0]):
+            rr = oracle.true_residual(dims, U, masses[k], b[k], x[k], oracle.BC_T_ANTIPERIODIC)
+            assert rr <= 1e-10 and stats[j].status == 0, (dims, k, rr)
+            j += 1
+
+
+@pytest.mark.parametrize("engine,stream", [("AUTO", True), ("LAUNCH", False), ("FUSED2", True)])
+def test_batch_tune(qx, engine, stream):
+    import torch
+
+    specs = [((8, 8, 8, 8), 2), ((6, 4, 4, 8), 3)]
+    systems, keep = _systems(qx, torch, specs)
+    side = torch.cuda.Stream() if stream else torch.cuda.current_stream()
+    with torch.cuda.stream(side):
+        B = qx.Batch(systems, tol=1e-10, engine=getattr(qx, "ENGINE_" + engine))
+        nbt, lps, order = B.tune(2)
+        torch.cuda.synchronize()
+        assert nbt in (1, 2, 4) and lps in (1, 2, 4, 8) and order in (0, 1, 2, 3)
+        assert lps > 1  # batches of at most 1024 blocks per system split the hops
+        for k in keep:
+            assert not to_host(k[4]).any()  # tuning writes no solution
+        st = B.solve()
+        torch.cuda.synchronize()
+        _check(keep, st)
+        tuned = [to_host(k[4]).copy() for k in keep]
+        # the same shape set on the first system's handle gives the same bits
+        systems[0][1].set_launch(3, nbt, lps, order)
+        for k in keep:
+            k[4].zero_()
+        B2 = qx.Batch(systems, tol=1e-10, engine=getattr(qx, "ENGINE_" + engine))
+        st2 = B2.solve()
+        torch.cuda.synchronize()
+    for k, t in zip(keep, tuned):
+        assert np.array_equal(to_host(k[4]), t)
+    assert [s.iters for s in st] == [s.iters for s in st2]
+
+
+def test_batch_tune_rejects(qx):
+    import torch
+
+    systems, _ = _systems(qx, torch, [((4, 4, 4, 4), 1)])
+    B = qx.Batch(systems, tol=1e-10)
+    for n in (0, 65):
+        with pytest.raises(qx.QXError) as e:
+            B.tune(n)
+        assert e.value.code == qx.EINVAL
+    P = qx.Batch(systems, tol=1e-10, engine=qx.ENGINE_PERSISTENT)
+    with pytest.raises(qx.QXError) as e:
+        P.tune(1)
+    assert e.value.code == qx.EINVAL
+    L = qx.load()
+    assert L.qx_batch_tune(None, 1, None, None, None, None) == qx.EINVAL
+    # the batch still solves after a rejected call
+    st = B.solve()
+    assert st[0].status == 0
