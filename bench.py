@@ -508,6 +508,8 @@ def uneven_batch(torch, qx, synth):
         systems.append((g64, g32, bd, [mlist[(k + j) % 3] for j in range(4)], torch.empty_like(bd)))
     batch = qx.Batch(systems, tol=1e-10, mode=qx.CG_MIXED_F32)
     singles = [qx.Batch([s], tol=1e-10, mode=qx.CG_MIXED_F32) for s in systems]
+    # the solver's launch-shape tuner on the batch and on each single system
+    tuned = {"batch": list(batch.tune(2)), "singles": [list(b.tune(2)) for b in singles]}
     batch.solve()
     for b in singles:
         b.solve()
@@ -532,6 +534,7 @@ def uneven_batch(torch, qx, synth):
         "max_true_rel_residual": max(max(x.true_rel_residual for x in st),
                                      max(x.true_rel_residual for x in st1)),
         "all_converged": all(x.status == qx.OK for x in st + st1),
+        "solver_launch_shapes": tuned,
     }
     log(f"uneven batch: {out}")
     return out
