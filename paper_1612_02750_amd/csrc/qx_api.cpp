@@ -944,7 +944,7 @@ extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps,
       for (int x = 0; x < 4 && rc != QX_EHIP; ++x) {
         const LaunchShape sh{nb_t, l, x};
         if (!nbt_lps_instantiated(nb_t, l) || !shape_ok(sh, nb, csz)) continue;
-        if (split && l == 1) continue;
+        if ((nb_t > 1 && nb_t > nb) || (split && l == 1)) continue;
         float ms = 0.f;
         rc = time_shape(sh, &ms);
         if (rc == QX_OK && ms < best_ms) {
