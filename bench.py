@@ -373,6 +373,7 @@ def multi_rhs(torch, qx, synth):
     t_mx = time.perf_counter() - t0
     x_16 = torch.empty_like(bd)
     mixed16 = qx.Batch([(g64, g16, bd, [m] * nsrc, x_16)], tol=1e-10, mode=qx.CG_MIXED_F32)
+    tuned["mixed_f16_links_batch_12"] = list(mixed16.tune(2))
     mixed16.solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -385,6 +386,7 @@ def multi_rhs(torch, qx, synth):
     for name, glo in (("f32_links", g32), ("f16_links", g16)):
         x1 = torch.empty_like(bd[:1])
         b1 = qx.Batch([(g64, glo, bd[:1], [m], x1)], tol=1e-10, mode=qx.CG_MIXED_F32)
+        tuned[f"one_source_{name}"] = list(b1.tune(2))
         b1.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -456,6 +458,7 @@ def f16_links_weak32(torch, qx, synth):
     for name, glo in (("f32_links", g32), ("f16_links", g16)):
         x = torch.empty_like(bd)
         B = qx.Batch([(g64, glo, bd, [m], x)], tol=1e-10, mode=qx.CG_MIXED_F32)
+        shape = list(B.tune(2))
         B.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -463,7 +466,7 @@ def f16_links_weak32(torch, qx, synth):
             st = B.solve()
         torch.cuda.synchronize()
         out[name] = {"ms": round((time.perf_counter() - t0) / 3 * 1e3, 2), "iters": st[0].iters,
-                     "true_rel_residual": st[0].true_rel_residual}
+                     "true_rel_residual": st[0].true_rel_residual, "solver_launch_shape": shape}
         del B, x
     out["speedup_f16_links"] = round(out["f32_links"]["ms"] / out["f16_links"]["ms"], 3)
     log(f"32^4 weak field, FP16 inner links: {out}")
