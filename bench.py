@@ -277,6 +277,7 @@ def naik_cg(torch, qx, synth):
     for name, glo, mode in (("mixed", g32, qx.CG_MIXED_F32), ("fp64", None, qx.CG_FP64)):
         x = torch.empty_like(bd)
         B = qx.Batch([(g64, glo, bd, [m], x)], tol=tol, mode=mode)
+        out[f"{name}_solver_launch_shape"] = list(B.tune(2))
         B.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
