@@ -333,30 +333,23 @@ def test_force_gauge_covariance():
         np.testing.assert_allclose(Gg[mu], rot, rtol=0, atol=1e-9 * np.abs(G).max())
 
 
-def test_force_matches_torch_autograd():
-    """torch.autograd through torch.linalg.solve of a dense, differentiable A(U)
-    on 2^2 x 4^2, compared with the oracle's G (PyTorch convention for complex)."""
-    torch = pytest.importorskip("torch")
-    dims = (2, 4, 2, 4)
-    m = 0.2
+def _torch_dense_A(torch, dims, U, m):
+    """A(U) = m^2 - D_eo D_oe as a dense torch matrix, differentiable in U,
+    with D assembled link by link from its definition (the forward hop
+    +1/2 eta U_mu(x) and its backward partner -1/2 eta U_mu(x)^dag), rows of
+    each parity in checkerboard order.  Returns (Ut, A, D)."""
     V = int(np.prod(dims))
     hv = V // 2
-    U = _haar(dims, 6)
-    phi = synth.gauss_source(1, hv, 3)[0]
     sites = coords_bf(dims)
     pos = {c: i for i, c in enumerate(sites)}
     par = [sum(c) % 2 for c in sites]
     Ut = torch.tensor(U, dtype=torch.complex128, requires_grad=True)
-    # dense D(U) assembled from the link definition, differentiable in U
-    D = torch.zeros((3 * V, 3 * V), dtype=torch.complex128)
     rows = []
     for i, c in enumerate(sites):
         for mu in range(4):
             y = list(c)
             y[mu] = (y[mu] + 1) % dims[mu]
-            j = pos[tuple(y)]
-            e = eta_bf(mu, c)
-            rows.append((i, j, mu, e))
+            rows.append((i, pos[tuple(y)], mu, eta_bf(mu, c)))
     blocks = torch.zeros((V, V, 3, 3), dtype=torch.complex128)
     for i, j, mu, e in rows:
         blocks = blocks.index_put((torch.tensor([i]), torch.tensor([j])),
@@ -367,9 +360,20 @@ def test_force_matches_torch_autograd():
     ev = [3 * i + a for i in range(V) if par[i] == 0 for a in range(3)]
     od = [3 * i + a for i in range(V) if par[i] == 1 for a in range(3)]
     ev_t, od_t = torch.tensor(ev), torch.tensor(od)
-    Deo = D[ev_t][:, od_t]
-    Doe = D[od_t][:, ev_t]
-    A = m * m * torch.eye(3 * hv, dtype=torch.complex128) - Deo @ Doe
+    A = m * m * torch.eye(3 * hv, dtype=torch.complex128) - D[ev_t][:, od_t] @ D[od_t][:, ev_t]
+    return Ut, A, D
+
+
+def test_force_matches_torch_autograd():
+    """torch.autograd through torch.linalg.solve of a dense, differentiable A(U)
+    on 2^2 x 4^2, compared with the oracle's G (PyTorch convention for complex)."""
+    torch = pytest.importorskip("torch")
+    dims = (2, 4, 2, 4)
+    m = 0.2
+    hv = int(np.prod(dims)) // 2
+    U = _haar(dims, 6)
+    phi = synth.gauss_source(1, hv, 3)[0]
+    Ut, A, D = _torch_dense_A(torch, dims, U, m)
     # the dense D must be the oracle's (consistency of the two constructions)
     Dn = oracle.dense_D(dims, U)
     assert np.abs(D.detach().numpy() - Dn).max() < 1e-15
@@ -379,6 +383,46 @@ def test_force_matches_torch_autograd():
     S.backward()
     _, G, _, _ = oracle.force(dims, U, m, phi, tol=1e-14)
     np.testing.assert_allclose(Ut.grad.numpy(), G, rtol=0, atol=1e-11 * np.abs(G).max())
+
+
+@pytest.mark.parametrize("dims,seed", [((2, 4, 2, 4), 7), ((4, 2, 2, 4), 8)])
+def test_force_from_fields_general_backward(dims, seed):
+    """The general backward (lambda != x): L = Re<w, A^-1 b> with w != b has the
+    upstream gradient g = w, so lambda = A^-1 w.  torch.autograd through
+    torch.linalg.solve of the dense A(U) must equal
+    oracle.force_from_fields(x = A^-1 b, lambda = A^-1 w).  The solves here use
+    the torch matrix, not the oracle's CG.
+
+    The pin separates the two pairings of the outer products: the plausible
+    mistake W1 = (lambda, D_oe lambda), W2 = (x, D_oe x) -- which coincides with
+    the right pairing when lambda = x -- equals
+    (G(lambda, lambda) + G(x, x)) / 2 and must miss the autograd gradient by far
+    more than the tolerance."""
+    torch = pytest.importorskip("torch")
+    m = 0.15
+    hv = int(np.prod(dims)) // 2
+    U = _haar(dims, seed)
+    b = synth.gauss_source(1, hv, seed + 10)[0]
+    w = synth.gauss_source(1, hv, seed + 20)[0]
+    Ut, A, _ = _torch_dense_A(torch, dims, U, m)
+    bt = torch.tensor(b.reshape(-1))
+    wt = torch.tensor(w.reshape(-1))
+    L = torch.real(torch.vdot(wt, torch.linalg.solve(A, bt)))
+    L.backward()
+    Ad = A.detach()
+    x = torch.linalg.solve(Ad, bt).numpy().reshape(hv, 3)
+    lam = torch.linalg.solve(Ad, wt).numpy().reshape(hv, 3)
+    # A is Hermitian, so the adjoint solve is a solve with A itself
+    assert np.abs(Ad.numpy() - Ad.numpy().conj().T).max() < 1e-14
+    G = oracle.force_from_fields(dims, U, x, lam)
+    ref = Ut.grad.numpy()
+    tol = 1e-11 * np.abs(ref).max()
+    np.testing.assert_allclose(G, ref, rtol=0, atol=tol)
+    wrong = 0.5 * (oracle.force_from_fields(dims, U, lam, lam) + oracle.force_from_fields(dims, U, x, x))
+    assert np.abs(wrong - ref).max() > 1e3 * tol
+    # A is Hermitian, so Re<w, A^-1 b> = Re<b, A^-1 w>: the gradient is symmetric
+    # in the two solutions
+    np.testing.assert_allclose(oracle.force_from_fields(dims, U, lam, x), ref, rtol=0, atol=tol)
 
 
 # ------------------------------------------------------------- Naik term (f1)
