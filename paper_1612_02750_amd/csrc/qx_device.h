@@ -142,13 +142,18 @@ __host__ __device__ __forceinline__ int link_sign(const Geo& g, int mu, int x0, 
 // its own L2; with this remapping XCD k works on the k-th eighth of the
 // checkerboard range, so the t and z neighbours of its sites mostly live in
 // the same L2.
-__device__ __forceinline__ int logical_block(int xcd_order) {
-  const int b = blockIdx.x;
-  if (!xcd_order) return b;
-  const int G = gridDim.x;
+// xcd_block(b, G) is that remapping for dispatch index b of a G-block grid
+// (a bijection of [0, G)).
+__host__ __device__ __forceinline__ int xcd_block(int b, int G) {
   const int q = G >> 3, r = G & 7;
   const int x = b & 7, j = b >> 3;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + j;
+}
+
+__device__ __forceinline__ int logical_block(int xcd_order) {
+  const int b = blockIdx.x;
+  if (!xcd_order) return b;
+  return xcd_block(b, gridDim.x);
 }
 
 // Largest divisor of L that is at most cap.
