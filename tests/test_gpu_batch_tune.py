@@ -87,3 +87,37 @@ def test_batch_tune_rejects(qx):
     # the batch still solves after a rejected call
     st = B.solve()
     assert st[0].status == 0
+
+
+@pytest.mark.parametrize("engine_name", ["ENGINE_LAUNCH", "ENGINE_FUSED", "ENGINE_FUSED2"])
+def test_batch_profile_and_set_launch(qx, engine_name):
+    """qx_batch_profile: event-timed chunks of the solve, pass by pass.  Every
+    iteration slot launches one D_oe and one D_eo pass; under the
+    launch-per-pass engine each source served by a D_eo launch is one
+    iteration of that source, so the served-source count equals the summed
+    iteration counts; the profile leaves x untouched.  qx_batch_set_launch
+    then fixes a shape and the solve stays oracle-correct."""
+    import torch
+
+    systems, keep = _systems(qx, torch, [((8, 4, 6, 8), 3)])
+    engine = getattr(qx, engine_name)
+    B = qx.Batch(systems, tol=1e-10, mode=qx.CG_MIXED_F32, engine=engine)
+    chunk = B.chunk()
+    passes, st = B.profile(2)
+    assert passes["doe"]["launches"] == 2 * chunk
+    assert passes["deo"]["launches"] == 2 * chunk
+    for name, q in passes.items():
+        assert 0 <= q["active_launches"] <= q["launches"]
+        assert q["ms"] >= q["active_ms"] >= 0.0
+        if q["active_launches"]:
+            assert q["active_ms"] > 0.0
+    if engine_name == "ENGINE_LAUNCH":
+        assert passes["deo"]["source_launches"] == sum(s.iters for s in st)
+        assert passes["p"]["launches"] == 2 * chunk and passes["xr"]["launches"] == 2 * chunk
+    assert all(s.iters > 0 for s in st)
+    assert not to_host(systems[0][4]).any()  # x untouched
+    B.set_launch(2, 2, 1)
+    st = B.solve()
+    _check(keep, st)
+    with pytest.raises(qx.QXError):
+        B.set_launch(3, 2, 1)
