@@ -1,36 +1,38 @@
 """Benchmark: staggered Dslash + even-odd CG on one MI355X.
 
-Workload (one step): a full mixed-precision solve of (m^2 - D_eo D_oe) x = b to
-a true FP64 relative residual of 1e-10 on a 16^4 lattice with weak-field links
-U = exp(0.3 i H) (seed 0), one Gaussian source (seed 1), m = 0.05, FP32 inner
-iteration on 12-real links, FP64 reliable updates when |r| drops below
-0.1 max|r|.  Inputs are resident in HBM before the timed region; the step
-includes packing b, every inner iteration and reliable update, and unpacking x.
+Workload (one step): the multi-source solve of the CG benchmark extended to
+many right-hand sides -- a 32^4 lattice with Haar-random SU(3) links (seed 0),
+twelve complex-Gaussian sources (seed 1), m = 0.02 for every source, solved
+together to a true FP64 relative residual of 1e-10 per source: FP32 inner
+iterations on 12-real links, FP64 reliable updates when |r| drops below
+0.1 max|r|, one batch (one launch per CG pass for all twelve sources,
+replayed from HIP graphs).  Inputs are resident in HBM before the timed
+region; a step includes packing the sources, every inner iteration and
+reliable update, and unpacking the solutions.  K steps are timed one by one
+(host synchronisation around each); ms_per_step is their median and value
+the sustained GFLOP/s of the median step.
 
 Reported beside it (same run):
-  * the same solve in plain FP64 (time-to-solution, mixed vs FP64);
-  * the dominant kernel (the FP32 half-Dslash) timed alone, launches replayed
-    from a HIP graph between HIP events on their stream, against the HBM
-    roofline;
-  * the half-Dslash on 32^4 (the size where links no longer fit the 256 MB
-    Infinity Cache) and 48^4 in FP32-12, FP64-18 and FP16-12 (per-site
-    scaled vectors), one and twelve sources;
-  * the measured bandwidth of a plain copy kernel;
-  * 32^4 with twelve sources (Haar links, m = 0.02): one mixed batch against
-    plain FP64 solves one after another and an FP64 batch, the same batch with
-    FP16 inner links, and its first source alone with FP32 and FP16 inner
-    links; a 32^4 weak-field solve with FP32 and FP16 inner links; the 16^4
-    step with FP16 inner links;
-  * the improved operator (Naik term): Dslash at 32^4 / 48^4 and a 16^4 CG;
-  * one HMC molecular-dynamics trajectory on 16^4 and point-source meson
-    correlators on 16^3 x 32;
-  * the uneven batch (8^4 ... 24^4, four sources each) replayed as one graph
-    against its systems solved one at a time, and the 16^4 fermion force;
-  * the CPU oracle (FP64 CG on the host cores) on the same system, whole
-    solves repeated for about 10 s.
+  * the same twelve systems in plain FP64: as one FP64 batch and as twelve
+    FP64 single-source solves one after another (medians of three), i.e. the
+    time-to-solution comparison mixed vs FP64 at equal and at single batching;
+  * the roofline of the dominant kernel of the step, the D_eo pass of the
+    iteration (half-Dslash with the A epilogue and the <p, A p> partials),
+    from HIP events around each of its launches in an event-timed run of the
+    same batch (two chunks of its solve, eager launches), and the other passes
+    of the iteration from the same run;
+  * the 16^4 weak-field single-source solve (mixed vs FP64, every engine, FP16
+    inner links);
+  * the half-Dslash on 32^4 and 48^4 in FP32-12, FP64-18 and FP16-12, one and
+    twelve sources, with and without the Naik term; the copy and read probes;
+  * the 32^4 twelve-source batch with FP16 inner links and its first source
+    alone; the improved operator's CG, an HMC trajectory, meson correlators,
+    the uneven batch and the 16^4 fermion force;
+  * the CPU oracle on the host cores: FP64 CG iterations of the step's first
+    system, and the half-Dslash at 16^4 and 32^4 on all threads and on one.
 
 Flop convention: 570 flops per output site per half-Dslash; one CG iteration
-costs 606 V (two half-Dslash + BLAS-1), one reliable update 570 V + 12 V.
+costs 606 V per source (two half-Dslash + BLAS-1), one reliable update 582 V.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu]
 """
@@ -56,12 +58,16 @@ FLOPS_SITE_NAIK = 1146  # 16 SU(3) x colour-vector products + 15 vector sums
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--no-multi", action="store_true",
-                    help="skip the 32^4 twelve-source comparison")
+                    help="skip the 32^4 FP16-link and one-source comparisons")
+    ap.add_argument("--solver-shape", default=None,
+                    help="nbt,lps,order of the step's batch in --kernels-only runs")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed step, its FP64 comparisons and its pass timing")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the dominant-kernel timing and the copy probe (for counter runs)")
     return ap.parse_args()
@@ -86,37 +92,28 @@ def time_kernel(torch, fn, reps):
     return e0.elapsed_time(e1) / reps * 1e-3  # seconds per launch
 
 
-BYTES_SITE_F32_12 = 432  # 8 FP32 12-real links + one input and one output colour vector
-
-# HBM-side bytes per launch of the dominant kernel from two rocprofv3 counter
-# runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
-# counters read for the library's copy kernel on 1 GiB (FETCH x 2.000, WRITE
-# x 1.000).  Reported only while the kernel sources and the launch shape are
-# the ones the counters were taken with.
-# From profiles/dslash_16x16x16x16_to_48x48x48x48_counters.md; keyed by
-# launch shape "nbt,lps,order".
-TRAFFIC = {
-    "sha": "35f119f62d191bfe",
-    "bytes": {
-        "1,1,0": 16248832,
-        "1,1,1": 15069184,
-        "1,1,2": 14880768,
-        "1,1,3": 14880768,
-        "1,2,0": 16277504,
-        "1,2,1": 15097856,
-        "1,2,2": 14901248,
-        "1,2,3": 14901248,
-        "1,4,0": 16254976,
-        "1,4,1": 15075328,
-        "1,4,2": 14886912,
-        "1,4,3": 14886912,
-        "1,8,0": 16287744,
-        "1,8,1": 15108096,
-        "1,8,2": 14911488,
-        "1,8,3": 14911488
-    },
+# Algorithmic bytes per output site of the passes of one mixed iteration
+# (FP32 12-real links, FP32 colour vectors): links are read once per launch
+# that has work, a colour vector of every served source once per site.
+LINK_B_F32_12 = 384   # 8 links x 12 reals x 4 B
+VEC_B_F32 = 24        # one FP32 colour vector (3 complex)
+PASS_BYTES = {
+    # pass: (bytes per output site per launch, per served source)
+    "doe": (LINK_B_F32_12, 2 * VEC_B_F32),   # p read, t written
+    "deo": (LINK_B_F32_12, 3 * VEC_B_F32),   # t and p read, A p written
+    "xr": (0, 6 * VEC_B_F32),                # x, r, p, A p read; x, r written
+    "p": (0, 3 * VEC_B_F32),                 # r, p read; p written
 }
-KERNEL_SOURCES = ("qx_dslash.hip", "qx_device.h", "qx_internal.h", "qx_launch.h", "qx_dispatch.h")
+
+# HBM-side bytes per launch of the dominant kernel (k_iter_deo of the
+# twelve-source step, all sources served) from two rocprofv3 counter runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
+# counters read for the library's copy and read probes on 1 GiB (FETCH x 2,
+# WRITE x 1).  Reported only while the engine sources and the launch shape are
+# the ones the counters were taken with; keyed by "nbt,lps,order".
+TRAFFIC = {"sha": None, "bytes": {}}
+KERNEL_SOURCES = ("qx_engine_kernels.h", "qx_device.h", "qx_internal.h", "qx_launch.h",
+                  "qx_dispatch.h")
 
 
 def kernel_sha():
@@ -127,35 +124,119 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def dominant_kernel(torch, qx, lat, g32, bd, reps, plain=False):
-    """The FP32 12-real half-Dslash on the workload lattice, timed alone
-    (plain=True: a few ordinary launches for a counter run, not timed)."""
-    p32 = qx.pack(lat, bd, "f32")
-    o32 = qx.dslash(g32, p32, 0, 1)
-    if plain:
-        for _ in range(reps):
-            qx.dslash(g32, p32, 0, 1, out=o32)
-        torch.cuda.synchronize()
-        return None, None
-    t_k = qx.time_dslash(g32, p32, 0, 1, out=o32, reps=reps)
-    achieved = BYTES_SITE_F32_12 * lat.hv / t_k / 1e9
-    log(f"dominant kernel (FP32-12 half-Dslash, {lat.dims}): {t_k * 1e6:.2f} us, "
-        f"{achieved:.0f} GB/s algorithmic, {FLOPS_SITE * lat.hv / t_k / 1e9:.0f} GFLOP/s")
-    return t_k, achieved
+def _sync_time(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
 
 
-def launch_floor(torch, qx, synth, reps):
-    """Per-launch time of the same kernel on a 2^4 lattice (8 output sites,
-    one block) with the same graph-replayed timer: the dispatch-to-dispatch
-    floor that every launch pays, whatever its work."""
-    dims = (2, 2, 2, 2)
+def _flops(stats, V):
+    return sum(s.iters * 606 + s.reliable_updates * 582 for s in stats) * V
+
+
+def config3_system(torch, qx, synth):
+    """The step's system: 32^4 Haar links (seed 0), 12 Gaussian sources (seed 1)."""
+    dims, nsrc = (32, 32, 32, 32), 12
     lat = qx.Lattice(dims)
-    g = qx.Gauge(lat, torch.from_numpy(synth.haar_gauge(dims, 0)).cuda(), "f32", 12)
-    pin = qx.pack(lat, torch.from_numpy(synth.gauss_source(1, lat.hv, 1)).cuda(), "f32")
-    out = qx.dslash(g, pin, 0, 1)
-    t = qx.time_dslash(g, pin, 0, 1, out=out, reps=reps)
-    log(f"launch floor (2^4 half-Dslash, graph-replayed): {t * 1e6:.2f} us")
-    return t
+    Ud = torch.from_numpy(synth.haar_gauge(dims, 0)).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", 18)
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    del Ud
+    bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
+    return lat, g64, g32, bd
+
+
+def pass_roofline(passes, hv):
+    """Per pass of the event-timed run: average duration of the launches that
+    had work, the sources they served on average, algorithmic bytes per launch
+    and the fraction of the HBM peak."""
+    out = {}
+    for name, (per_site, per_src) in PASS_BYTES.items():
+        q = passes[name]
+        if not q["active_launches"]:
+            continue
+        us = q["active_ms"] / q["active_launches"] * 1e3
+        nrun = q["source_launches"] / q["active_launches"]
+        by = (per_site + per_src * nrun) * hv
+        out[name] = {"avg_us": round(us, 2), "launches": q["active_launches"],
+                     "sources_served": round(nrun, 3), "algorithmic_bytes": int(by),
+                     "gbs": round(by / (us * 1e-6) / 1e9, 1),
+                     "frac": round(by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    for name in ("finalize", "update"):
+        q = passes[name]
+        if q["launches"]:
+            out[name] = {"avg_us": round(q["ms"] / q["launches"] * 1e3, 2),
+                         "launches": q["launches"]}
+    return out
+
+
+def headline(torch, qx, synth, args):
+    """The timed step (module docstring) with its FP64 comparisons and the
+    event timing of its passes."""
+    m, tol = 0.02, 1e-10
+    lat, g64, g32, bd = config3_system(torch, qx, synth)
+    nsrc, V, hv = bd.shape[0], lat.V, lat.hv
+    g32.tune(nsrc)
+    g64.tune(nsrc)
+    g64.tune(1)
+    x_mx = torch.empty_like(bd)
+    mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=tol, mode=qx.CG_MIXED_F32)
+    shape = list(mixed.tune(2))
+    log(f"step: solver launch shape {shape}")
+    for _ in range(args.warmup):
+        mixed.solve()
+    times, st = [], None
+    for _ in range(args.steps):
+        t, st = _sync_time(torch, mixed.solve)
+        times.append(t)
+    t_step = float(np.median(times))
+    flops = _flops(st, V)
+    log(f"step: {[round(t * 1e3, 1) for t in times]} ms, median {t_step * 1e3:.1f} ms, "
+        f"iters {max(s.iters for s in st)}, updates {max(s.reliable_updates for s in st)}, "
+        f"max residual {max(s.true_rel_residual for s in st):.2e}")
+    # the passes of the same batch, event-timed (two chunks from the start)
+    passes, st_p = mixed.profile(2)
+    roof = pass_roofline(passes, hv)
+    log(f"passes: {roof}")
+    out = {"times_ms": [round(t * 1e3, 2) for t in times], "t_step": t_step, "flops": flops,
+           "stats": st, "shape": shape, "passes": roof,
+           "profile_iters": [s.iters for s in st_p]}
+    # FP64: one batch of the twelve sources, and twelve single-source solves
+    x_b = torch.empty_like(bd)
+    b64 = qx.Batch([(g64, None, bd, [m] * nsrc, x_b)], tol=tol, mode=qx.CG_FP64)
+    out["fp64_batch_shape"] = list(b64.tune(2))
+    b64.solve()
+    tb = []
+    for _ in range(3):
+        t, stb = _sync_time(torch, b64.solve)
+        tb.append(t)
+    del b64, x_b
+    x_s = torch.empty_like(bd)
+    singles = [qx.Batch([(g64, None, bd[k:k + 1], [m], x_s[k:k + 1])], tol=tol, mode=qx.CG_FP64)
+               for k in range(nsrc)]
+    shape1 = list(singles[0].tune(2))
+    for b in singles[1:]:
+        b.set_launch(*shape1)
+    singles[0].solve()
+    ts = []
+    for _ in range(3):
+        t, st1 = _sync_time(torch, lambda: [b.solve()[0] for b in singles])
+        ts.append(t)
+    del singles, x_s
+    out.update({
+        "fp64_batch_ms": [round(t * 1e3, 2) for t in tb], "t_fp64_batch": float(np.median(tb)),
+        "fp64_seq_ms": [round(t * 1e3, 2) for t in ts], "t_fp64_seq": float(np.median(ts)),
+        "fp64_single_shape": shape1,
+        "fp64_iters_max": max(s.iters for s in stb),
+        "max_true_rel_residual": max(max(s.true_rel_residual for s in st),
+                                     max(s.true_rel_residual for s in stb),
+                                     max(s.true_rel_residual for s in st1)),
+    })
+    log(f"fp64 batch {out['fp64_batch_ms']} ms, fp64 one by one {out['fp64_seq_ms']} ms")
+    out["_keep"] = (lat, g64, g32, bd, x_mx)
+    return out
 
 
 def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key, out,
@@ -344,101 +425,39 @@ def mesons(torch, qx, synth):
     return out
 
 
-def multi_rhs(torch, qx, synth):
-    """32^4 Haar links, 12 Gaussian sources, m = 0.02, tol 1e-10: the twelve
-    sources solved together (FP32 12-real inner iteration, FP64 reliable
-    updates, one batch) against plain FP64 CG solving them one after another;
-    the same batch with FP16 12-real inner links, and the first source alone
-    with FP32 and with FP16 inner links."""
-    dims, m, nsrc = (32, 32, 32, 32), 0.02, 12
-    lat = qx.Lattice(dims)
-    Ud = torch.from_numpy(synth.haar_gauge(dims, 0)).cuda()
-    g64 = qx.Gauge(lat, Ud, "f64", 18)
-    g32 = qx.Gauge(lat, Ud, "f32", 12)
-    g16 = qx.Gauge(lat, Ud, "f16", 12)
-    del Ud
-    shape12 = g32.tune(nsrc)
-    shape1 = g64.tune(1)
-    # FP16 inner links run the FP32-vector engine: the FP32 handle's shapes
-    g16.set_launch(nsrc, *shape12)
+def multi_rhs_extras(torch, qx, synth, h):
+    """The step's system with FP16 12-real inner links (one batch of the twelve
+    sources), and its first source alone with FP32 and with FP16 inner links."""
+    m = 0.02
+    lat, g64, g32, bd, _ = h["_keep"]
+    nsrc = bd.shape[0]
+    # the step's links again (the FP16 handle is packed from the canonical field)
+    g16 = qx.Gauge(lat, torch.from_numpy(synth.haar_gauge(lat.dims, 0)).cuda(), "f16", 12)
+    g16.set_launch(nsrc, *g32.launch(nsrc))
     g16.set_launch(1, *g32.tune(1))
-    bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
-    x_mx = torch.empty_like(bd)
-    mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=1e-10, mode=qx.CG_MIXED_F32)
-    tuned = {"mixed_batch_12": list(mixed.tune(2))}
-    mixed.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = mixed.solve()
-    torch.cuda.synchronize()
-    t_mx = time.perf_counter() - t0
-    x_16 = torch.empty_like(bd)
-    mixed16 = qx.Batch([(g64, g16, bd, [m] * nsrc, x_16)], tol=1e-10, mode=qx.CG_MIXED_F32)
-    tuned["mixed_f16_links_batch_12"] = list(mixed16.tune(2))
-    mixed16.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st16 = mixed16.solve()
-    torch.cuda.synchronize()
-    t_16 = time.perf_counter() - t0
-    del mixed16, x_16
-    # one source of the same system: FP32 and FP16 inner links
+    out = {"workload": "32^4 Haar links, 12 Gaussian sources, m=0.02, tol 1e-10"}
+    x16 = torch.empty_like(bd)
+    b16 = qx.Batch([(g64, g16, bd, [m] * nsrc, x16)], tol=1e-10, mode=qx.CG_MIXED_F32)
+    out["f16_links_batch_shape"] = list(b16.tune(2))
+    b16.solve()
+    t, st16 = _sync_time(torch, b16.solve)
+    out["mixed_f16_links_batch_12_ms"] = round(t * 1e3, 2)
+    out["mixed_f16_links_iters_max"] = max(s.iters for s in st16)
+    del b16, x16
     one = {}
     for name, glo in (("f32_links", g32), ("f16_links", g16)):
         x1 = torch.empty_like(bd[:1])
         b1 = qx.Batch([(g64, glo, bd[:1], [m], x1)], tol=1e-10, mode=qx.CG_MIXED_F32)
-        tuned[f"one_source_{name}"] = list(b1.tune(2))
+        shape = list(b1.tune(2))
         b1.solve()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(2):
-            s1 = b1.solve()
-        torch.cuda.synchronize()
-        one[name] = {"ms": round((time.perf_counter() - t0) / 2 * 1e3, 2), "iters": s1[0].iters,
-                     "true_rel_residual": s1[0].true_rel_residual}
+        t, s1 = _sync_time(torch, lambda: [b1.solve(), b1.solve()][-1])
+        one[name] = {"ms": round(t / 2 * 1e3, 2), "iters": s1[0].iters,
+                     "true_rel_residual": s1[0].true_rel_residual, "solver_launch_shape": shape}
         del b1, x1
-    x_b64 = torch.empty_like(bd)
-    batch64 = qx.Batch([(g64, None, bd, [m] * nsrc, x_b64)], tol=1e-10, mode=qx.CG_FP64)
-    tuned["fp64_batch_12"] = list(batch64.tune(2))
-    batch64.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stb = batch64.solve()
-    torch.cuda.synchronize()
-    t_b64 = time.perf_counter() - t0
-    del batch64, x_b64
-    x_64 = torch.empty_like(bd)
-    plains = [qx.Batch([(g64, None, bd[k:k + 1], [m], x_64[k:k + 1])], tol=1e-10, mode=qx.CG_FP64)
-              for k in range(nsrc)]
-    tuned["fp64_sequential"] = [list(p.tune(1)) for p in plains][0]
-    plains[0].solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st64 = [p.solve()[0] for p in plains]
-    torch.cuda.synchronize()
-    t_64 = time.perf_counter() - t0
-    out = {
-        "workload": "32^4 Haar links, 12 Gaussian sources, m=0.02, tol 1e-10",
-        "mixed_batch_12_ms": round(t_mx * 1e3, 2),
-        "fp64_sequential_12_ms": round(t_64 * 1e3, 2),
-        "speedup": round(t_64 / t_mx, 3),
-        "fp64_batch_12_ms": round(t_b64 * 1e3, 2),
-        "speedup_vs_fp64_batch": round(t_b64 / t_mx, 3),
-        "mixed_iters_max": max(s.iters for s in st),
-        "fp64_iters_max": max(s.iters for s in st64),
-        "mixed_f16_links_batch_12_ms": round(t_16 * 1e3, 2),
-        "mixed_f16_links_iters_max": max(s.iters for s in st16),
-        "speedup_f16_links": round(t_64 / t_16, 3),
-        "one_source_mixed": one,
-        "max_true_rel_residual": max(max(s.true_rel_residual for s in st),
-                                     max(s.true_rel_residual for s in st64),
-                                     max(s.true_rel_residual for s in stb),
-                                     max(s.true_rel_residual for s in st16)),
-        "launch_shape_f32_12src": list(shape12),
-        "launch_shape_f64_1src": list(shape1),
-        "solver_launch_shapes": tuned,
-    }
-    log(f"32^4 x 12 sources: {out}")
+    out["one_source_mixed"] = one
+    out["max_true_rel_residual"] = max([s.true_rel_residual for s in st16] +
+                                       [v["true_rel_residual"] for v in one.values()])
+    log(f"32^4 x 12 sources, FP16 inner links and one source: {out}")
     return out
 
 
@@ -474,22 +493,121 @@ def f16_links_weak32(torch, qx, synth):
     return out
 
 
-def cg_kernels_sample(torch, qx, synth):
-    """A few CG iterations for counter runs: the step's 16^4 mixed solve (the
-    AUTO engine) cut at 32 iterations, and the 32^4 twelve-source mixed solve
-    (launch-per-pass engine) cut at 6."""
-    for dims, seed_kind, nsrc, m, iters in (((16, 16, 16, 16), "weak", 1, 0.05, 32),
-                                            ((32, 32, 32, 32), "haar", 12, 0.02, 6)):
-        lat = qx.Lattice(dims)
-        U = synth.weak_gauge(dims, 0.3, 0) if seed_kind == "weak" else synth.haar_gauge(dims, 0)
-        Ud = torch.from_numpy(U).cuda()
-        g64 = qx.Gauge(lat, Ud, "f64", 18)
-        g32 = qx.Gauge(lat, Ud, "f32", 12)
-        del Ud
-        bd = torch.from_numpy(synth.gauss_source(nsrc, lat.hv, 1)).cuda()
-        qx.cg(g64, bd, [m] * nsrc, glo=g32, tol=1e-10, max_iter=iters, raise_on_fail=False)
-        torch.cuda.synchronize()
-        del g64, g32, bd
+def kernels_only(torch, qx, synth, shape):
+    """Counter runs: the step's batch under the given solver launch shape,
+    its first two chunks (32 iterations, every source served), eagerly."""
+    m = 0.02
+    lat, g64, g32, bd = config3_system(torch, qx, synth)
+    x = torch.empty_like(bd)
+    B = qx.Batch([(g64, g32, bd, [m] * bd.shape[0], x)], tol=1e-10, mode=qx.CG_MIXED_F32)
+    B.set_launch(*shape)
+    passes, st = B.profile(2)
+    torch.cuda.synchronize()
+    return pass_roofline(passes, lat.hv), [s.iters for s in st]
+
+
+def config2_16(torch, qx, synth):
+    """16^4 weak-field links eps 0.3, m 0.05, one source, tol 1e-10: the mixed
+    solve (AUTO engine, solver-tuned shape) against plain FP64, under each
+    engine, and with FP16 inner links."""
+    dims, m, eps, tol, delta = (16, 16, 16, 16), 0.05, 0.3, 1e-10, 0.1
+    lat = qx.Lattice(dims)
+    Ud = torch.from_numpy(synth.weak_gauge(dims, eps, 0)).cuda()
+    bd = torch.from_numpy(synth.gauss_source(1, lat.hv, 1)).cuda()
+    g64 = qx.Gauge(lat, Ud, "f64", 18)
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    shape32, shape64 = g32.tune(1), g64.tune(1)
+    out = {"workload": "16^4 weak-field links eps=0.3, m=0.05, 1 Gaussian source, tol 1e-10"}
+    x_mx, x_64 = torch.empty_like(bd), torch.empty_like(bd)
+    mixed = qx.Batch([(g64, g32, bd, [m], x_mx)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
+    plain = qx.Batch([(g64, None, bd, [m], x_64)], tol=tol, mode=qx.CG_FP64)
+    out["solver_launch_shapes"] = {"mixed": list(mixed.tune(2)), "fp64": list(plain.tune(2))}
+    for b in (mixed, plain):
+        b.solve()
+    tm = [_sync_time(torch, mixed.solve)[0] for _ in range(10)]
+    tp = [_sync_time(torch, plain.solve)[0] for _ in range(10)]
+    st, s64 = mixed.solve(), plain.solve()
+    out.update({"mixed_ms": round(float(np.median(tm)) * 1e3, 3),
+                "fp64_ms": round(float(np.median(tp)) * 1e3, 3),
+                "mixed_iters": st[0].iters, "mixed_reliable_updates": st[0].reliable_updates,
+                "fp64_iters": s64[0].iters,
+                "true_rel_residual": {"mixed": st[0].true_rel_residual,
+                                      "fp64": s64[0].true_rel_residual}})
+    out["speedup_mixed_vs_fp64"] = round(out["fp64_ms"] / out["mixed_ms"], 3)
+    out["gflops_mixed"] = round(_flops(st, lat.V) / (out["mixed_ms"] * 1e-3) / 1e9, 1)
+    engines = {}
+    for name, eng in (("launch", qx.ENGINE_LAUNCH), ("fused", qx.ENGINE_FUSED),
+                      ("persistent", qx.ENGINE_PERSISTENT)):
+        xe = torch.empty_like(bd)
+        be = qx.Batch([(g64, g32, bd, [m], xe)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta,
+                      engine=eng)
+        be.solve()
+        te = [_sync_time(torch, be.solve)[0] for _ in range(3)]
+        engines[name] = round(float(np.median(te)) * 1e3, 3)
+        del be
+    out["engines_mixed_ms"] = engines
+    g16 = qx.Gauge(lat, Ud, "f16", 12)
+    g16.set_launch(1, *shape32)
+    x16 = torch.empty_like(bd)
+    b16 = qx.Batch([(g64, g16, bd, [m], x16)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
+    b16.solve()
+    t16 = [_sync_time(torch, b16.solve)[0] for _ in range(3)]
+    s16 = b16.solve()
+    out["mixed_f16_links_ms"] = round(float(np.median(t16)) * 1e3, 3)
+    out["mixed_f16_links_iters"] = s16[0].iters
+    log(f"16^4 config 2: {out}")
+    return out
+
+
+def cpu_baseline(torch, qx, synth):
+    """The oracle on the host cores: FP64 CG iterations of the step's first
+    system (calls of 20 iterations from a zero guess until 12 s have passed),
+    and the half-Dslash at 16^4 and 32^4 on every thread and on one."""
+    import oracle
+
+    threads = oracle.threads()
+    dims, m = (32, 32, 32, 32), 0.02
+    V = int(np.prod(dims))
+    U = synth.haar_gauge(dims, 0)
+    b = synth.gauss_source(1, V // 2, 1)[0]
+    t0 = time.perf_counter()
+    iters, calls = 0, 0
+    while True:
+        _, _, it, _ = oracle.cg(dims, U, m, b, tol=1e-10, max_iter=20)
+        iters += it
+        calls += 1
+        t = time.perf_counter() - t0
+        if t >= 12.0:
+            break
+    gflops = iters * 606 * V / t / 1e9
+    dsl = {}
+    for d in ((16, 16, 16, 16), (32, 32, 32, 32)):
+        Ud = synth.haar_gauge(d, 0) if d != dims else U
+        chi = synth.gauss_source(1, int(np.prod(d)) // 2, 2)[0]
+        for nthr in (threads, 1):
+            oracle.set_threads(nthr)
+            reps = 20 if d[0] == 16 else (5 if nthr > 1 else 3)
+            ts = []
+            for _ in range(reps):
+                t1 = time.perf_counter()
+                oracle.dslash_eo(d, Ud, chi, 0)
+                ts.append(time.perf_counter() - t1)
+            tm = float(np.median(ts))
+            dsl[f"{d[0]}^4_{nthr}thr"] = {"ms": round(tm * 1e3, 2),
+                                          "gflops": round(570 * int(np.prod(d)) / 2 / tm / 1e9, 2)}
+        oracle.set_threads(threads)
+    out = {
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"FP64 CG iterations of the step's first system (32^4 Haar, m=0.02, source 0): "
+                  f"{calls} calls of 20 iterations from a zero guess, {iters} iterations in "
+                  f"{t:.1f} s on {threads} OpenMP threads; same flop convention",
+        "dslash_medians": dsl,
+    }
+    log(f"cpu oracle: {out}")
+    return out
 
 
 def uneven_batch(torch, qx, synth):
@@ -577,7 +695,8 @@ def force_16(torch, qx, synth):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one process, one MI355X); "
+                                   "run it with --gpus 1"}))
         sys.exit(2)
     import torch
 
@@ -589,152 +708,47 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
 
-    # ------------------------------------------------------------- workload
-    dims = (16, 16, 16, 16)
-    m, eps, tol, delta = 0.05, 0.3, 1e-10, 0.1
-    lat = qx.Lattice(dims)
-    V, hv = lat.V, lat.hv
-    U = synth.weak_gauge(dims, eps, 0)
-    b = synth.gauss_source(1, hv, 1)
-    Ud = torch.from_numpy(U).cuda()
-    bd = torch.from_numpy(b).cuda()
-    g64 = qx.Gauge(lat, Ud, "f64", 18)
-    g32 = qx.Gauge(lat, Ud, "f32", 12)
     if args.kernels_only:
-        # counter runs: the kernels of the timed run with its launch shapes
-        # (read from the tuning cache that run wrote), a few plain launches each
-        # the dominant kernel under every one-source launch shape, three
-        # dispatches each in this order (the counter summaries map dispatches
-        # to shapes by their order)
-        order = []
-        for lps in (1, 2, 4, 8):
-            for xo in (0, 1, 2, 3):
-                g32.set_launch(1, 1, lps, xo)
-                dominant_kernel(torch, qx, lat, g32, bd, 3, plain=True)
-                order.append([1, lps, xo])
-        dslash_sweep(torch, qx, tune=False, plain=True)
+        shape = [int(v) for v in (args.solver_shape or "4,2,0").split(",")]
+        roof, iters = kernels_only(torch, qx, synth, shape)
         copy_probe(torch, qx, timed=False)
-        cg_kernels_sample(torch, qx, synth)
-        print(json.dumps({"kernels_only": True, "dominant_shapes_in_order": order}))
+        print(json.dumps({"kernels_only": True, "solver_shape": shape, "passes": roof,
+                          "iters_after": iters}))
         return
-    shape32 = g32.tune(1)
-    shape64 = g64.tune(1)
-    log(f"tuned launch shapes: f32-12 {shape32}, f64-18 {shape64}")
-    x_mx = torch.empty_like(bd)
-    x_64 = torch.empty_like(bd)
-    mixed = qx.Batch([(g64, g32, bd, [m], x_mx)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
-    plain = qx.Batch([(g64, None, bd, [m], x_64)], tol=tol, mode=qx.CG_FP64)
 
-    # the solver's own launch-shape tuner, for both solves (outside the timed region)
-    solver_shapes = {"mixed": list(mixed.tune(2)), "fp64": list(plain.tune(2))}
-    log(f"solver launch shapes: {solver_shapes}")
-    for _ in range(args.warmup):
-        mixed.solve()
-    plain.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = mixed.solve()
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / args.steps
-    s_mx = st[0]
-    log(f"mixed: {t_mixed * 1e3:.3f} ms/solve, iters {s_mx.iters}, updates {s_mx.reliable_updates}, "
-        f"residual {s_mx.true_rel_residual:.2e}")
-
-    reps64 = max(3, args.steps // 2)
-    t0 = time.perf_counter()
-    for _ in range(reps64):
-        st64 = plain.solve()
-    torch.cuda.synchronize()
-    t_fp64 = (time.perf_counter() - t0) / reps64
-    s_64 = st64[0]
-    log(f"fp64:  {t_fp64 * 1e3:.3f} ms/solve, iters {s_64.iters}, residual {s_64.true_rel_residual:.2e}")
-
-    # the same mixed solve under each CG engine
-    engines = {}
-    for name, eng in (("launch", qx.ENGINE_LAUNCH), ("persistent", qx.ENGINE_PERSISTENT)):
-        xe = torch.empty_like(bd)
-        be = qx.Batch([(g64, g32, bd, [m], xe)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta,
-                      engine=eng)
-        be.solve()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(3):
-            se = be.solve()
-        torch.cuda.synchronize()
-        engines[name] = {"ms": round((time.perf_counter() - t0) / 3 * 1e3, 3), "iters": se[0].iters}
-        del be
-    log(f"engines (mixed 16^4): {engines}")
-    # the same mixed solve with FP16 inner links (FP32 vectors), FP32 handle's shape
-    g16 = qx.Gauge(lat, Ud, "f16", 12)
-    g16.set_launch(1, *shape32)
-    x16 = torch.empty_like(bd)
-    b16 = qx.Batch([(g64, g16, bd, [m], x16)], tol=tol, mode=qx.CG_MIXED_F32, delta=delta)
-    b16.solve()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(3):
-        s16 = b16.solve()
-    torch.cuda.synchronize()
-    t_f16 = (time.perf_counter() - t0) / 3
-    log(f"mixed, FP16 inner links: {t_f16 * 1e3:.3f} ms/solve, iters {s16[0].iters}, "
-        f"residual {s16[0].true_rel_residual:.2e}")
-    del b16, x16
-
-    flops_mixed = (s_mx.iters * 606 + s_mx.reliable_updates * 582) * V
-    value = flops_mixed / t_mixed / 1e9
-
-    # ---------------------------------------------- dominant kernel vs roofline
-    t_k, achieved = dominant_kernel(torch, qx, lat, g32, bd, args.kernel_reps)
-    t_floor = launch_floor(torch, qx, synth, args.kernel_reps)
+    h = headline(torch, qx, synth, args)
+    keep = h.pop("_keep")
+    lat = keep[0]
+    V, hv = lat.V, lat.hv
+    st = h["stats"]
+    value = h["flops"] / h["t_step"] / 1e9
+    deo = h["passes"]["deo"]
     sha = kernel_sha()
     traffic = None
-    if TRAFFIC and TRAFFIC["sha"] == sha:
-        traffic = TRAFFIC["bytes"].get(",".join(str(v) for v in shape32))
+    if TRAFFIC["sha"] == sha:
+        traffic = TRAFFIC["bytes"].get(",".join(str(v) for v in h["shape"]))
+    torch.cuda.empty_cache()
 
-    # ------------------------------------------- 32^4 and 48^4 Dslash (HBM size)
-    d32 = dslash_sweep(torch, qx)
+    extras = {}
+    if not args.headline_only:
+        extras["config2_16^4"] = config2_16(torch, qx, synth)
+        extras["dslash_sweep"] = dslash_sweep(torch, qx)
+        copy_gbs, read_gbs = copy_probe(torch, qx)
+        extras["copy_probe_gbs"] = round(copy_gbs, 1)
+        extras["read_probe_gbs"] = round(read_gbs, 1)
+        if not args.no_multi:
+            extras["multi_rhs_32^4_extras"] = multi_rhs_extras(torch, qx, synth, {"_keep": keep})
+            extras["f16_links_32^4_weak"] = f16_links_weak32(torch, qx, synth)
+        extras["naik_cg_16^4"] = naik_cg(torch, qx, synth)
+        extras["hmc_md_16^4"] = hmc_md(torch, qx, synth)
+        extras["mesons_16^3x32"] = mesons(torch, qx, synth)
+        extras["uneven_batch"] = uneven_batch(torch, qx, synth)
+        extras["force_16^4"] = force_16(torch, qx, synth)
+    del keep
+    torch.cuda.empty_cache()
+    cpu = None if args.no_cpu else cpu_baseline(torch, qx, synth)
 
-    copy_gbs, read_gbs = copy_probe(torch, qx)
-
-    multi = None if args.no_multi else multi_rhs(torch, qx, synth)
-    f16w = None if args.no_multi else f16_links_weak32(torch, qx, synth)
-    naik = naik_cg(torch, qx, synth)
-    md = hmc_md(torch, qx, synth)
-    mes = mesons(torch, qx, synth)
-    uneven = uneven_batch(torch, qx, synth)
-    frc = force_16(torch, qx, synth)
-
-
-    # ------------------------------------------------------------ CPU oracle
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-
-        threads = oracle.threads()
-        # whole FP64 solves of the step's system, repeated until 10 s of host time
-        t0 = time.perf_counter()
-        solves, iters = 0, 0
-        while True:
-            xo, sto, it_o, rr_o = oracle.cg(dims, U, m, b[0], tol=tol)
-            solves += 1
-            iters += it_o
-            t_cpu = time.perf_counter() - t0
-            if t_cpu >= 10.0:
-                break
-        cpu = {
-            "value": round(iters * 606 * V / t_cpu / 1e9, 3),
-            "unit": "GFLOP/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"{solves} full FP64 CG solves of the same 16^4 system to 1e-10 "
-                      f"({it_o} iterations each, {t_cpu:.1f} s in all, true residual {rr_o:.1e}), "
-                      f"{threads} OpenMP threads",
-        }
-        # parity of the benchmarked solution against the oracle
-        rr_gpu = oracle.true_residual(dims, U, m, b[0], x_mx.cpu().numpy()[0])
-        log(f"cpu oracle: {cpu}; oracle residual of the GPU solution {rr_gpu:.2e}")
-
+    t_mx, t_b, t_s = h["t_step"], h["t_fp64_batch"], h["t_fp64_seq"]
     out = {
         "metric": "Dslash GFLOP/s + % HBM roofline; CG time-to-solution @1e-10, mixed vs FP64",
         "value": round(value, 2),
@@ -742,57 +756,59 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_mixed * 1e3, 4),
+        "ms_per_step": round(t_mx * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 inner / f64 reliable updates",
         "data": "synthetic",
         "config": {
-            "workload": "mixed-precision even-odd CG, 16^4 weak-field links eps=0.3, m=0.05, "
-                        "1 Gaussian source, FP32 12-real inner, FP64 reliable updates delta=0.1, "
-                        "tol 1e-10",
-            "lattice": list(dims),
-            "nrhs": 1,
+            "workload": "multi-source mixed-precision even-odd CG: 32^4 Haar-random SU(3) links "
+                        "(seed 0), 12 complex-Gaussian sources (seed 1) solved together, m=0.02, "
+                        "FP32 12-real inner, FP64 reliable updates delta=0.1, tol 1e-10 (true FP64 "
+                        "residual per source)",
+            "lattice": [32, 32, 32, 32],
+            "nrhs": 12,
+            "solver_launch_shape": h["shape"],
         },
-        "cg_time_to_solution_ms": {"mixed_f32_12": round(t_mixed * 1e3, 3),
-                                   "fp64": round(t_fp64 * 1e3, 3),
-                                   "speedup_mixed_vs_fp64": round(t_fp64 / t_mixed, 3),
-                                   "mixed_f16_links_12": round(t_f16 * 1e3, 3),
-                                   "mixed_f16_links_iters": s16[0].iters},
-        "cg_engines_mixed_ms": engines,
-        "cg_solver_launch_shapes": solver_shapes,
-        "cg_iterations": {"mixed": s_mx.iters, "mixed_reliable_updates": s_mx.reliable_updates,
-                          "fp64": s_64.iters},
-        "true_rel_residual": {"mixed": s_mx.true_rel_residual, "fp64": s_64.true_rel_residual},
+        "step_times_ms": h["times_ms"],
+        "cg_time_to_solution_ms": {
+            "mixed_batch_12": round(t_mx * 1e3, 2),
+            "fp64_batch_12": round(t_b * 1e3, 2),
+            "fp64_one_by_one_12": round(t_s * 1e3, 2),
+            "speedup_vs_fp64_batch": round(t_b / t_mx, 3),
+            "speedup_vs_fp64_one_by_one": round(t_s / t_mx, 3),
+            "fp64_batch_runs_ms": h["fp64_batch_ms"],
+            "fp64_one_by_one_runs_ms": h["fp64_seq_ms"],
+            "fp64_solver_launch_shapes": {"batch": h["fp64_batch_shape"],
+                                          "single": h["fp64_single_shape"]},
+        },
+        "cg_iterations": {"mixed_max": max(s.iters for s in st),
+                          "mixed_reliable_updates_max": max(s.reliable_updates for s in st),
+                          "fp64_max": h["fp64_iters_max"]},
+        "max_true_rel_residual": h["max_true_rel_residual"],
         "roofline": {
-            "kernel": f"k_dslash<float, 12, {shape32[0]}, {shape32[1]}> (FP32 12-real half-Dslash, 16^4, "
-                      f"one source)",
+            "kernel": f"k_iter_deo<float, 12, {h['shape'][0]}, {h['shape'][1]}, float> "
+                      f"(D_eo half-Dslash of the step with the A epilogue and <p, Ap> partials; "
+                      f"solver launch shape {h['shape']})",
             "bound": "hbm",
-            "achieved": round(achieved, 1),
+            "achieved": deo["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": deo["frac"],
             "traffic": traffic,
-            "avg_launch_us": round(t_k * 1e6, 3),
-            "launch_floor_us": round(t_floor * 1e6, 3),
-            "launch_shape": list(shape32),
-            "kernel_src_sha": sha,
-            "bytes_per_site": BYTES_SITE_F32_12,
+            "avg_launch_us": deo["avg_us"],
+            "launches_timed": deo["launches"],
+            "sources_served": deo["sources_served"],
+            "bytes_per_launch": deo["algorithmic_bytes"],
+            "bytes_per_site": f"{PASS_BYTES['deo'][0]} + {PASS_BYTES['deo'][1]} per source",
             "sites_per_launch": hv,
+            "kernel_src_sha": sha,
+            "passes": h["passes"],
         },
-        "dslash_sweep": d32,
-        "multi_rhs_32^4": multi,
-        "f16_links_32^4_weak": f16w,
-        "naik_cg_16^4": naik,
-        "hmc_md_16^4": md,
-        "mesons_16^3x32": mes,
-        "uneven_batch": uneven,
-        "force_16^4": frc,
-        "copy_probe_gbs": round(copy_gbs, 1),
-        "read_probe_gbs": round(read_gbs, 1),
         "cpu_baseline": cpu,
     }
+    out.update(extras)
     print(json.dumps(out))
 
 

@@ -168,14 +168,16 @@ const char* qx_last_error(void);
 
 /* ------------------------------------------------------------- lattice */
 
-/* Create a lattice description (host only).  flags: QX_BC_T_ANTIPERIODIC or 0.
+/* Create a lattice description (host only): the 4-D grid of sites with one
+   SU(3) matrix per link (Sec. 1).  flags: QX_BC_T_ANTIPERIODIC or 0.
    QX_EINVAL for an odd extent, an extent < 2 or V >= 2^31. */
 int qx_lattice_create(const int32_t dims[4], uint32_t flags, qx_lattice_t** out);
 int qx_lattice_destroy(qx_lattice_t* lat);
 /* Number of sites V, or -1 for a NULL handle. */
 int64_t qx_lattice_volume(const qx_lattice_t* lat);
 
-/* Copy the even-odd index maps computed by the device geometry code into
+/* Geometry of the 4-D grid (Sec. 1; the even-odd split is this library's
+   reading).  Copy the even-odd index maps computed by the device geometry code into
    device buffers: lex_of_eo[V] (int32) and nbr_eo[V][8] (int32; entry k < 4
    is the eo index of x + mu_k, entry 4 + k that of x - mu_k, periodic wrap).
    Exists so that tests can check the on-the-fly neighbour arithmetic of the
@@ -188,12 +190,14 @@ int qx_debug_index_maps(const qx_lattice_t* lat, int32_t* lex_of_eo, int32_t* nb
 /* Bytes of a packed gauge field of the given precision and link storage. */
 int qx_gauge_bytes(const qx_lattice_t* lat, int prec, int recon, size_t* bytes);
 
-/* Pack the canonical complex128 [4][V][3][3] gauge field U_canon (device) into
+/* SU(N) gauge field, N = 3 (Sec. 4; one matrix per link, Sec. 1).
+   Pack the canonical complex128 [4][V][3][3] gauge field U_canon (device) into
    `packed` (device, qx_gauge_bytes long, owned by the caller and borrowed by
    the handle, which must not outlive it).  The staggered phase eta and the
    boundary sign are folded into the packed links.  With QX_RECON_12 the call
-   synchronises the stream and checks that every link satisfies
-   row2 = conj(row0 x row1) to 1e-10 (returns QX_ENOTUNITARY otherwise). */
+   synchronises the stream and checks that every link is in SU(3): rows 0 and
+   1 orthonormal and row2 = conj(row0 x row1), each to 1e-10, every element
+   finite (returns QX_ENOTUNITARY otherwise). */
 int qx_gauge_load(const qx_lattice_t* lat, const void* U_canon, int prec, int recon, void* packed,
                   hipStream_t stream, qx_gauge_t** out);
 int qx_gauge_destroy(qx_gauge_t* g);
@@ -211,14 +215,18 @@ int qx_field_unpack(const qx_lattice_t* lat, int nrhs, int prec, const void* pac
 
 /* ---------------------------------------------------------- operators */
 
-/* out = D in, from parity 1 - out_parity to parity out_parity, with the factor
+/* The staggered Dirac operator on SU(N) links (Sec. 4), half of it: the
+   hops from one parity to the other.
+   out = D in, from parity 1 - out_parity to parity out_parity, with the factor
    1/2, for nrhs sources at once (each link is loaded once per site and applied
    to every source).  in/out are packed fields of the gauge handle's precision;
    they must not alias. */
 int qx_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const void* in, void* out,
               hipStream_t stream);
 
-/* out = (m_s^2 - D_eo D_oe) in for each source s on even sites; masses is a
+/* The even-site operator of the conjugate-gradient solver of the staggered
+   Dirac matrix (Sec. 4): A = m^2 - D_eo D_oe, Hermitian positive definite.
+   out = (m_s^2 - D_eo D_oe) in for each source s on even sites; masses is a
    host array of nrhs values; tmp_odd is a packed odd field of nrhs sources
    used as scratch.  Buffers must not alias. */
 int qx_apply_A(const qx_gauge_t* g, int nrhs, const double* masses, const void* in, void* out,
@@ -230,7 +238,11 @@ int qx_apply_A(const qx_gauge_t* g, int nrhs, const double* masses, const void* 
 int qx_cg_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params, int nrhs,
                           size_t* bytes);
 
-/* Solve (m_s^2 - D_eo D_oe) x_s = b_s for s < nrhs, every source with its own
+/* The conjugate-gradient solve of the staggered Dirac matrix in single and
+   double precision (Sec. 4): plain FP64 CG, or FP32 inner iterations with
+   FP64 reliable updates (this library's reading of the single-precision
+   solver at a double-precision residual).
+   Solve (m_s^2 - D_eo D_oe) x_s = b_s for s < nrhs, every source with its own
    CG recurrence (no block Krylov).  g64: FP64 gauge handle (reliable updates
    and the final residual); glo: the inner-precision handle for
    QX_CG_MIXED_F32 (FP32 links, 18 or 12 reals, or FP16 links: the inner
@@ -263,7 +275,9 @@ typedef struct {
 int qx_batch_workspace_bytes(int nsys, const qx_system_t* systems, const qx_cg_params_t* params,
                              size_t* bytes);
 
-/* Plan a batch: every system (any mix of lattice sizes) is solved by one set
+/* Many solves of the conjugate-gradient solver (Sec. 4) at once (this
+   library's batching of systems and sources; the paper measures one right-hand
+   side).  Plan a batch: every system (any mix of lattice sizes) is solved by one set
    of launches per CG step that covers all systems, converged sources are
    masked out, and the launch sequence of a chunk of iterations is captured
    once into a HIP graph that qx_batch_solve replays.  ws must stay valid and
@@ -288,6 +302,52 @@ int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream);
 int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps, int* order,
                   hipStream_t stream);
 
+/* Set the launch shape of a batch's solver kernels (as qx_batch_tune would
+   after finding it), e.g. to repeat a tuned solve or a measurement under the
+   same shape.  Synchronises the stream.  QX_EINVAL for a shape the batch
+   cannot launch or the persistent engine. */
+int qx_batch_set_launch(qx_batch_t* batch, int nbt, int lps, int order, hipStream_t stream);
+
+/* Pass kinds of the solver's launches (qx_batch_profile): the p update
+   p = r + beta p, the half-Dslash D_oe (t = D_oe p, with whatever the engine
+   fuses into it), the half-Dslash D_eo with the A epilogue and the <p, A p>
+   partial sums, the x/r update with the |r|^2 partial sums, the finalize
+   kernels of alpha and beta, and every launch of a reliable update. */
+enum {
+  QX_PASS_P = 0,
+  QX_PASS_DOE = 1,
+  QX_PASS_DEO = 2,
+  QX_PASS_XR = 3,
+  QX_PASS_FINALIZE = 4,
+  QX_PASS_UPDATE = 5,
+  QX_NPASS = 6
+};
+
+/* Event timing of one pass kind: launches, those that had work (the host saw
+   at least one source in the pass's phase when it enqueued them), the sum over
+   those of the number of such sources, and the summed event-to-event
+   durations (ms) of all and of the working launches. */
+typedef struct {
+  int launches;
+  int active_launches;
+  long long source_launches;
+  double ms;
+  double active_ms;
+} qx_pass_stats_t;
+
+/* Measurement of a batch's solve, pass by pass (for benchmarks and
+   profilers): runs the start of the solve and `nchunks` (1..64) chunks of its
+   inner iterations with the launch sequence qx_batch_solve replays, but
+   enqueued eagerly, with a HIP event recorded on the stream before and after
+   every launch, and the host reading the source states before each iteration
+   and each reliable-update slot to count the sources it serves.  passes: host
+   array of QX_NPASS entries (indexed by QX_PASS_*); stats (nullable): the
+   states after the last chunk (seconds = 0).  The systems' x are not written;
+   synchronises the stream.  QX_EINVAL for the persistent engine or a bad
+   argument. */
+int qx_batch_profile(qx_batch_t* batch, int nchunks, qx_pass_stats_t* passes,
+                     qx_cg_stats_t* stats, hipStream_t stream);
+
 /* As qx_batch_solve without any host synchronisation (for callers that keep
    enqueueing dependent work): enqueues the start of the solve, exactly
    `nchunks` (>= 1) chunks of inner-iteration slots with their reliable-update
@@ -310,7 +370,8 @@ int qx_batch_destroy(qx_batch_t* batch);
 
 /* -------------------------------------------------------------- force */
 
-/* Link gradient of a real function L of the solution x = A^{-1} b, in the
+/* Fermion force for hybrid Monte Carlo (Sec. 4): the backward of the solve.
+   Link gradient of a real function L of the solution x = A^{-1} b, in the
    PyTorch convention for complex tensors (G = dL/dRe U + i dL/dIm U):
    given x and lam = A^{-1} (dL/dRe x + i dL/dIm x) (packed FP64 even fields,
    nrhs sources, summed over sources), with y = D_oe x, nu = D_oe lam,
@@ -326,7 +387,9 @@ int qx_force_from_fields(const qx_gauge_t* g64, int nrhs, const void* x_packed,
 int qx_force_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* params, int nrhs,
                              size_t* bytes);
 
-/* Action S = sum_s phi_s^dag A^{-1} phi_s and its link gradient G (as in
+/* Fermion force for hybrid Monte Carlo (Sec. 4): the pseudofermion action
+   and its link gradient.
+   Action S = sum_s phi_s^dag A^{-1} phi_s and its link gradient G (as in
    qx_force_from_fields with lam = x): one solve (params as for qx_cg_solve,
    mass shared by all sources), one extra half-Dslash and one outer-product
    pass.  phi: canonical [nrhs][V/2][3]; x_out (nullable): canonical solution.
@@ -334,6 +397,18 @@ int qx_force_workspace_bytes(const qx_lattice_t* lat, const qx_cg_params_t* para
 int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_cg_params_t* params,
              int nrhs, double mass, const void* phi, void* grad_U, double* S_out, void* x_out,
              void* ws, size_t ws_bytes, qx_cg_stats_t* stats, hipStream_t stream);
+
+/* Backward of the action S = sum_s phi_s^dag A^{-1} phi_s (fermion force, HMC,
+   Sec. 4) for a real upstream gradient gS = dL/dS: grad_U = gS * G with G the
+   link gradient qx_force returned (grad_U_S), and
+   grad_phi = dL/dRe phi + i dL/dIm phi = 2 gS x (A is Hermitian, so
+   dS/dphi = 2 A^{-1} phi = 2 x with x the solution qx_force returned).
+   Either output may be NULL (its input is then not read); an output may alias
+   its input.  Layouts: G, grad_U canonical complex128 [4][V][3][3]; x, grad_phi
+   canonical [nrhs][V/2][3] (device).  Asynchronous on the stream; QX_EINVAL
+   for a NULL input an output needs or nrhs < 1. */
+int qx_action_backward(const qx_lattice_t* lat, int nrhs, double gS, const void* grad_U_S,
+                       const void* x, void* grad_U, void* grad_phi, hipStream_t stream);
 
 /* su(3) force along the generators T_a = lambda_a / 2 (Gell-Mann matrices)
    for the left variation U -> exp(i e T_a) U: F^a = Re[i tr(T_a U G^dag)].

@@ -59,6 +59,8 @@ _D = ctypes.c_double
 
 def _declare(L):
     L.oracle_threads.argtypes = []
+    L.oracle_set_threads.argtypes = [_I]
+    L.oracle_set_threads.restype = None
     L.oracle_index_maps.argtypes = [_P, _P, _P]
     L.oracle_dslash_full.argtypes = [_P, _I, _P, _P, _P]
     L.oracle_dslash_eo.argtypes = [_P, _I, _P, _I, _P, _P]
@@ -98,6 +100,11 @@ def volume(dims) -> int:
 def threads() -> int:
     """OpenMP threads of the oracle's parallel loops."""
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n threads from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 def index_maps(dims):

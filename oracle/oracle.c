@@ -107,14 +107,17 @@ static int dims_ok(const int L[4]) {
   return 1;
 }
 
+/* Threads an OpenMP loop of the oracle runs on, and a way to change them
+   (n >= 1; the timing of the CPU baseline on one core). */
+int oracle_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) { omp_set_num_threads(n >= 1 ? n : 1); }
+
 /*
  * Even-odd index maps, for the bit-exact check of the device geometry.
  * eo = parity * V/2 + (lex >> 1).  lex_of_eo[eo] is the lexicographic site;
  * nbr_eo[8*eo + k] is the eo index of x + mu (k = mu) and x - mu (k = 4 + mu)
  * with periodic wrap.
  */
-/* Threads an OpenMP loop of the oracle runs on. */
-int oracle_threads(void) { return omp_get_max_threads(); }
 
 int oracle_index_maps(const int L[4], int32_t* lex_of_eo, int32_t* nbr_eo) {
   if (!dims_ok(L)) return ORACLE_EINVAL;

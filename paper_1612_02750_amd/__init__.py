@@ -53,6 +53,15 @@ class _Stats(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class _PassStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int), ("active_launches", ctypes.c_int),
+                ("source_launches", ctypes.c_longlong), ("ms", ctypes.c_double),
+                ("active_ms", ctypes.c_double)]
+
+
+PASS_NAMES = ("p", "doe", "deo", "xr", "finalize", "update")
+
+
 class _System(ctypes.Structure):
     _fields_ = [("g64", ctypes.c_void_p), ("glo", ctypes.c_void_p), ("nrhs", ctypes.c_int),
                 ("masses", ctypes.POINTER(ctypes.c_double)), ("b", ctypes.c_void_p),
@@ -110,6 +119,9 @@ def load():
         "qx_force_workspace_bytes": ([_P, _P, _I, _P], _I),
         "qx_force": ([_P, _P, _P, _I, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P, _P], _I),
         "qx_force_su3": ([_P, _P, _P, _P, _P], _I),
+        "qx_action_backward": ([_P, _I, ctypes.c_double, _P, _P, _P, _P, _P], _I),
+        "qx_batch_profile": ([_P, _I, _P, _P, _P], _I),
+        "qx_batch_set_launch": ([_P, _I, _I, _I, _P], _I),
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
         "qx_gauge_action": ([_P, _P, ctypes.c_double, _P, _SZ, _P, _P], _I),
         "qx_gauge_force": ([_P, _P, ctypes.c_double, _P, _I, _P], _I),
@@ -410,6 +422,21 @@ class Batch:
                                     ctypes.byref(o), _stream(stream)))
         return n.value, l.value, o.value
 
+    def set_launch(self, nbt: int, lps: int, order: int, stream=None):
+        """Solve under this launch shape from now on (as a tuner result)."""
+        _check(load().qx_batch_set_launch(self._h, int(nbt), int(lps), int(order), _stream(stream)))
+
+    def profile(self, nchunks: int = 2, stream=None):
+        """Event timing of nchunks chunks of this batch's solve, pass by pass:
+        {pass name: {launches, active_launches, source_launches, ms, active_ms}}
+        and the statistics after the last chunk."""
+        ps = (_PassStats * len(PASS_NAMES))()
+        st = (_Stats * self.nsrc)()
+        _check(load().qx_batch_profile(self._h, int(nchunks), ps, st, _stream(stream)))
+        out = {n: {f: getattr(ps[i], f) for f, _ in _PassStats._fields_}
+               for i, n in enumerate(PASS_NAMES)}
+        return out, _stats(st, self.nsrc)
+
     def chunk(self) -> int:
         c = ctypes.c_int()
         _check(load().qx_batch_info(self._h, None, ctypes.byref(c)))
@@ -460,6 +487,18 @@ def force(g64: Gauge, phi, mass: float, glo: Optional[Gauge] = None, tol=1e-10,
                       float(mass), _ptr(phi), _ptr(G), ctypes.byref(S), _ptr(x), _ptr(ws),
                       ws.numel(), st, _stream(stream)))
     return S.value, G, x, _stats(st, nrhs)
+
+
+def action_backward(lat: Lattice, gS: float, G, x, need_U=True, need_phi=True, stream=None):
+    """Backward of S = sum_s phi_s^dag A^-1 phi_s for the upstream gradient gS:
+    (gS * G, 2 gS x), either None when not needed (computed by the library)."""
+    torch = _torch()
+    gU = torch.empty_like(G) if need_U else None
+    gphi = torch.empty_like(x) if need_phi else None
+    _check(load().qx_action_backward(lat._h, x.shape[0], float(gS), _ptr(G), _ptr(x),
+                                     _ptr(gU) if need_U else None,
+                                     _ptr(gphi) if need_phi else None, _stream(stream)))
+    return gU, gphi
 
 
 # ------------------------------------------------------- molecular dynamics

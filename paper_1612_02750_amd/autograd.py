@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import torch
 
-from . import CG_FP64, CG_MIXED_F32, Gauge, cg, force, force_from_fields
+from . import CG_FP64, CG_MIXED_F32, Gauge, action_backward, cg, force, force_from_fields
 
 
 def _gauges(lat, U, mixed, recon):
@@ -48,14 +48,16 @@ class StaggeredAction(torch.autograd.Function):
         g64, glo = _gauges(lat, U, mixed, recon)
         mode = CG_MIXED_F32 if mixed else CG_FP64
         S, G, x, _ = force(g64, phi.detach().contiguous(), float(mass), glo, tol=tol, mode=mode)
+        ctx.lat = lat
         ctx.save_for_backward(G, x)
         return torch.tensor(S, dtype=torch.float64, device=U.device)
 
     @staticmethod
     def backward(ctx, gS):
         G, x = ctx.saved_tensors
-        gU = G * gS if ctx.needs_input_grad[0] else None
-        gphi = 2.0 * x * gS if ctx.needs_input_grad[1] else None
+        # gS * G and 2 gS x (dS/dphi = 2 A^-1 phi) are formed by the library
+        gU, gphi = action_backward(ctx.lat, float(gS), G, x, ctx.needs_input_grad[0],
+                                   ctx.needs_input_grad[1])
         return gU, gphi, None, None, None, None, None
 
 

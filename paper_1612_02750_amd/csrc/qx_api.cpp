@@ -261,7 +261,8 @@ extern "C" int qx_gauge_load(const qx_lattice_t* lat, const void* U_canon, int p
     memcpy(&err, &bits, sizeof err);
     if (!(err <= 1e-10))
       return fail(QX_ENOTUNITARY,
-                  "qx_gauge_load: 12-real links need SU(3) links; max |row2 - conj(row0 x row1)| = %g",
+                  "qx_gauge_load: 12-real links need SU(3) links; largest deviation of rows 0-1 "
+                  "from orthonormality or of row 2 from conj(row0 x row1) = %g",
                   err);
   }
   qx_gauge* g = new (std::nothrow) qx_gauge;
@@ -896,6 +897,95 @@ static int replan(qx_batch* B, hipStream_t s) {
   return rc;
 }
 
+extern "C" int qx_batch_set_launch(qx_batch_t* batch, int nbt, int lps, int order,
+                                   hipStream_t stream) {
+  if (!batch) return fail(QX_EINVAL, "qx_batch_set_launch: NULL batch");
+  qx_batch* B = batch;
+  if (B->persistent) return fail(QX_EINVAL, "qx_batch_set_launch: not for the persistent engine");
+  int nb = 1;
+  for (const auto& sp : B->specs) nb = std::max(nb, sp.nrhs);
+  const LaunchShape sh{nbt, lps, order};
+  if (!nbt_lps_instantiated(nbt, lps) || !shape_ok(sh, nb, cplx_bytes(lo_prec(&B->params))))
+    return fail(QX_EINVAL, "qx_batch_set_launch: shape (%d, %d, %d) not available", nbt, lps, order);
+  B->forced = true;
+  B->forced_shape = sh;
+  return replan(B, stream);
+}
+
+static_assert(PASS_P == QX_PASS_P && PASS_DOE == QX_PASS_DOE && PASS_DEO == QX_PASS_DEO &&
+                  PASS_XR == QX_PASS_XR && PASS_FINALIZE == QX_PASS_FINALIZE &&
+                  PASS_UPDATE == QX_PASS_UPDATE && NPASS == QX_NPASS,
+              "pass kinds");
+
+extern "C" int qx_batch_profile(qx_batch_t* batch, int nchunks, qx_pass_stats_t* passes,
+                                qx_cg_stats_t* stats, hipStream_t stream) {
+  if (!batch || !passes || nchunks < 1 || nchunks > 64)
+    return fail(QX_EINVAL, "qx_batch_profile: bad argument");
+  qx_batch* B = batch;
+  if (B->persistent) return fail(QX_EINVAL, "qx_batch_profile: not for the persistent engine");
+  const int n = B->cfg.nsrc_total;
+  // the number of sources in the given phase, read from the device states
+  auto count = [&](int phase, int* out) -> int {
+    QX_HIP(hipMemcpyAsync(B->h_st, B->cfg.d_st, sizeof(SrcState) * n, hipMemcpyDeviceToHost, stream),
+           "qx_batch_profile: state readback");
+    QX_HIP(hipStreamSynchronize(stream), "qx_batch_profile: state readback");
+    int c = 0;
+    for (int k = 0; k < n; ++k) c += B->h_st[k].phase == phase;
+    *out = c;
+    return QX_OK;
+  };
+  int rc = enqueue_start(B, stream);
+  if (rc) return rc;
+  PassProf prof;
+  B->cfg.prof = &prof;
+  // the launch sequence of enqueue_chunk, enqueued eagerly, the host reading
+  // the states before each iteration and update to tag the launches
+  for (int c = 0; c < nchunks && !rc; ++c)
+    for (int i = 0; i < B->chunk && !rc; ++i) {
+      rc = count(PH_RUN, &prof.nrun);
+      if (rc) break;
+      if (engine_iteration(B->cfg, i & 1, stream) != hipSuccess) {
+        rc = fail(QX_EHIP, "qx_batch_profile: iteration");
+        break;
+      }
+      if ((i + 1) % B->ru_every == 0 || i + 1 == B->chunk) {
+        rc = count(PH_RU, &prof.nrun);
+        if (!rc && engine_reliable_update(B->cfg, i + 1 == B->chunk, stream) != hipSuccess)
+          rc = fail(QX_EHIP, "qx_batch_profile: reliable update");
+      }
+    }
+  B->cfg.prof = nullptr;
+  if (rc) return rc;
+  if (prof.err != hipSuccess) return hip_fail(prof.err, "qx_batch_profile: events");
+  QX_HIP(hipStreamSynchronize(stream), "qx_batch_profile: chunks");
+  for (int k = 0; k < QX_NPASS; ++k) passes[k] = qx_pass_stats_t{};
+  for (const PassProf::Rec& r : prof.recs) {
+    float ms = 0.f;
+    QX_HIP(hipEventElapsedTime(&ms, r.e0, r.e1), "qx_batch_profile: elapsed");
+    qx_pass_stats_t& q = passes[r.kind];
+    q.launches += 1;
+    q.ms += ms;
+    if (r.nrun > 0) {
+      q.active_launches += 1;
+      q.active_ms += ms;
+      q.source_launches += r.nrun;
+    }
+  }
+  QX_HIP(hipMemcpyAsync(B->h_st, B->cfg.d_st, sizeof(SrcState) * n, hipMemcpyDeviceToHost, stream),
+         "qx_batch_profile: state readback");
+  QX_HIP(hipStreamSynchronize(stream), "qx_batch_profile: state readback");
+  if (stats)
+    for (int k = 0; k < n; ++k) {
+      const SrcState& q = B->h_st[k];
+      stats[k].status = q.status;
+      stats[k].iters = q.iters;
+      stats[k].reliable_updates = q.updates;
+      stats[k].true_rel_residual = q.relres;
+      stats[k].seconds = 0.0;
+    }
+  return QX_OK;
+}
+
 extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps, int* order,
                              hipStream_t stream) {
   if (!batch || nchunks < 1 || nchunks > 64)
@@ -1104,6 +1194,20 @@ extern "C" int qx_force(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_c
   QX_HIP(hipStreamSynchronize(stream), "qx_force");
   if (S_out) *S_out = S;
   return solve_rc;
+}
+
+extern "C" int qx_action_backward(const qx_lattice_t* lat, int nrhs, double gS, const void* grad_U_S,
+                                  const void* x, void* grad_U, void* grad_phi, hipStream_t stream) {
+  if (!lat || nrhs < 1 || (grad_U && !grad_U_S) || (grad_phi && !x))
+    return fail(QX_EINVAL, "qx_action_backward: bad argument");
+  const Geo& g = lat->geo;
+  if (grad_U)
+    QX_HIP(launch_scale_c128(grad_U_S, gS, (size_t)4 * 2 * g.hv * 9, grad_U, stream),
+           "qx_action_backward: link gradient");
+  if (grad_phi)
+    QX_HIP(launch_scale_c128(x, 2.0 * gS, (size_t)nrhs * g.hv * 3, grad_phi, stream),
+           "qx_action_backward: source gradient");
+  return QX_OK;
 }
 
 extern "C" int qx_force_su3(const qx_lattice_t* lat, const void* U_canon, const void* grad_U,

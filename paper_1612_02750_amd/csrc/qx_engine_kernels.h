@@ -375,8 +375,9 @@ __global__ void __launch_bounds__(256) k_finalize(const SysDesc* __restrict__ sy
 }
 
 hipError_t finalize(const EngineCfg& c, int kind, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(256), 0, s, c.d_sys, c.nsys, c.d_st,
-                     kind);
+  QX_TIMED(c, kind == FIN_RU || kind == FIN_COMMIT ? PASS_UPDATE : PASS_FINALIZE, s,
+           hipLaunchKernelGGL(k_finalize, dim3(c.nsrc_total), dim3(256), 0, s, c.d_sys, c.nsys,
+                              c.d_st, kind));
   return hipGetLastError();
 }
 
@@ -1249,10 +1250,13 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
     const int rin = parity ? 6 : 1, rout = parity ? 1 : 6;
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-      hipLaunchKernelGGL((k_f2_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         c.d_st, c.d_st1, pin, pout, rin, rout, c.shape.xcd);
-      hipLaunchKernelGGL((k_f2_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         c.d_st1, c.d_st, pout, rout, c.shape.xcd);
+      QX_TIMED(c, PASS_DOE, s,
+               hipLaunchKernelGGL((k_f2_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
+                                  c.d_sys, c.nsys, c.d_st, c.d_st1, pin, pout, rin, rout,
+                                  c.shape.xcd));
+      QX_TIMED(c, PASS_DEO, s,
+               hipLaunchKernelGGL((k_f2_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
+                                  c.d_sys, c.nsys, c.d_st1, c.d_st, pout, rout, c.shape.xcd));
       return hipGetLastError();
     });
   }
@@ -1260,26 +1264,35 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     // p alternates between slots 2 and 5; the states between the two slots
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
     return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-      hipLaunchKernelGGL((k_fiter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys,
-                         c.nsys, c.d_st, c.d_st1, pin, pout, c.shape.xcd);
-      hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                         c.d_st1, pout, c.shape.xcd);
-      hipLaunchKernelGGL(k_fiter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,
-                         pout, c.shape.xcd);
+      QX_TIMED(c, PASS_DOE, s,
+               hipLaunchKernelGGL((k_fiter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
+                                  c.d_sys, c.nsys, c.d_st, c.d_st1, pin, pout, c.shape.xcd));
+      QX_TIMED(c, PASS_DEO, s,
+               hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
+                                  c.d_sys, c.nsys, c.d_st1, pout, c.shape.xcd));
+      QX_TIMED(c, PASS_XR, s,
+               hipLaunchKernelGGL(k_fiter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1,
+                                  c.d_st, pout, c.shape.xcd));
       return hipGetLastError();
     });
   }
   hipError_t e = with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
-    hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                       c.d_st, c.shape.xcd);
-    hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s, c.d_sys, c.nsys,
-                       c.d_st, 2, c.shape.xcd);
+    QX_TIMED(c, PASS_P, s,
+             hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                                c.shape.xcd));
+    QX_TIMED(c, PASS_DOE, s,
+             hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
+                                c.d_sys, c.nsys, c.d_st, c.shape.xcd));
+    QX_TIMED(c, PASS_DEO, s,
+             hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
+                                c.d_sys, c.nsys, c.d_st, 2, c.shape.xcd));
     return hipGetLastError();
   });
   if (e == hipSuccess) e = finalize(c, FIN_ALPHA, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st, c.shape.xcd);
+    QX_TIMED(c, PASS_XR, s,
+             hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                                c.shape.xcd));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = finalize(c, FIN_BETA, s);
@@ -1297,25 +1310,29 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   const bool handoff = c.fused && c.two && !last;
   SrcState* copy = c.fused && !handoff ? c.d_st1 : nullptr;
   hipError_t e = with_nbt(c.shape.nbt, [&]<int NBT>() {
-    hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
-    hipLaunchKernelGGL((k_ru_residual<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
-                       c.d_st, c.shape.xcd, copy, handoff ? 1 : 0);
+    QX_TIMED(c, PASS_UPDATE, s,
+             hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
+                                c.d_st, c.shape.xcd));
+    QX_TIMED(c, PASS_UPDATE, s,
+             hipLaunchKernelGGL((k_ru_residual<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys,
+                                c.nsys, c.d_st, c.shape.xcd, copy, handoff ? 1 : 0));
     return hipGetLastError();
   });
   if (handoff) return e;
   if (c.fused) {
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_fru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st1, c.d_st,
-                         c.shape.xcd);
+      QX_TIMED(c, PASS_UPDATE, s,
+               hipLaunchKernelGGL(k_fru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys,
+                                  c.d_st1, c.d_st, c.shape.xcd));
       e = hipGetLastError();
     }
     return e;
   }
   if (e == hipSuccess) e = finalize(c, FIN_RU, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_ru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                       c.shape.xcd);
+    QX_TIMED(c, PASS_UPDATE, s,
+             hipLaunchKernelGGL(k_ru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                                c.shape.xcd));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = finalize(c, FIN_COMMIT, s);

@@ -67,15 +67,30 @@ __global__ void __launch_bounds__(256) k_pack_gauge(Geo g, const cplx<double>* _
       *reinterpret_cast<cplx<R>*>(o + link_elem_offset<R, E>(e, g.hv, cb)) = {
           to_store<R>(sg * v[e].re), to_store<R>(sg * v[e].im)};
     if constexpr (RECON == 12) {
-      // row 2 against conj(row0 x row1)
+      // U in SU(3) <=> rows 0 and 1 orthonormal and row 2 = conj(row0 x row1):
+      // the largest deviation from the three conditions, +inf when any of the
+      // 18 reals is not finite (fmax would drop a NaN)
+      bool fin = true;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) fin = fin && isfinite(v[e].re) && isfinite(v[e].im);
       const cplx<double> a0 = cmul(v[1], v[5]), b0 = cmul(v[2], v[4]);
       const cplx<double> a1 = cmul(v[2], v[3]), b1 = cmul(v[0], v[5]);
       const cplx<double> a2 = cmul(v[0], v[4]), b2 = cmul(v[1], v[3]);
       const double d0 = fabs(v[6].re - (a0.re - b0.re)) + fabs(v[6].im + (a0.im - b0.im));
       const double d1 = fabs(v[7].re - (a1.re - b1.re)) + fabs(v[7].im + (a1.im - b1.im));
       const double d2 = fabs(v[8].re - (a2.re - b2.re)) + fabs(v[8].im + (a2.im - b2.im));
-      err = fmax(fmax(d0, d1), d2);
-      if (err != err) err = __builtin_inf();
+      double n0 = 0.0, n1 = 0.0, o_re = 0.0, o_im = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        n0 += v[c].re * v[c].re + v[c].im * v[c].im;
+        n1 += v[3 + c].re * v[3 + c].re + v[3 + c].im * v[3 + c].im;
+        // row0 . conj(row1)
+        o_re += v[c].re * v[3 + c].re + v[c].im * v[3 + c].im;
+        o_im += v[c].im * v[3 + c].re - v[c].re * v[3 + c].im;
+      }
+      err = fmax(fmax(fmax(d0, d1), d2),
+                 fmax(fmax(fabs(n0 - 1.0), fabs(n1 - 1.0)), fabs(o_re) + fabs(o_im)));
+      if (!fin) err = __builtin_inf();
     }
   }
   if constexpr (RECON == 12) {
@@ -491,6 +506,25 @@ hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials
   hipLaunchKernelGGL(k_redot_partial, dim3(nblk), dim3(256), 0, s, (const cplx<double>*)a,
                      (const cplx<double>*)b, n, partials);
   hipLaunchKernelGGL(k_redot_final, dim3(1), dim3(256), 0, s, partials, nblk, out);
+  return hipGetLastError();
+}
+
+// out = s * in over n complex128 values (grid-stride).
+__global__ void __launch_bounds__(256) k_scale_c128(size_t n, double sc,
+                                                    const cplx<double>* __restrict__ in,
+                                                    cplx<double>* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const cplx<double> v = in[i];
+    out[i] = {sc * v.re, sc * v.im};
+  }
+}
+
+hipError_t launch_scale_c128(const void* in, double sc, size_t n, void* out, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<size_t>(grid_for(n, 256), 65536);
+  hipLaunchKernelGGL(k_scale_c128, dim3(grid), dim3(256), 0, s, n, sc, (const cplx<double>*)in,
+                     (cplx<double>*)out);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 // Host-callable launchers of the gfx950 kernels (internal to libqx.so).
 #pragma once
 
+#include <vector>
+
 #include "qx_internal.h"
 
 namespace qx {
@@ -67,6 +69,56 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
 
 // ------------------------------------------------------------------ engine
 
+// Pass kinds of the solver launches (the QX_PASS_* values of qx.h).
+enum PassKind : int { PASS_P = 0, PASS_DOE = 1, PASS_DEO = 2, PASS_XR = 3, PASS_FINALIZE = 4,
+                      PASS_UPDATE = 5, NPASS = 6 };
+
+// Event timing of the solver's launches (measurement only): while an engine
+// configuration carries one, every launch of its iteration and update
+// sequences is bracketed by two HIP events on the launch's stream, tagged with
+// its pass kind and with the number of sources the host expects it to serve
+// (nrun, set before the launches are enqueued).  Events come from a pool that
+// lives as long as the object.
+struct PassProf {
+  struct Rec {
+    int kind, nrun;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  int nrun = 0;
+  hipError_t err = hipSuccess;
+
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) {
+        err = r;
+        return nullptr;
+      }
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int kind, hipStream_t s) {
+    Rec r{kind, nrun, next(), next()};
+    if (!r.e0 || !r.e1) return;
+    const hipError_t e = hipEventRecord(r.e0, s);
+    if (e != hipSuccess) err = e;
+    recs.push_back(r);
+  }
+  void end(hipStream_t s) {
+    if (recs.empty()) return;
+    const hipError_t e = hipEventRecord(recs.back().e1, s);
+    if (e != hipSuccess) err = e;
+  }
+  ~PassProf() {
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
+};
+
 // One solver launch configuration: the systems (device table), their source
 // states, the inner precision and link storage, the FP64 link storage, the
 // number of sources each thread handles (nb), and the launch shape.
@@ -81,7 +133,16 @@ struct EngineCfg {
   SrcState* d_st1 = nullptr;  // second slot of the fused launch sequence
   bool fused = false;         // three launches per iteration (redundant reductions), see the engine
   bool two = false;           // with fused: two launches per iteration (x/r step folded into D_oe)
+  PassProf* prof = nullptr;   // event timing of every launch (measurement only), or null
 };
+
+// Launch statement `launch` bracketed by the pass timer of c (when set).
+#define QX_TIMED(c, kind, s, launch)       \
+  do {                                     \
+    if ((c).prof) (c).prof->begin(kind, s); \
+    launch;                                \
+    if ((c).prof) (c).prof->end(s);        \
+  } while (0)
 
 bool engine_supported(const EngineCfg& c);
 hipError_t engine_init(const EngineCfg& c, int zero_xhi, hipStream_t s);
@@ -102,6 +163,8 @@ hipError_t engine_persistent(const EngineCfg& c, int iters, GridSync* gs, int gr
 hipError_t launch_force(const Geo& g, int nsrc, const void* x, const void* lam, const void* y,
                         const void* nu, void* G, hipStream_t s);
 hipError_t launch_su3_force(const Geo& g, const void* U, const void* G, double* F, hipStream_t s);
+// out = sc * in over n complex128 values.
+hipError_t launch_scale_c128(const void* in, double sc, size_t n, void* out, hipStream_t s);
 // out = sum_i Re(conj(a_i) b_i) over n complex128 values (two deterministic passes).
 hipError_t launch_redot(const void* a, const void* b, size_t n, double* partials, int nblk,
                         double* out, hipStream_t s);
