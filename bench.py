@@ -433,7 +433,7 @@ def multi_rhs_extras(torch, qx, synth, h):
     nsrc = bd.shape[0]
     # the step's links again (the FP16 handle is packed from the canonical field)
     g16 = qx.Gauge(lat, torch.from_numpy(synth.haar_gauge(lat.dims, 0)).cuda(), "f16", 12)
-    g16.set_launch(nsrc, *g32.launch(nsrc))
+    g16.tune(nsrc)
     g16.set_launch(1, *g32.tune(1))
     out = {"workload": "32^4 Haar links, 12 Gaussian sources, m=0.02, tol 1e-10"}
     x16 = torch.empty_like(bd)

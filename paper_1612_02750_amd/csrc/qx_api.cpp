@@ -123,9 +123,11 @@ bool tune_read_file_locked(const char* path) {
     if (j == std::string::npos) break;
     const std::string key = s.substr(i + 1, j - i - 1);
     int nbt = 0, lps = 0, x = 0;
+    // the wide shapes only for FP32 one-hop links (keys ":p1:" without ":r36:")
+    const bool wide = key.find(":p1:") != std::string::npos && key.find(":r36:") == std::string::npos;
     if (sscanf(s.c_str() + j + 1, " : [ %d , %d , %d ]", &nbt, &lps, &x) == 3 &&
-        nbt_lps_instantiated(nbt, lps))
-      g_tune[key] = LaunchShape{nbt, lps, x < 0 ? 0 : x > 3 ? 3 : x};
+        nbt_lps_instantiated(nbt, lps, wide))
+      g_tune[key] = LaunchShape{nbt, lps, x < 0 ? 0 : x > kMaxOrder ? kMaxOrder : x};
     i = j + 1;
   }
   return true;
@@ -523,7 +525,9 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   // (1, 4, 1).  (At 32^4 the tuned order stays: FP64 with twelve sources
   // was 8 % slower under order 1 than under the tuned order 0.)
   if (sh.xcd == 0 && max_nblk <= kFuseMaxBlocks) sh.xcd = 1;
-  if (!shape_ok(sh, nb, cplx_bytes(prec_lo)) || !nbt_lps_instantiated(sh.nbt, sh.lps)) {
+  if (!shape_ok(sh, nb, cplx_bytes(prec_lo)) ||
+      !nbt_lps_instantiated(sh.nbt, sh.lps,
+                            wide_compiled(prec_lo, s0.glo->recon) && s0.glo->prec != QX_PREC_F16)) {
     // the first default that takes nb sources in one block
     const LaunchShape cands[4] = {{1, 2, 1}, {2, 2, 1}, {4, 2, 1}, {4, 1, 1}};
     sh = cands[0];
@@ -539,7 +543,7 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
   // (4, 2, 0) against 1.18 s under the tuned (4, 2, 1); FP64 2.19 s against
   // 2.37 s.  (One source per thread keeps the tuned order: at 32^4 the tuned
   // shapes were within 1-2 % of the best there.)
-  if (max_nblk > kFuseMaxBlocks && sh.nbt > 1) sh.xcd = 0;
+  if (max_nblk > kFuseMaxBlocks && sh.nbt > 1 && sh.xcd < 4) sh.xcd = 0;
   if (B->forced) sh = B->forced_shape;
 
   B->cfg = EngineCfg{};
@@ -554,6 +558,13 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
       return fail(QX_EINVAL, "batch: all systems must use the same link storage");
   }
   B->cfg.nsrc_max = nb;
+  // six or twelve sources per thread are compiled for the launch-per-pass
+  // stencils of FP32 one-hop links only: other paths take at most four
+  const bool fused_planned = p.engine == QX_ENGINE_FUSED || p.engine == QX_ENGINE_FUSED2 ||
+                             (p.engine == QX_ENGINE_AUTO && max_nblk <= kFuseMaxBlocks);
+  const bool wide_ok = wide_compiled(prec_lo, s0.glo->recon) && s0.glo->prec != QX_PREC_F16 &&
+                       !fused_planned && p.engine != QX_ENGINE_PERSISTENT;
+  if (!wide_ok) sh = narrow_shape(sh);
   B->cfg.shape = sh;
   B->cfg.nsys = (int)B->specs.size();
   B->cfg.d_sys = (const SysDesc*)(B->ws + B->layout.sys_off);
@@ -905,7 +916,9 @@ extern "C" int qx_batch_set_launch(qx_batch_t* batch, int nbt, int lps, int orde
   int nb = 1;
   for (const auto& sp : B->specs) nb = std::max(nb, sp.nrhs);
   const LaunchShape sh{nbt, lps, order};
-  if (!nbt_lps_instantiated(nbt, lps) || !shape_ok(sh, nb, cplx_bytes(lo_prec(&B->params))))
+  const size_t csz = cplx_bytes(lo_prec(&B->params));
+  const bool wide = wide_compiled(B->cfg.prec_lo, B->cfg.recon_lo) && !B->cfg.links16;
+  if (!nbt_lps_instantiated(nbt, lps, wide) || !shape_ok(sh, nb, csz))
     return fail(QX_EINVAL, "qx_batch_set_launch: shape (%d, %d, %d) not available", nbt, lps, order);
   B->forced = true;
   B->forced_shape = sh;
@@ -1001,6 +1014,9 @@ extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps,
   int max_nblk = 0;
   for (const auto& d : B->sys) max_nblk = std::max(max_nblk, d.nblk);
   const bool split = max_nblk <= kFuseMaxBlocks;
+  // six or twelve sources per thread only on the launch-per-pass FP32 one-hop path
+  const bool wide =
+      wide_compiled(B->cfg.prec_lo, B->cfg.recon_lo) && !B->cfg.links16 && !B->cfg.fused;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   QX_HIP(hipEventCreate(&e0), "qx_batch_tune: event");
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1029,11 +1045,11 @@ extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps,
   LaunchShape best{};
   float best_ms = 1e30f;
   int rc = QX_OK;
-  for (int nb_t : {1, 2, 4})
+  for (int nb_t : {1, 2, 4, 6, 12})
     for (int l : {1, 2, 4, 8})
-      for (int x = 0; x < 4 && rc != QX_EHIP; ++x) {
+      for (int x = 0; x <= kMaxOrder && rc != QX_EHIP; ++x) {
         const LaunchShape sh{nb_t, l, x};
-        if (!nbt_lps_instantiated(nb_t, l) || !shape_ok(sh, nb, csz)) continue;
+        if (!nbt_lps_instantiated(nb_t, l, wide) || !shape_ok(sh, nb, csz)) continue;
         if ((nb_t > 1 && nb_t > nb) || (split && l == 1)) continue;
         float ms = 0.f;
         rc = time_shape(sh, &ms);
@@ -1244,7 +1260,7 @@ extern "C" int qx_get_launch(const qx_gauge_t* g, int nrhs, int* nbt, int* lps, 
 }
 
 extern "C" int qx_set_launch(const qx_gauge_t* g, int nrhs, int nbt, int lps, int xcd_order) {
-  if (!g || nrhs < 1 || !nbt_lps_instantiated(nbt, lps))
+  if (!g || nrhs < 1 || !nbt_lps_instantiated(nbt, lps, wide_compiled(g->prec, g->recon)))
     return fail(QX_EINVAL, "qx_set_launch: unsupported shape (nbt %d, lps %d)", nbt, lps);
   const LaunchShape sh{nbt, lps, xcd_order};
   // the standalone operators split the sources into passes that fit a block;
@@ -1551,13 +1567,16 @@ extern "C" int qx_tune_dslash(const qx_gauge_t* g, int nrhs, void* scratch, hipS
   QX_HIP(hipMemsetAsync(in, 0, fb, stream), "qx_tune_dslash: clear");
   LaunchShape best{};
   float best_ms = 1e30f;
-  const int nbts[3] = {1, 2, 4}, lpss[4] = {1, 2, 4, 8};
+  const int nbts[5] = {1, 2, 4, 6, 12}, lpss[4] = {1, 2, 4, 8};
+  const size_t csz = cplx_bytes(g->prec);
   for (int nbt : nbts) {
     if (nbt > 1 && nbt > nrhs) continue;
     for (int lps : lpss) {
-      for (int x = 0; x < 4; ++x) {
+      for (int x = 0; x <= kMaxOrder; ++x) {
         const LaunchShape sh{nbt, lps, x};
-        if (!nbt_lps_instantiated(nbt, lps) || !shape_ok(sh, nrhs, cplx_bytes(g->prec))) continue;
+        if (!nbt_lps_instantiated(nbt, lps, wide_compiled(g->prec, g->recon)) ||
+            !shape_ok(sh, nrhs, csz))
+          continue;
         float ms = 0.f;
         const int rc = time_launches("qx_tune_dslash: timing", stream, 20,
                                      [&](hipStream_t s, int r) {

@@ -172,7 +172,27 @@ __host__ __device__ __forceinline__ int divisor_upto(int L, int cap) {
 // uses.  The tiling needs whole blocks per (z, t) plane (Lh * L1 a multiple
 // of 64) and falls back to checkerboard order otherwise.  A bijection of
 // [0, hv / 64) onto itself.
+//
+// Orders 4 and 5 give each of the eight XCDs a slab of the lattice and walk it
+// plane by plane, so that the blocks an XCD runs at the same time work on
+// neighbouring (z, t) planes and the colour vectors those planes share stay in
+// its L2: order 4 cuts z into eight slabs and walks t (slowest), then z, then
+// the blocks of a (z, t) plane; order 5 cuts t and walks z.  With the
+// XCD-contiguous dispatch (logical_block) slab k is the range XCD k runs.  They
+// need whole blocks per (z, t) plane and the cut extent divisible by 8, and
+// fall back to checkerboard order otherwise.  Stencil kernels under orders 4
+// and 5 also store their outputs non-temporally (st_cplx).
 __host__ __device__ __forceinline__ int tile_block(int bl, const Geo& g, int order) {
+  if (order >= 4) {
+    const int cut = order == 4 ? g.L2 : g.L3;
+    if ((g.s2 & 63) || (cut & 7)) return bl;
+    const int P = g.s2 >> 6, w = cut >> 3;
+    const int per = (g.hv >> 6) >> 3;  // blocks of one slab
+    const int k = bl / per, j = bl - k * per;
+    const int a = j / (w * P), b = k * w + (j / P) % w;
+    const int z = order == 4 ? b : a, t = order == 4 ? a : b;
+    return (z + g.L2 * t) * P + j % P;
+  }
   if (order < 2 || (g.s2 & 63)) return bl;
   const int P = g.s2 >> 6;  // blocks per (z, t) plane
   const int tz = divisor_upto(g.L2, order == 2 ? 2 : 4);
@@ -340,12 +360,18 @@ __device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<LS>* __res
 
 // Loader of the input vectors of a stencil: in_j(site, colour) for the
 // sources j of the calling thread, from one packed field.
+//
+// Every loader serves the NBT source slots of a thread: slots past the last
+// source it may read (jmax, uniform) read that source again, so that a
+// stencil can load every slot of a hop unconditionally.
 template <typename R>
 struct FieldIn {
   const cplx<R>* __restrict__ p;  // first source of the thread
   size_t ss, hv;                  // source stride (3 hv), colour stride (hv)
+  int jmax;                       // last readable slot
   __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
-    return ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
+    const int jj = j < jmax ? j : jmax;
+    return ld_cplx<false>(p + jj * ss + c * hv, (unsigned)site);
   }
 };
 
@@ -364,13 +390,29 @@ __device__ __forceinline__ cplx<float> h2_scaled(unsigned w, float sc) {
 struct FieldInH {
   const char* __restrict__ p;  // first source of the thread
   size_t hv;
+  int jmax;  // last readable slot
   __device__ __forceinline__ cplx<float> operator()(int j, int c, int site) const {
+    const int jj = j < jmax ? j : jmax;
     // the three colours of a site read the same record: one load after CSE
     const qx_u32x4 r =
-        reinterpret_cast<const qx_u32x4*>(p + (size_t)j * 16 * hv)[(unsigned)site];
+        reinterpret_cast<const qx_u32x4*>(p + (size_t)jj * 16 * hv)[(unsigned)site];
     return h2_scaled(c == 0 ? r.x : c == 1 ? r.y : r.z, __uint_as_float(r.w));
   }
 };
+
+// *p = v, non-temporally when nt (outputs the next pass reads from far away).
+template <typename R>
+__device__ __forceinline__ void st_cplx(cplx<R>* p, const cplx<R>& v, bool nt) {
+  if (nt) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t.x = v.re;
+    t.y = v.im;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2*>(p));
+  } else {
+    *p = v;
+  }
+}
 
 // Store the colour vector v of site cb into an FP16 source (layout of
 // FieldInH): scale = the largest |re| or |im| of v, pairs = v / scale.
@@ -394,14 +436,18 @@ __device__ __forceinline__ void st_field_h(char* __restrict__ src, int cb,
   reinterpret_cast<qx_u32x4*>(src)[cb] = r;
 }
 
-// acc[j] += hop H applied to in_j, j < NBT (bit j of act).
+// acc[j] += hop H applied to in_j for every slot j < NBT.  The colour vectors
+// of all slots are loaded before any product is formed and no slot is
+// skipped: a per-slot test would put every slot's loads behind its own branch
+// and let a wavefront have only one slot's loads in flight.  Callers mask
+// unused slots when they store.
 // Hops 8..15 (RECON == 36) are the three-hop terms, with the links at lf3/lb3.
 template <int H, typename R, int RECON, int NBT, bool NT, typename In, typename LS>
 __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __restrict__ lf,
                                             const cplx<LS>* __restrict__ lb,
                                             const cplx<LS>* __restrict__ lf3,
                                             const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
-                                            const In& in, unsigned act, cplx<R> (&acc)[NBT][3]) {
+                                            const In& in, cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   constexpr int mu = H & 3;
   constexpr bool fwd = (H & 4) == 0;
@@ -417,43 +463,45 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
     sign = flip ? -e : e;
   }
   const int nb = s.template nbr<H>();
+  cplx<R> v[NBT][3];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[j][c] = in(j, c, nb);
   cplx<R> u[9];
   const cplx<LS>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
   load_link<R, RECON, NT>(u, base + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv, sign);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
-    if (!(act >> j & 1u)) continue;
-    const cplx<R> c0 = in(j, 0, nb), c1 = in(j, 1, nb), c2 = in(j, 2, nb);
     if constexpr (fwd) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cfma(acc[j][a], u[3 * a + 0], c0);
-        cfma(acc[j][a], u[3 * a + 1], c1);
-        cfma(acc[j][a], u[3 * a + 2], c2);
+        cfma(acc[j][a], u[3 * a + 0], v[j][0]);
+        cfma(acc[j][a], u[3 * a + 1], v[j][1]);
+        cfma(acc[j][a], u[3 * a + 2], v[j][2]);
       }
     } else {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        cfms_conj(acc[j][a], u[0 + a], c0);
-        cfms_conj(acc[j][a], u[3 + a], c1);
-        cfms_conj(acc[j][a], u[6 + a], c2);
+        cfms_conj(acc[j][a], u[0 + a], v[j][0]);
+        cfms_conj(acc[j][a], u[3 + a], v[j][1]);
+        cfms_conj(acc[j][a], u[6 + a], v[j][2]);
       }
     }
   }
 }
 
-// acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT (bit j of act).
+// acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT.
 // Each hop is its own instantiation, guarded by a wavefront-uniform test.
 template <typename R, int RECON, int NBT, int LPS, bool NT, typename In, typename LS>
 __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __restrict__ lf,
                                              const cplx<LS>* __restrict__ lb,
                                              const cplx<LS>* __restrict__ lf3,
                                              const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
-                                             int dp, const In& in, unsigned act,
-                                             cplx<R> (&acc)[NBT][3]) {
+                                             int dp, const In& in, cplx<R> (&acc)[NBT][3]) {
 #define QX_HOP(H)                               \
   if (LPS == 1 || (H) % LPS == dp)              \
-  stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, act, acc)
+  stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, acc)
   QX_HOP(0);
   QX_HOP(1);
   QX_HOP(2);
@@ -476,11 +524,12 @@ __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __res
 }
 
 // The same for the links of output parity pout; whether the links stream past
-// the caches is decided once per launch (Geo::stream_links).
+// the caches is decided once per launch (Geo::stream_links).  The caller runs
+// it only for sites of the lattice (every slot of the thread is computed).
 template <typename R, int RECON, int NBT, int LPS, typename In, typename LS>
 __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __restrict__ links,
                                              int pout, int cb, const Site& s, int dp, const In& in,
-                                             unsigned act, cplx<R> (&acc)[NBT][3]) {
+                                             cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   const size_t hv = (size_t)g.hv;
   // link regions [parity][mu] (link_elem_offset); the improved operator's three-hop links follow
@@ -493,14 +542,14 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __res
     Site s3 = s;
     three_hop_geometry(g, cb, s3);
     if (g.stream_links)
-      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s3, dp, in, act, acc);
+      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s3, dp, in, acc);
     else
-      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s3, dp, in, act, acc);
+      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s3, dp, in, acc);
   } else {
     if (g.stream_links)
-      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s, dp, in, act, acc);
+      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
     else
-      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s, dp, in, act, acc);
+      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
   }
 }
 
@@ -594,6 +643,9 @@ __device__ __forceinline__ void for_each_slot(const cplx<R> (&acc)[NBT][3], cplx
 // Threads per stencil block allowed by the register budget (see max_waves).
 template <typename R, int NBT>
 constexpr int kMaxThreads = sizeof(R) * NBT > 8 ? 512 : 1024;
+
+// Is the stencil output of this block order stored non-temporally?
+__host__ __device__ __forceinline__ bool order_nt(int order) { return order >= 4; }
 
 // ------------------------------------------------------------- reductions
 

@@ -35,9 +35,22 @@ hipError_t with_prec(int prec, F&& f) {
   return hipErrorInvalidValue;
 }
 
-// (sources per thread, wavefronts per site) pairs that are instantiated.
-template <typename F>
+// (sources per thread, wavefronts per site) pairs that are instantiated.  The
+// wide pairs (six and twelve sources per thread) only where WIDE is set: the
+// FP32 one-hop stencils of the standalone Dslash and of the launch-per-pass
+// solver (wide_compiled); FP64 accumulators for that many sources do not fit
+// the registers, and the other kernels serve few sources per system.
+template <bool WIDE, typename F>
 hipError_t with_nbt_lps(int nbt, int lps, F&& f) {
+  if constexpr (WIDE) {
+    switch (nbt * 16 + lps) {
+      case 6 * 16 + 1: return f.template operator()<6, 1>();
+      case 6 * 16 + 2: return f.template operator()<6, 2>();
+      case 12 * 16 + 1: return f.template operator()<12, 1>();
+      case 12 * 16 + 2: return f.template operator()<12, 2>();
+      default: break;
+    }
+  }
   switch (nbt * 16 + lps) {
     case 1 * 16 + 1: return f.template operator()<1, 1>();
     case 1 * 16 + 2: return f.template operator()<1, 2>();
@@ -52,9 +65,14 @@ hipError_t with_nbt_lps(int nbt, int lps, F&& f) {
   }
 }
 
-inline bool nbt_lps_instantiated(int nbt, int lps) {
+// Are the wide pairs compiled for links of this precision and storage?
+inline bool wide_compiled(int prec, int recon) { return prec == 1 && recon != 36; }
+
+// wide: the kernel has the wide pairs (wide_compiled, and the caller's path).
+inline bool nbt_lps_instantiated(int nbt, int lps, bool wide) {
   return (nbt == 1 && (lps == 1 || lps == 2 || lps == 4 || lps == 8)) ||
-         (nbt == 2 && (lps == 1 || lps == 2 || lps == 4)) || (nbt == 4 && (lps == 1 || lps == 2));
+         (nbt == 2 && (lps == 1 || lps == 2 || lps == 4)) || (nbt == 4 && (lps == 1 || lps == 2)) ||
+         (wide && (nbt == 6 || nbt == 12) && (lps == 1 || lps == 2));
 }
 
 template <typename F>
@@ -64,5 +82,9 @@ hipError_t with_nbt(int nbt, F&& f) {
   if (nbt == 4) return f.template operator()<4>();
   return hipErrorInvalidValue;
 }
+
+// At most four sources per thread (the kernels without wide pairs: the FP64
+// reliable-update stencils, the A epilogue of the standalone operator).
+inline int narrow_nbt(int nbt) { return nbt > 4 ? 4 : nbt; }
 
 }  // namespace qx

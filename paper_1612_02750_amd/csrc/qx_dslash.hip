@@ -24,20 +24,19 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const c
   const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
   const size_t hv = g.hv, ss = 3 * hv;
   const int k0 = grp * NBT;
-  unsigned act = 0;
-#pragma unroll
-  for (int j = 0; j < NBT; ++j)
-    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
+  const int jmax = nsrc - 1 - k0;  // last source slot of the group
+  const bool nt = order_nt(xcd);
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
-  if (act) {
+  if (cb < g.hv && jmax >= 0) {
     Site s;
     site_geometry(g, pout, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(g, links, pout, cb, s, dp, FieldIn<R>{in + k0 * ss, ss, hv},
-                                     act, acc);
+    stencil_part<R, RECON, NBT, LPS>(g, links, pout, cb, s, dp,
+                                     FieldIn<R>{in + k0 * ss, ss, hv, jmax}, acc);
   }
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
-    if (act >> j & 1u) out[(k0 + j) * ss + c * hv + cb] = {scale * v.re, scale * v.im};
+    if (j <= jmax && cb < g.hv)
+      st_cplx(out + (k0 + j) * ss + c * hv + cb, cplx<R>{scale * v.re, scale * v.im}, nt);
   });
 }
 
@@ -53,20 +52,17 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_dslash_h(
   const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
   const size_t hv = g.hv, ss = 16 * hv;
   const int k0 = grp * NBT;
-  unsigned act = 0;
-#pragma unroll
-  for (int j = 0; j < NBT; ++j)
-    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
+  const int jmax = nsrc - 1 - k0;
   cplx<float> acc[NBT][3];
   zero_acc<float, NBT>(acc);
-  if (act) {
+  if (cb < g.hv && jmax >= 0) {
     Site s;
     site_geometry(g, pout, cb, s);
-    stencil_part<float, RECON, NBT, LPS>(g, links, pout, cb, s, dp, FieldInH{in + k0 * ss, hv},
-                                         act, acc);
+    stencil_part<float, RECON, NBT, LPS>(g, links, pout, cb, s, dp,
+                                         FieldInH{in + k0 * ss, hv, jmax}, acc);
   }
   for_each_slot<float, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, const cplx<float>(&v)[3]) {
-    if (!(act >> j & 1u)) return;
+    if (j > jmax || cb >= g.hv) return;
     const cplx<float> o[3] = {{scale * v[0].re, scale * v[0].im},
                               {scale * v[1].re, scale * v[1].im},
                               {scale * v[2].re, scale * v[2].im}};
@@ -89,19 +85,16 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_deo_axpy(Geo g, const
   const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
   const size_t hv = g.hv, ss = 3 * hv;
   const int k0 = grp * NBT;
-  unsigned act = 0;
-#pragma unroll
-  for (int j = 0; j < NBT; ++j)
-    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
-  if (!act) return;
+  const int jmax = nsrc - 1 - k0;
+  if (cb >= g.hv || jmax < 0) return;
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
   Site s;
   site_geometry(g, 0, cb, s);
-  stencil_part<R, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldIn<R>{t + k0 * ss, ss, hv}, act, acc);
+  stencil_part<R, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldIn<R>{t + k0 * ss, ss, hv, jmax}, acc);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
-    if (!(act >> j & 1u)) continue;
+    if (j > jmax) continue;
     const R m2 = (R)m.m2[k0 + j];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -121,20 +114,17 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_deo_axpy_h(
   const int cb = tile_block(logical_block(xcd), g, xcd) * kTile + lane;
   const size_t hv = g.hv, ss = 16 * hv;
   const int k0 = grp * NBT;
-  unsigned act = 0;
-#pragma unroll
-  for (int j = 0; j < NBT; ++j)
-    if (k0 + j < nsrc && cb < g.hv) act |= 1u << j;
-  if (!act) return;
+  const int jmax = nsrc - 1 - k0;
+  if (cb >= g.hv || jmax < 0) return;
   cplx<float> acc[NBT][3];
   zero_acc<float, NBT>(acc);
   Site s;
   site_geometry(g, 0, cb, s);
-  stencil_part<float, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldInH{t + k0 * ss, hv}, act, acc);
-  const FieldInH pin{p + k0 * ss, hv};
+  stencil_part<float, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldInH{t + k0 * ss, hv, jmax}, acc);
+  const FieldInH pin{p + k0 * ss, hv, jmax};
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
-    if (!(act >> j & 1u)) continue;
+    if (j > jmax) continue;
     const float m2 = (float)m.m2[k0 + j];
     cplx<float> o[3];
 #pragma unroll
@@ -159,7 +149,9 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
                          const void* in, void* out, int nsrc, double scale, LaunchShape sh,
                          hipStream_t s) {
   const size_t csz = cplx_bytes(prec);
-  if (!nbt_lps_instantiated(sh.nbt, sh.lps) || !shape_ok(sh, 1, csz)) return hipErrorInvalidValue;
+  const bool wide = wide_compiled(prec, recon);
+  if (!wide) sh = narrow_shape(sh);
+  if (!nbt_lps_instantiated(sh.nbt, sh.lps, wide) || !shape_ok(sh, 1, csz)) return hipErrorInvalidValue;
   const size_t field = source_bytes(g, prec);
   const int per = sources_per_pass(sh, csz);
   const unsigned grid = grid_for(g.hv, kTile);
@@ -174,7 +166,7 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
     char* po = (char*)out + k0 * field;
     if (prec == 2) {
       hipError_t e = with_recon(recon, [&]<int RECON>() {
-        return with_nbt_lps(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
+        return with_nbt_lps<false>(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
           hipLaunchKernelGGL((k_dslash_h<RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, gl,
                              (const cplx<__half>*)links, pout, pin, po, n, (float)scale, sh.xcd);
           return hipGetLastError();
@@ -184,7 +176,7 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
       continue;
     }
     hipError_t e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
-      return with_nbt_lps(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
+      return with_nbt_lps<(sizeof(R) == 4 && RECON != 36)>(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
         hipLaunchKernelGGL((k_dslash<R, RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, gl,
                            (const cplx<R>*)links, pout, (const cplx<R>*)pin, (cplx<R>*)po, n,
                            (R)scale, sh.xcd);
@@ -208,10 +200,11 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
     const int n = std::min(per, nrhs - k0);
     Masses16 m{};
     for (int k = 0; k < n; ++k) m.m2[k] = m2[k0 + k];
-    const int threads = 64 * ((n + sh.nbt - 1) / sh.nbt);
+    const int nbt = narrow_nbt(sh.nbt);  // the A epilogue kernels take at most four
+    const int threads = 64 * ((n + nbt - 1) / nbt);
     if (prec == 2) {
       e = with_recon(recon, [&]<int RECON>() {
-        return with_nbt(sh.nbt, [&]<int NBT>() {
+        return with_nbt(nbt, [&]<int NBT>() {
           hipLaunchKernelGGL((k_deo_axpy_h<RECON, NBT>), dim3(grid), dim3(threads), 0, s, g,
                              (const cplx<__half>*)links, (const char*)tmp + k0 * field,
                              (const char*)in + k0 * field, (char*)out + k0 * field, n, m, sh.xcd);
@@ -222,7 +215,7 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
       continue;
     }
     e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
-      return with_nbt(sh.nbt, [&]<int NBT>() {
+      return with_nbt(nbt, [&]<int NBT>() {
         hipLaunchKernelGGL((k_deo_axpy<R, RECON, NBT>), dim3(grid), dim3(threads), 0, s, g,
                            (const cplx<R>*)links, (const cplx<R>*)((const char*)tmp + k0 * field),
                            (const cplx<R>*)((const char*)in + k0 * field),

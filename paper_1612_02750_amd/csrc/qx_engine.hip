@@ -27,9 +27,12 @@ bool engine_supported(const EngineCfg& c) {
   const bool ok_lo = (c.prec_lo == 0 || c.prec_lo == 1) && (!c.links16 || c.prec_lo == 1) &&
                      (c.recon_lo == 18 || c.recon_lo == 12 || c.recon_lo == 36);
   const bool ok_hi = c.recon_hi == 18 || c.recon_hi == 12 || c.recon_hi == 36;
-  const bool ok_shape = nbt_lps_instantiated(c.shape.nbt, c.shape.lps) &&
+  // the FP64 reliable-update stencils take narrow_nbt sources per thread, one wavefront each
+  const LaunchShape rsh{narrow_nbt(c.shape.nbt), 1, 0};
+  const bool wide = wide_compiled(c.prec_lo, c.recon_lo) && !c.links16;
+  const bool ok_shape = nbt_lps_instantiated(c.shape.nbt, c.shape.lps, wide) &&
                         shape_ok(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo)) &&
-                        shape_groups(c.shape, c.nsrc_max) <= max_waves(c.shape.nbt, 16);
+                        shape_groups(rsh, c.nsrc_max) <= max_waves(rsh.nbt, 16);
   return ok_lo && ok_hi && ok_shape && c.nsrc_max >= 1 && c.nsrc_max <= 64 && c.nsys >= 1 &&
          c.nblk_total >= 1 && c.nvblk_total >= 1;
 }

@@ -106,9 +106,11 @@ struct SumIn {
   const cplx<double>* __restrict__ hi;
   const cplx<Rlo>* __restrict__ lo;
   size_t ss, hv;
+  int jmax;  // last readable slot (FieldIn)
   __device__ __forceinline__ cplx<double> operator()(int j, int c, int site) const {
-    const cplx<double> a = ld_cplx<false>(hi + j * ss + c * hv, (unsigned)site);
-    const cplx<Rlo> b = ld_cplx<false>(lo + j * ss + c * hv, (unsigned)site);
+    const int jj = j < jmax ? j : jmax;
+    const cplx<double> a = ld_cplx<false>(hi + jj * ss + c * hv, (unsigned)site);
+    const cplx<Rlo> b = ld_cplx<false>(lo + jj * ss + c * hv, (unsigned)site);
     return {a.re + (double)b.re, a.im + (double)b.im};
   }
 };
@@ -408,12 +410,14 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
-                                     FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv}, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(
+        d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
+        FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0}, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
+  const bool nt = order_nt(order);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
-    if (act >> j & 1u) t[(k0 + j) * ss + c * hv + cb] = v;
+    if (act >> j & 1u) st_cplx(t + (k0 + j) * ss + c * hv + cb, v, nt);
   });
   if constexpr (LPS > 1) __syncthreads();  // the LDS buffer is reused by the next tile
 }
@@ -438,21 +442,23 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   if (act) {
     Site s;
     site_geometry(d.g, 0, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
-                                     FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(
+        d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
+        FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0}, acc);
   }
   double dot[NBT];
 #pragma unroll
   for (int j = 0; j < NBT; ++j) dot[j] = 0.0;
   const cplx<R>* p = slot<R>(d.vlo, pslot, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
+  const bool nt = order_nt(order);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
     if (!(act >> j & 1u)) return;
     const R m2 = (R)rd<FRESH>(q0[k0 + j].m2);
     const size_t i = (k0 + j) * ss + c * hv + cb;
     const cplx<R> pv = p[i];
     const cplx<R> r = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
-    Ap[i] = r;
+    st_cplx(Ap + i, r, nt);
     dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
   });
   const int G = (int)(blockDim.x >> 6) / LPS;
@@ -591,13 +597,16 @@ struct PendIn {
   const cplx<R>* __restrict__ r;  // first source of the thread
   const cplx<R>* __restrict__ p;
   size_t ss, hv;
+  int jmax;  // last readable slot (FieldIn)
   unsigned upd;
   R beta[NBT];
+  // both vectors are loaded for every slot (no branch between the loads)
   __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
-    const cplx<R> pv = ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
-    if (!(upd >> j & 1u)) return pv;
-    const cplx<R> rv = ld_cplx<false>(r + j * ss + c * hv, (unsigned)site);
-    return {fma(beta[j], pv.re, rv.re), fma(beta[j], pv.im, rv.im)};
+    const int jj = j < jmax ? j : jmax;
+    const cplx<R> pv = ld_cplx<false>(p + jj * ss + c * hv, (unsigned)site);
+    const cplx<R> rv = ld_cplx<false>(r + jj * ss + c * hv, (unsigned)site);
+    const cplx<R> n = {fma(beta[j], pv.re, rv.re), fma(beta[j], pv.im, rv.im)};
+    return (upd >> j & 1u) ? n : pv;
   }
 };
 
@@ -660,7 +669,8 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   const bool in_range = cb < d.g.hv;
   const cplx<R>* p_in = slot<R>(d.vlo, pin, vs);
   const cplx<R>* r_in = slot<R>(d.vlo, 1, vs);
-  PendIn<R, NBT> src{r_in + k0 * ss, p_in + k0 * ss, ss, hv, group_bits<NBT>(upd, k0), {}};
+  PendIn<R, NBT> src{r_in + k0 * ss, p_in + k0 * ss, ss, hv, d.nsrc - 1 - k0,
+                     group_bits<NBT>(upd, k0), {}};
 #pragma unroll
   for (int j = 0; j < NBT; ++j) src.beta[j] = k0 + j < d.nsrc ? (R)beta_sh[k0 + j] : (R)0;
   // p_new at the block's own even sites
@@ -681,11 +691,12 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp, src, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp, src, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
+  const bool nt = order_nt(xcd);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
-    if (act >> j & 1u) t[(k0 + j) * ss + c * hv + cb] = v;
+    if (act >> j & 1u) st_cplx(t + (k0 + j) * ss + c * hv + cb, v, nt);
   });
 }
 
@@ -777,17 +788,19 @@ struct StepIn {
   const cplx<R>* __restrict__ ap;
   const cplx<R>* __restrict__ p;
   size_t ss, hv;
+  int jmax;  // last readable slot (FieldIn)
   unsigned upd, sub;
   R alpha[NBT], beta[NBT];
+  // the three vectors are loaded for every slot (no branch between the loads)
   __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
-    const cplx<R> pv = ld_cplx<false>(p + j * ss + c * hv, (unsigned)site);
-    if (!(upd >> j & 1u)) return pv;
-    cplx<R> rn = ld_cplx<false>(r + j * ss + c * hv, (unsigned)site);
-    if (sub >> j & 1u) {
-      const cplx<R> av = ld_cplx<false>(ap + j * ss + c * hv, (unsigned)site);
-      rn = {fma(-alpha[j], av.re, rn.re), fma(-alpha[j], av.im, rn.im)};
-    }
-    return {fma(beta[j], pv.re, rn.re), fma(beta[j], pv.im, rn.im)};
+    const int jj = j < jmax ? j : jmax;
+    const cplx<R> pv = ld_cplx<false>(p + jj * ss + c * hv, (unsigned)site);
+    const cplx<R> rv = ld_cplx<false>(r + jj * ss + c * hv, (unsigned)site);
+    const cplx<R> av = ld_cplx<false>(ap + jj * ss + c * hv, (unsigned)site);
+    const cplx<R> rs = {fma(-alpha[j], av.re, rv.re), fma(-alpha[j], av.im, rv.im)};
+    const cplx<R> rn = (sub >> j & 1u) ? rs : rv;
+    const cplx<R> n = {fma(beta[j], pv.re, rn.re), fma(beta[j], pv.im, rn.im)};
+    return (upd >> j & 1u) ? n : pv;
   }
 };
 
@@ -897,8 +910,8 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   const cplx<R>* r_in = slot<R>(d.vlo, rin, vs);
   const cplx<R>* ap = slot<R>(d.vlo, 3, vs);
   const cplx<R>* p_in = slot<R>(d.vlo, pin, vs);
-  StepIn<R, NBT> src{r_in + k0 * ss, ap + k0 * ss, p_in + k0 * ss, ss, hv, group_bits<NBT>(upd, k0),
-                     group_bits<NBT>(step, k0), {}, {}};
+  StepIn<R, NBT> src{r_in + k0 * ss, ap + k0 * ss, p_in + k0 * ss, ss, hv, d.nsrc - 1 - k0,
+                     group_bits<NBT>(upd, k0), group_bits<NBT>(step, k0), {}, {}};
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     src.alpha[j] = k0 + j < d.nsrc ? (R)al_sh[k0 + j] : (R)0;
@@ -940,11 +953,12 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp, src, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp, src, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
+  const bool nt = order_nt(xcd);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
-    if (act >> j & 1u) t[(k0 + j) * ss + c * hv + cb] = v;
+    if (act >> j & 1u) st_cplx(t + (k0 + j) * ss + c * hv + cb, v, nt);
   });
 }
 
@@ -975,8 +989,9 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   if (act) {
     Site s;
     site_geometry(d.g, 0, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
-                                     FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv}, act, acc);
+    stencil_part<R, RECON, NBT, LPS>(
+        d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
+        FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0}, acc);
   }
   double dpa[NBT], dra[NBT], daa[NBT], drr[NBT];
 #pragma unroll
@@ -984,13 +999,14 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   const cplx<R>* p = slot<R>(d.vlo, pslot, vs);
   const cplx<R>* r = slot<R>(d.vlo, rslot, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
+  const bool nt = order_nt(xcd);
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
     if (!(act >> j & 1u)) return;
     const R m2 = (R)q0[k0 + j].m2;
     const size_t i = (k0 + j) * ss + c * hv + cb;
     const cplx<R> pv = p[i], rv = r[i];
     const cplx<R> a = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
-    Ap[i] = a;
+    st_cplx(Ap + i, a, nt);
     dpa[j] += (double)pv.re * (double)a.re + (double)pv.im * (double)a.im;
     dra[j] += (double)rv.re * (double)a.re + (double)rv.im * (double)a.im;
     daa[j] += (double)a.re * (double)a.re + (double)a.im * (double)a.im;
@@ -1115,8 +1131,9 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
   site_geometry(d.g, 1, cb, s);
   stencil_part<double, RECON, NBT, 1>(
       d.g, (const cplx<double>*)d.links_hi, 1, cb, s, 0,
-      SumIn<Rlo>{slot<double>(d.vhi, 0, vs) + k0 * ss, slot<Rlo>(d.vlo, 0, vs) + k0 * ss, ss, hv},
-      act, acc);
+      SumIn<Rlo>{slot<double>(d.vhi, 0, vs) + k0 * ss, slot<Rlo>(d.vlo, 0, vs) + k0 * ss, ss, hv,
+                 d.nsrc - 1 - k0},
+      acc);
   cplx<double>* t = slot<double>(d.vhi, 3, vs);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
@@ -1162,9 +1179,9 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
     zero_acc<double, NBT>(acc);
     Site s;
     site_geometry(d.g, 0, cb, s);
-    stencil_part<double, RECON, NBT, 1>(d.g, (const cplx<double>*)d.links_hi, 0, cb, s, 0,
-                                        FieldIn<double>{slot<double>(d.vhi, 3, vs) + k0 * ss, ss, hv},
-                                        act, acc);
+    stencil_part<double, RECON, NBT, 1>(
+        d.g, (const cplx<double>*)d.links_hi, 0, cb, s, 0,
+        FieldIn<double>{slot<double>(d.vhi, 3, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0}, acc);
     cplx<double>* xhi = slot<double>(d.vhi, 0, vs);
     cplx<double>* rhi = slot<double>(d.vhi, 1, vs);
     const cplx<double>* bb = slot<double>(d.vhi, 2, vs);
@@ -1249,7 +1266,7 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     // p alternates between slots 2 and 5, r between 1 and 6
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
     const int rin = parity ? 6 : 1, rout = parity ? 1 : 6;
-    return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+    return with_nbt_lps<false>(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
       QX_TIMED(c, PASS_DOE, s,
                hipLaunchKernelGGL((k_f2_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
                                   c.d_sys, c.nsys, c.d_st, c.d_st1, pin, pout, rin, rout,
@@ -1263,7 +1280,7 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   if (c.fused) {
     // p alternates between slots 2 and 5; the states between the two slots
     const int pin = parity ? 5 : 2, pout = parity ? 2 : 5;
-    return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+    return with_nbt_lps<false>(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
       QX_TIMED(c, PASS_DOE, s,
                hipLaunchKernelGGL((k_fiter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
                                   c.d_sys, c.nsys, c.d_st, c.d_st1, pin, pout, c.shape.xcd));
@@ -1276,7 +1293,9 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
       return hipGetLastError();
     });
   }
-  hipError_t e = with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+  // the launch-per-pass stencils have the wide shapes for FP32 one-hop links
+  constexpr bool kWide = sizeof(R) == 4 && RECON != 36 && std::is_same_v<LS, R>;
+  hipError_t e = with_nbt_lps<kWide>(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     QX_TIMED(c, PASS_P, s,
              hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
                                 c.shape.xcd));
@@ -1302,14 +1321,16 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
 // RECON: the storage of the FP64 links (the update works on them).
 template <typename Rlo, int RECON>
 hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
-  const int G = shape_groups(c.shape, c.nsrc_max);
+  // FP64 stencils: at most four sources per thread (ru_nbt)
+  const LaunchShape rsh{narrow_nbt(c.shape.nbt), 1, c.shape.xcd};
+  const int G = shape_groups(rsh, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * G);
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
   // the two-launch sequence leaves an update's last step to its next D_oe
   // pass, except at the end of a chunk (the host reads the states there)
   const bool handoff = c.fused && c.two && !last;
   SrcState* copy = c.fused && !handoff ? c.d_st1 : nullptr;
-  hipError_t e = with_nbt(c.shape.nbt, [&]<int NBT>() {
+  hipError_t e = with_nbt(rsh.nbt, [&]<int NBT>() {
     QX_TIMED(c, PASS_UPDATE, s,
              hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
                                 c.d_st, c.shape.xcd));
@@ -1345,7 +1366,7 @@ int persistent_per_cu_impl(const EngineCfg& c) {
   const int threads = 64 * c.shape.lps * G;
   const size_t lds = shape_lds(c.shape, c.nsrc_max, cplx_bytes(c.prec_lo));
   int per_cu = 0;
-  hipError_t e = with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+  hipError_t e = with_nbt_lps<false>(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &per_cu, reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS, LS>), threads, lds);
   });
@@ -1362,7 +1383,7 @@ hipError_t persistent_impl(const EngineCfg& c, int iters, GridSync* gs, int grid
   int nsys = c.nsys, nsrc = c.nsrc_total, nblk = c.nblk_total, nvblk = c.nvblk_total;
   SrcState* st = c.d_st;
   void* args[] = {&sys, &nsys, &st, &nsrc, &nblk, &nvblk, &iters, &gs, &timeout};
-  return with_nbt_lps(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
+  return with_nbt_lps<false>(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     return hipLaunchCooperativeKernel(
         reinterpret_cast<const void*>(&k_cg_persistent<R, RECON, NBT, LPS, LS>), dim3(grid),
         dim3(threads), args, (unsigned)lds, s);

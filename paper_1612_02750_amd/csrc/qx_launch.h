@@ -11,11 +11,13 @@ namespace qx {
 // lps * groups wavefronts; lps wavefronts share the eight hops of a site,
 // each group takes nbt sources (groups = ceil(nsrc / nbt)).
 struct LaunchShape {
-  int nbt = 1;  // sources per thread: 1, 2 or 4
+  int nbt = 1;  // sources per thread: 1, 2 or 4 (FP32 arithmetic also 6 and 12)
   int lps = 2;  // wavefronts per site: 1, 2, 4 or 8
   int xcd = 1;  // block order: 0 as dispatched, 1 XCD-contiguous, 2 and 3 XCD-contiguous
-                // with (z, t)-tiled traversal (tile_block)
+                // with (z, t)-tiled traversal, 4 and 5 one z or t slab per XCD walked
+                // plane by plane with non-temporal output stores (tile_block)
 };
+constexpr int kMaxOrder = 5;
 
 inline int shape_groups(const LaunchShape& s, int nsrc) { return (nsrc + s.nbt - 1) / s.nbt; }
 // LDS bytes of the hop reduction (0 without hop splitting).
@@ -27,10 +29,20 @@ inline size_t shape_lds(const LaunchShape& s, int nsrc, size_t cplx_sz) {
 // which then get up to 256 VGPRs.
 inline int max_waves(int nbt, size_t cplx_sz) { return (cplx_sz / 2) * nbt > 8 ? 8 : 16; }
 // Is the shape launchable for nsrc sources with complex numbers of cplx_sz bytes?
+// Shape with at most four sources per thread (and at most two wavefronts per
+// site when it had more), for a kernel without the wide pairs.
+inline LaunchShape narrow_shape(LaunchShape s) {
+  if (s.nbt > 4) {
+    s.nbt = 4;
+    if (s.lps > 2) s.lps = 2;
+  }
+  return s;
+}
 inline bool shape_ok(const LaunchShape& s, int nsrc, size_t cplx_sz) {
-  const bool nbt_ok = s.nbt == 1 || s.nbt == 2 || s.nbt == 4;
+  const bool nbt_ok = s.nbt == 1 || s.nbt == 2 || s.nbt == 4 ||
+                      (cplx_sz == 8 && (s.nbt == 6 || s.nbt == 12));
   const bool lps_ok = s.lps == 1 || s.lps == 2 || s.lps == 4 || s.lps == 8;
-  if (!nbt_ok || !lps_ok || s.xcd < 0 || s.xcd > 3 || nsrc < 1) return false;
+  if (!nbt_ok || !lps_ok || s.xcd < 0 || s.xcd > kMaxOrder || nsrc < 1) return false;
   const int waves = s.lps * shape_groups(s, nsrc);
   return waves <= max_waves(s.nbt, cplx_sz) && shape_lds(s, nsrc, cplx_sz) <= 64 * 1024;
 }

@@ -79,8 +79,8 @@ int qxg_xcd_perm(int G, int32_t* out) {
 }
 
 // Exhaustive bijection check of tile_block: every L2, L3 even in [2, maxL],
-// P = (L0 / 2) L1 / 64 blocks per (z, t) plane in [1, maxP], orders 2 and 3
-// (and 0, 1, identity).  Returns the number of geometries that fail.
+// P = (L0 / 2) L1 / 64 blocks per (z, t) plane in [1, maxP], orders 0 to 5.
+// Returns the number of (geometry, order) pairs that fail.
 int64_t qxg_tile_bijection_failures(int maxL, int maxP) {
   int64_t bad = 0;
   std::vector<int> seen;
@@ -91,7 +91,7 @@ int64_t qxg_tile_bijection_failures(int maxL, int maxP) {
         const int32_t L[4] = {64 * P, 2, L2, L3};
         const Geo g = geo_of(L, 0);
         const int nb = g.hv / 64;
-        for (int order = 0; order < 4; ++order) {
+        for (int order = 0; order < 6; ++order) {
           seen.assign(nb, 0);
           bool ok = true;
           for (int bl = 0; bl < nb && ok; ++bl) {

@@ -80,13 +80,19 @@ def test_tune_cache_roundtrip(lib, tmp_path):
     src.write_text('{\n  "gfx950:4x4x4x8:p1:r12:n3": [2, 2, 1],\n'
                    '  "gfx950:4x4x4x8:p0:r18:n1": [4, 8, 0],\n'
                    '  "gfx950:8x8x8x8:p2:r36:n1": [1, 8, 7],\n'
+                   '  "gfx950:8x8x8x8:p1:r18:n12": [12, 2, 4],\n'
+                   '  "gfx950:8x8x8x8:p0:r18:n12": [12, 2, 4],\n'
+                   '  "gfx950:8x8x8x8:p1:r36:n12": [6, 1, 0],\n'
                    '  "broken": [1, 2]\n}\n')
     assert lib.qx_tune_cache_load(str(src).encode()) == 0
     out = tmp_path / "out.json"
     assert lib.qx_tune_cache_save(str(out).encode()) == 0
     txt = out.read_text()
     assert '"gfx950:4x4x4x8:p1:r12:n3": [2, 2, 1]' in txt
-    assert '"gfx950:8x8x8x8:p2:r36:n1": [1, 8, 3]' in txt  # order clamped to 0..3
+    assert '"gfx950:8x8x8x8:p2:r36:n1": [1, 8, 5]' in txt  # order clamped to 0..5
+    # six or twelve sources per thread: FP32 one-hop links only
+    assert '"gfx950:8x8x8x8:p1:r18:n12": [12, 2, 4]' in txt
+    assert "p0:r18:n12" not in txt and "p1:r36:n12" not in txt
     assert "p0:r18:n1" not in txt and "broken" not in txt
     assert lib.qx_tune_cache_load(str(tmp_path / "missing.json").encode()) == 1
     assert lib.qx_tune_cache_save(str(tmp_path / "no" / "dir.json").encode()) == 1

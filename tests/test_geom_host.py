@@ -103,7 +103,7 @@ def test_device_link_signs_antiperiodic(geo, dims):
 
 
 def test_tile_block_bijection_exhaustive(geo):
-    """Orders 0-3 are bijections of the block range for every L2, L3 even up to
+    """Orders 0-5 are bijections of the block range for every L2, L3 even up to
     48 and 1-4 blocks per (z, t) plane."""
     assert geo.qxg_tile_bijection_failures(48, 4) == 0
 
@@ -111,7 +111,7 @@ def test_tile_block_bijection_exhaustive(geo):
 @pytest.mark.parametrize("dims", [(16, 16, 16, 16), (32, 32, 32, 32), (48, 48, 48, 48),
                                   (16, 16, 16, 32), (24, 24, 24, 24), (8, 8, 8, 8),
                                   (12, 12, 12, 12), (32, 32, 32, 64)])
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
 def test_tile_block_bijection_real_shapes(geo, dims, order):
     hv = int(np.prod(dims)) // 2
     nb = hv // 64
@@ -119,6 +119,24 @@ def test_tile_block_bijection_real_shapes(geo, dims, order):
     assert geo.qxg_tile_perm(_p(np.array(dims, np.int32)), order, _p(out)) == nb
     assert np.array_equal(np.sort(out), np.arange(nb))
     s2 = dims[0] // 2 * dims[1]
+    if order >= 4:
+        cut = dims[2] if order == 4 else dims[3]
+        if s2 % 64 or cut % 8:
+            assert np.array_equal(out, np.arange(nb))
+            return
+        # slab k (positions [k nb/8, (k+1) nb/8)) covers one eighth of the cut
+        # extent, every plane of it, in plane-major order
+        P = s2 // 64
+        plane = out // P
+        z, t = plane % dims[2], plane // dims[2]
+        w = cut // 8
+        per = nb // 8
+        for k in range(8):
+            zs = z[k * per:(k + 1) * per] if order == 4 else t[k * per:(k + 1) * per]
+            assert zs.min() == k * w and zs.max() == (k + 1) * w - 1
+        walk = t if order == 4 else z
+        assert np.all(np.diff(walk[:per]) >= 0)  # the other extent is walked in order
+        return
     if s2 % 64 == 0 and dims[3] >= 4:
         # tiled: position bl's block lies in the (z, t) plane the tile walk names
         P = s2 // 64

@@ -49,7 +49,8 @@ def test_batch_tune(qx, engine, stream):
         B = qx.Batch(systems, tol=1e-10, engine=getattr(qx, "ENGINE_" + engine))
         nbt, lps, order = B.tune(2)
         torch.cuda.synchronize()
-        assert nbt in (1, 2, 4) and lps in (1, 2, 4, 8) and order in (0, 1, 2, 3)
+        # small systems run the fused sequences, which take at most four sources per thread
+        assert nbt in (1, 2, 4) and lps in (1, 2, 4, 8) and order in range(6)
         assert lps > 1  # batches of at most 1024 blocks per system split the hops
         for k in keep:
             assert not to_host(k[4]).any()  # tuning writes no solution

@@ -115,20 +115,28 @@ def test_dslash_multi_rhs(qx, nrhs, prec, recon, tol):
     assert err <= tol
 
 
-SHAPES_NL = [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2)]
+SHAPES_NARROW = [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4), (4, 1), (4, 2)]
+SHAPES_NL = SHAPES_NARROW + [(6, 1), (6, 2), (12, 1), (12, 2)]
 
 
 @pytest.mark.parametrize("nbt,lps", SHAPES_NL)
-@pytest.mark.parametrize("prec,recon,tol", [("f64", 18, 1e-13), ("f32", 12, 1e-5)])
+@pytest.mark.parametrize("prec,recon,tol", [("f64", 18, 1e-13), ("f32", 12, 1e-5),
+                                            ("f32", 18, 1e-5)])
 def test_dslash_launch_shapes(qx, nbt, lps, prec, recon, tol):
     """Every compiled launch shape (sources per thread, wavefronts per site), with
     V/2 = 192 ragged against the 64-site tiles and a source count that leaves
-    partly filled groups."""
+    partly filled groups (5 sources: 6 and 12 per thread fill one group
+    partly).  Six and twelve sources per thread exist for FP32 one-hop links
+    only: FP64 rejects them."""
     dims = (6, 4, 2, 8)
     lat = qx.Lattice(dims, antiperiodic_t=True)
     U = gauge(dims, seed=4)
     g = qx.Gauge(lat, to_dev(U), prec, recon)
     nrhs = 5
+    if nbt > 4 and prec == "f64":
+        with pytest.raises(qx.QXError):
+            g.set_launch(nrhs, nbt, lps, 1)
+        return
     g.set_launch(nrhs, nbt, lps, (nbt + lps) % 2)
     chi = synth.gauss_source(nrhs, lat.hv, 8)
     out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), 1, nrhs), nrhs, prec))
@@ -137,12 +145,15 @@ def test_dslash_launch_shapes(qx, nbt, lps, prec, recon, tol):
         assert rel(out[k], ref) <= tol, (k, nbt, lps)
 
 
-@pytest.mark.parametrize("order", [0, 1, 2, 3])
-@pytest.mark.parametrize("dims", [(8, 16, 4, 8), (16, 16, 6, 12)])
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("dims", [(8, 16, 4, 8), (16, 16, 6, 12), (8, 16, 8, 16)])
 def test_dslash_block_orders(qx, order, dims):
     """Every block order, on lattices whose (z, t) planes hold whole 64-site
     blocks so that the tiled orders 2 and 3 are in effect (tiles cut to the
-    divisors 2/3 of L2 = 6 and 6/4 of L3 = 12 on the second lattice)."""
+    divisors 2/3 of L2 = 6 and 6/4 of L3 = 12 on the second lattice); the slab
+    orders 4 and 5 (with non-temporal output stores) are in effect where L2
+    (order 4) or L3 (order 5) is a multiple of 8, and fall back to
+    checkerboard order elsewhere."""
     lat = qx.Lattice(dims, antiperiodic_t=True)
     U = gauge(dims, seed=12)
     nrhs = 3
@@ -150,7 +161,7 @@ def test_dslash_block_orders(qx, order, dims):
     refs = [oracle.dslash_eo(dims, U, chi[k], 0, oracle.BC_T_ANTIPERIODIC) for k in range(nrhs)]
     for prec, recon, tol in (("f64", 18, 1e-13), ("f32", 12, 1e-5)):
         g = qx.Gauge(lat, to_dev(U), prec, recon)
-        for nbt, lps in ((1, 1), (1, 4), (2, 2), (4, 1)):
+        for nbt, lps in ((1, 1), (1, 4), (2, 2), (4, 1)) + (((6, 2), (12, 1)) if prec == "f32" else ()):
             g.set_launch(nrhs, nbt, lps, order)
             out = to_host(qx.unpack(lat, qx.dslash(g, qx.pack(lat, to_dev(chi), prec), 0, nrhs),
                                     nrhs, prec))
@@ -190,7 +201,7 @@ def test_tuner_and_graph_timer(qx, prec, recon, tol):
     g = qx.Gauge(lat, to_dev(U), prec, recon)
     for nrhs in (1, 3):
         nbt, lps, xcd = g.tune(nrhs)
-        assert (nbt, lps) in SHAPES_NL and xcd in (0, 1, 2, 3)
+        assert (nbt, lps) in SHAPES_NL and xcd in range(6)
         chi = synth.gauss_source(nrhs, lat.hv, 10 + nrhs)
         pin = qx.pack(lat, to_dev(chi), prec)
         out = qx.dslash(g, pin, 1, nrhs)
@@ -408,6 +419,39 @@ def test_cg_multi_rhs_config3_32_4(qx):
         rr = oracle.true_residual(dims, U, m, b[k], x[k])
         print(f"source {k}: iters {st[k].iters}, oracle residual {rr:.2e}", flush=True)
         assert rr <= 1e-10 and st[k].status == 0, (k, rr)
+
+
+@pytest.mark.parametrize("shape", [(12, 2, 4), (12, 1, 0), (6, 2, 5), (6, 1, 1), (4, 2, 4)])
+def test_cg_wide_shapes_launch_engine(qx, shape):
+    """Twelve sources under the launch-per-pass engine with six or twelve
+    sources per thread and the slab block orders: every source solves to 1e-10
+    by the oracle.  The masses differ, so the sources stop at different
+    iterations and the stencils compute slots whose source no longer runs (their
+    outputs are not stored).  The FP64 reliable updates take four sources per
+    thread."""
+    import torch
+
+    dims = (8, 16, 8, 16)
+    lat = qx.Lattice(dims, antiperiodic_t=True)
+    U = gauge(dims, seed=21)
+    Ud = to_dev(U)
+    g64 = qx.Gauge(lat, Ud, "f64")
+    g32 = qx.Gauge(lat, Ud, "f32", 12)
+    masses = [0.05 + 0.04 * k for k in range(12)]
+    b = synth.gauss_source(12, lat.hv, 22)
+    x = torch.empty_like(to_dev(b))
+    B = qx.Batch([(g64, g32, to_dev(b), masses, x)], tol=1e-10, mode=qx.CG_MIXED_F32,
+                 engine=qx.ENGINE_LAUNCH)
+    B.set_launch(*shape)
+    st = B.solve()
+    _check_solution(dims, U, masses, b, to_host(x), st, flags=oracle.BC_T_ANTIPERIODIC)
+    assert st[11].iters < st[0].iters
+    # the same under the default shape: the same mathematics, rounding aside
+    x2 = torch.empty_like(x)
+    B2 = qx.Batch([(g64, g32, to_dev(b), masses, x2)], tol=1e-10, mode=qx.CG_MIXED_F32,
+                  engine=qx.ENGINE_LAUNCH)
+    B2.solve()
+    assert rel(to_host(x), to_host(x2)) <= 1e-8
 
 
 def test_uneven_batch_config4(qx):
@@ -825,7 +869,7 @@ def test_naik_dslash_parity(qx, dims, prec, tol):
                 assert rel(out[k], ref) <= tol, (anti, pout, k)
 
 
-@pytest.mark.parametrize("nbt,lps", SHAPES_NL)
+@pytest.mark.parametrize("nbt,lps", SHAPES_NARROW)
 def test_naik_launch_shapes(qx, nbt, lps):
     dims = (6, 4, 2, 8)
     lat = qx.Lattice(dims, antiperiodic_t=True)
