@@ -232,6 +232,17 @@ int qx_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const void* in, voi
 int qx_apply_A(const qx_gauge_t* g, int nrhs, const double* masses, const void* in, void* out,
                void* tmp_odd, hipStream_t stream);
 
+/* qx_apply_A without the tmp_odd workspace, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc): the odd intermediate lives in a device array of the
+   library (32 MiB, one per GPU, held until the process ends), so the call
+   allocates nothing.  It needs nrhs * qx_field_bytes(lat, 1, prec) <= 32 MiB
+   (else QX_EINVAL; e.g. FP64 16^4: 20 sources, FP32 32^4: 2 sources).  Same
+   kernels and results as qx_apply_A.  Calls on one GPU share the array: calls
+   that overlap in time on one GPU (other streams or threads) race. */
+int qx_apply_A_noalloc(const qx_gauge_t* g, int nrhs, const double* masses, const void* in,
+                       void* out, hipStream_t stream);
+
 /* ------------------------------------------------------------- solver */
 
 /* Workspace bytes for qx_cg_solve with nrhs sources. */

@@ -121,6 +121,7 @@ def load():
         "qx_force_su3": ([_P, _P, _P, _P, _P], _I),
         "qx_action_backward": ([_P, _I, ctypes.c_double, _P, _P, _P, _P, _P], _I),
         "qx_batch_profile": ([_P, _I, _P, _P, _P], _I),
+        "qx_apply_A_noalloc": ([_P, _I, _P, _P, _P, _P], _I),
         "qx_batch_set_launch": ([_P, _I, _I, _I, _P], _I),
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
         "qx_gauge_action": ([_P, _P, ctypes.c_double, _P, _SZ, _P, _P], _I),
@@ -331,6 +332,16 @@ def apply_A(g: Gauge, packed_in, masses: Sequence[float], out=None, tmp=None, st
     m = (ctypes.c_double * nrhs)(*masses)
     _check(load().qx_apply_A(g._h, nrhs, m, _ptr(packed_in), _ptr(out), _ptr(tmp),
                              _stream(stream)))
+    return out
+
+
+def apply_A_noalloc(g: Gauge, packed_in, masses: Sequence[float], out=None, stream=None):
+    """apply_A with the odd intermediate in the library's device array (no
+    workspace; at most 32 MiB of it)."""
+    nrhs = len(masses)
+    out = _bytes(g.lat.field_bytes(nrhs, g.prec)) if out is None else out
+    m = (ctypes.c_double * nrhs)(*masses)
+    _check(load().qx_apply_A_noalloc(g._h, nrhs, m, _ptr(packed_in), _ptr(out), _stream(stream)))
     return out
 
 

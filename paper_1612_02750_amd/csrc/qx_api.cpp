@@ -322,6 +322,23 @@ extern "C" int qx_dslash(const qx_gauge_t* g, int out_parity, int nrhs, const vo
   return QX_OK;
 }
 
+extern "C" int qx_apply_A_noalloc(const qx_gauge_t* g, int nrhs, const double* masses,
+                                  const void* in, void* out, hipStream_t stream) {
+  if (!g || !masses || !in || !out || nrhs < 1)
+    return fail(QX_EINVAL, "qx_apply_A_noalloc: bad argument");
+  if (in == out) return fail(QX_EINVAL, "qx_apply_A_noalloc: buffers must not alias");
+  const size_t need = (size_t)nrhs * source_bytes(g->geo, g->prec);
+  if (need > kNoAllocScratchBytes)
+    return fail(QX_EINVAL,
+                "qx_apply_A_noalloc: %d sources need %zu bytes of scratch; the library's array "
+                "holds %zu (use qx_apply_A with a workspace)",
+                nrhs, need, kNoAllocScratchBytes);
+  QX_HIP(launch_apply_A_noalloc(g->geo, g->prec, g->recon, g->packed, nrhs, masses, in, out,
+                                shape_for(g, nrhs), stream),
+         "qx_apply_A_noalloc");
+  return QX_OK;
+}
+
 extern "C" int qx_apply_A(const qx_gauge_t* g, int nrhs, const double* masses, const void* in,
                           void* out, void* tmp_odd, hipStream_t stream) {
   if (!g || !masses || !in || !out || !tmp_odd || nrhs < 1)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "qx_device.h"
 #include "qx_dispatch.h"
@@ -190,7 +191,7 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
 
 hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, int nrhs,
                           const double* m2, const void* in, void* out, void* tmp, LaunchShape sh,
-                          hipStream_t s) {
+                          hipStream_t s, bool square) {
   hipError_t e = launch_dslash(g, prec, recon, links, 1, in, tmp, nrhs, 1.0, sh, s);
   if (e != hipSuccess) return e;
   const size_t field = source_bytes(g, prec);
@@ -199,7 +200,7 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
   for (int k0 = 0; k0 < nrhs; k0 += per) {
     const int n = std::min(per, nrhs - k0);
     Masses16 m{};
-    for (int k = 0; k < n; ++k) m.m2[k] = m2[k0 + k];
+    for (int k = 0; k < n; ++k) m.m2[k] = square ? m2[k0 + k] * m2[k0 + k] : m2[k0 + k];
     const int nbt = narrow_nbt(sh.nbt);  // the A epilogue kernels take at most four
     const int threads = 64 * ((n + nbt - 1) / nbt);
     if (prec == 2) {
@@ -226,6 +227,48 @@ hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, 
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ------------------------------------------------ allocation-free operator
+//
+// The D_oe intermediate of the allocation-free A lives in a file-scope device
+// array (one per GPU, held until the process ends).  In host code the array's
+// name is not a device address: its address on the current device comes from
+// hipGetSymbolAddress, looked up once per device and kept in noalloc_ptr.
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_apply_A_noalloc(const Geo& g, int prec, int recon, const void* links, int nrhs,
+                                  const double* masses, const void* in, void* out, LaunchShape sh,
+                                  hipStream_t s) {
+  if ((size_t)nrhs * source_bytes(g, prec) > kNoAllocScratchBytes) return hipErrorInvalidValue;
+  void* tmp = nullptr;
+  const hipError_t e = noalloc_scratch(&tmp);
+  if (e != hipSuccess) return e;
+  // every element of the odd intermediate is written by the D_oe launch
+  // before A's epilogue reads it: nothing to clear
+  return launch_apply_A(g, prec, recon, links, nrhs, masses, in, out, tmp, sh, s, true);
 }
 
 }  // namespace qx

@@ -74,10 +74,20 @@ hipError_t launch_batch_stats(const void* st, int n, const void* gs, void* out, 
 hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, int pout,
                          const void* in, void* out, int nsrc, double scale, LaunchShape sh,
                          hipStream_t s);
-// out_k = m2[k] in_k - D_eo D_oe in_k (tmp: odd scratch).
+// out_k = m2[k] in_k - D_eo D_oe in_k (tmp: odd scratch); square: m2 holds the
+// masses, squared on the host per pass.
 hipError_t launch_apply_A(const Geo& g, int prec, int recon, const void* links, int nrhs,
                           const double* m2, const void* in, void* out, void* tmp, LaunchShape sh,
-                          hipStream_t s);
+                          hipStream_t s, bool square = false);
+
+// A without a caller workspace: the odd intermediate of nrhs sources
+// (nrhs * source_bytes) in the library's device array of kNoAllocScratchBytes
+// (hipErrorInvalidValue when it does not fit).  Allocates nothing; calls that
+// overlap on one GPU share the array and race.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+hipError_t launch_apply_A_noalloc(const Geo& g, int prec, int recon, const void* links, int nrhs,
+                                  const double* masses, const void* in, void* out, LaunchShape sh,
+                                  hipStream_t s);
 
 // ------------------------------------------------------------------ engine
 
