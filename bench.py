@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the 32^4 FP16-link and one-source comparisons")
     ap.add_argument("--solver-shape", default=None,
-                    help="nbt,lps,order of the step's batch in --kernels-only runs")
+                    help="nbt,lps,order of the step's batch instead of its tuner (profiler runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed step, its FP64 comparisons and its pass timing")
     ap.add_argument("--kernels-only", action="store_true",
@@ -109,9 +109,10 @@ PASS_BYTES = {
 # twelve-source step, all sources served) from two rocprofv3 counter runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
 # counters read for the library's copy and read probes on 1 GiB (FETCH x 2,
-# WRITE x 1).  Reported only while the engine sources and the launch shape are
-# the ones the counters were taken with; keyed by "nbt,lps,order".
-TRAFFIC = {"sha": None, "bytes": {}}
+# WRITE x 1), from profiles/cg_mixed_32x32x32x32_12src_counters.md.  Reported
+# only while the engine sources and the launch shape are the ones the counters
+# were taken with; keyed by "nbt,lps,order".
+TRAFFIC = {"sha": "3153b9fb2af85281", "bytes": {"6,2,0": 983612224}}
 KERNEL_SOURCES = ("qx_engine_kernels.h", "qx_device.h", "qx_internal.h", "qx_launch.h",
                   "qx_dispatch.h")
 
@@ -183,7 +184,11 @@ def headline(torch, qx, synth, args):
     g64.tune(1)
     x_mx = torch.empty_like(bd)
     mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=tol, mode=qx.CG_MIXED_F32)
-    shape = list(mixed.tune(2))
+    if args.solver_shape:  # a fixed shape (profiler runs), else the solver's own tuner
+        shape = [int(v) for v in args.solver_shape.split(",")]
+        mixed.set_launch(*shape)
+    else:
+        shape = list(mixed.tune(2))
     log(f"step: solver launch shape {shape}")
     for _ in range(args.warmup):
         mixed.solve()
