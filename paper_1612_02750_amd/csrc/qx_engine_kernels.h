@@ -142,11 +142,25 @@ __device__ __forceinline__ double tile_sum(int tile, size_t n, double* sh, F&& f
 // wavefront of 64 lanes reduced by one butterfly, the four wavefront sums
 // added in order.  Every thread of the block calls it (the block is a whole
 // number of wavefronts) and every thread gets the result.  sh: 4 doubles.
+// A virtual lane's values are loaded eight at a time before they are added
+// (in the same order), so that a lane has eight loads in flight.
+__device__ __forceinline__ double lane_sum(const double* __restrict__ a, int i, int n) {
+  double v = 0.0;
+  for (; i + 7 * 256 < n; i += 8 * 256) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = a[i + u * 256];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; i < n; i += 256) v += a[i];
+  return v;
+}
+
 __device__ __forceinline__ double canon_sum(const double* __restrict__ a, int n, double* sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
   for (int vw = w; vw < 4; vw += nw) {
-    double v = 0.0;
-    for (int i = vw * 64 + lane; i < n; i += 256) v += a[i];
+    double v = lane_sum(a, vw * 64 + lane, n);
     v = wave_sum(v);
     if (lane == 0) sh[vw] = v;
   }
@@ -364,7 +378,15 @@ __device__ __forceinline__ void finalize_one(const SysDesc* __restrict__ sys, in
   const int ph = fin_phase(kind);
   if (ph >= 0 && rd<FRESH>(st[g].phase) != ph) return;
   const double t = kind != FIN_COMMIT ? partial_total(d, k, kind, sh) : 0.0;
-  if (threadIdx.x == 0) finalize_source<FRESH>(kind, st[g], t);
+  if (threadIdx.x == 0) {
+    finalize_source<FRESH>(kind, st[g], t);
+    // The x/r pass of these engines leaves x_lo += alpha p to the next p pass
+    // (which reads p anyway) or to the next reliable update: pending after a
+    // beta step, applied by the time of the next alpha step or update.
+    StateRef<FRESH> q = st[g];
+    if (kind == FIN_BETA) q.xpend = 1;
+    if (kind == FIN_ALPHA || kind == FIN_RU) q.xpend = 0;
+  }
 }
 
 namespace {
@@ -470,7 +492,8 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
 
 // x_lo += alpha p, r -= alpha Ap over vector tile `tile` of source k of a
 // system, and the partial of |r|^2.  Works for any block size.
-template <typename R>
+// (UPDATE_X false: r only; x_lo += alpha p is left pending, SrcState::xpend.)
+template <typename R, bool UPDATE_X>
 __device__ __forceinline__ void xr_body(const SysDesc& d, int k, int tile, R al, int pslot,
                                         double* sh) {
   const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
@@ -479,29 +502,42 @@ __device__ __forceinline__ void xr_body(const SysDesc& d, int k, int tile, R al,
   const cplx<R>* p = slot<R>(d.vlo, pslot, vs) + k * n;
   const cplx<R>* Ap = slot<R>(d.vlo, 3, vs) + k * n;
   const double t = tile_sum(tile, n, sh, [&](size_t e) {
-    const cplx<R> pv = p[e], av = Ap[e];
-    cplx<R> xv = x[e], rv = r[e];
-    xv.re = fma(al, pv.re, xv.re);
-    xv.im = fma(al, pv.im, xv.im);
+    const cplx<R> av = Ap[e];
+    cplx<R> rv = r[e];
+    if constexpr (UPDATE_X) {
+      const cplx<R> pv = p[e];
+      cplx<R> xv = x[e];
+      xv.re = fma(al, pv.re, xv.re);
+      xv.im = fma(al, pv.im, xv.im);
+      x[e] = xv;
+    }
     rv.re = fma(-al, av.re, rv.re);
     rv.im = fma(-al, av.im, rv.im);
-    x[e] = xv;
     r[e] = rv;
     return (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
   });
   if (threadIdx.x == 0) d.partials_v[(size_t)k * d.vtiles + tile] = t;
 }
 
-// p = r + beta p over vector tile `tile` of source k.  Works for any block size.
+// p = r + beta p over vector tile `tile` of source k, after x_lo += alpha p
+// with the old p when the last x/r step left it pending (xp).  Works for any
+// block size.
 template <typename R>
-__device__ __forceinline__ void p_body(const SysDesc& d, int k, int tile, R be) {
+__device__ __forceinline__ void p_body(const SysDesc& d, int k, int tile, R be, bool xp, R al) {
   const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
   const cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
   cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  cplx<R>* x = slot<R>(d.vlo, 0, vs) + k * n;
   for (int t = threadIdx.x; t < kVTile; t += blockDim.x) {
     const size_t e = (size_t)tile * kVTile + t;
     if (e >= n) break;
     const cplx<R> rv = r[e], pv = p[e];
+    if (xp) {
+      cplx<R> xv = x[e];
+      xv.re = fma(al, pv.re, xv.re);
+      xv.im = fma(al, pv.im, xv.im);
+      x[e] = xv;
+    }
     p[e] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
   }
 }
@@ -513,7 +549,7 @@ __device__ __forceinline__ void xr_tile(const SysDesc* __restrict__ sys, int nsy
   const SysDesc& d = sys_of_vblock(sys, nsys, b);
   const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
   if (rd<FRESH>(st[d.src0 + k].phase) != PH_RUN) return;
-  xr_body<R>(d, k, tile, (R)rd<FRESH>(st[d.src0 + k].alpha), 2, sh);
+  xr_body<R, false>(d, k, tile, (R)rd<FRESH>(st[d.src0 + k].alpha), 2, sh);
 }
 
 // E0: p = r + beta p for running sources whose search direction the previous
@@ -525,7 +561,7 @@ __device__ __forceinline__ void p_tile(const SysDesc* __restrict__ sys, int nsys
   const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
   const SrcState& q = st[d.src0 + k];
   if (rd<FRESH>(q.phase) != PH_RUN || !rd<FRESH>(q.pend)) return;
-  p_body<R>(d, k, tile, (R)rd<FRESH>(q.beta));
+  p_body<R>(d, k, tile, (R)rd<FRESH>(q.beta), rd<FRESH>(q.xpend) != 0, (R)rd<FRESH>(q.alpha));
 }
 
 template <typename R>
@@ -722,7 +758,7 @@ __global__ void __launch_bounds__(256) k_fiter_xr(const SysDesc* __restrict__ sy
   }
   const bool go = run && as.ok;
   if (tile == 0 && threadIdx.x == 0) write_state<FIN_ALPHA>(q, st_out + g, run, t, go ? 1 : q.have_rr);
-  if (go) xr_body<R>(d, k, tile, (R)as.alpha, pslot, sh);
+  if (go) xr_body<R, true>(d, k, tile, (R)as.alpha, pslot, sh);
 }
 
 // R3 fused: the FP64 residual step (converged, broken down, or restart the
@@ -1112,6 +1148,28 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
 
 // ========================================================= reliable update
 
+// R0: x_lo += alpha p for sources waiting for an update whose last x/r step
+// left that term pending (launch-per-pass and persistent engines), in the
+// arithmetic of xr_body.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ru_xfix(const SysDesc* __restrict__ sys, int nsys,
+                                                 const SrcState* st, int xcd) {
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const SrcState& q = st[d.src0 + k];
+  const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
+  if (q.phase != PH_RU || !q.xpend || e >= n) return;
+  const size_t vs = n * d.nsrc, i = k * n + e;
+  const R al = (R)q.alpha;
+  const cplx<R> pv = slot<R>(d.vlo, 2, vs)[i];
+  cplx<R>* x = slot<R>(d.vlo, 0, vs);
+  cplx<R> xv = x[i];
+  xv.re = fma(al, pv.re, xv.re);
+  xv.im = fma(al, pv.im, xv.im);
+  x[i] = xv;
+}
+
 // R1: t_hi = 2 D_oe (x_hi + x_lo) in FP64 for sources waiting for an update.
 template <typename Rlo, int RECON, int NBT>
 __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
@@ -1330,7 +1388,14 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   // pass, except at the end of a chunk (the host reads the states there)
   const bool handoff = c.fused && c.two && !last;
   SrcState* copy = c.fused && !handoff ? c.d_st1 : nullptr;
-  hipError_t e = with_nbt(rsh.nbt, [&]<int NBT>() {
+  hipError_t e = hipSuccess;
+  if (!c.fused) {
+    QX_TIMED(c, PASS_UPDATE, s,
+             hipLaunchKernelGGL(k_ru_xfix<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                                c.shape.xcd));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = with_nbt(rsh.nbt, [&]<int NBT>() {
     QX_TIMED(c, PASS_UPDATE, s,
              hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
                                 c.d_st, c.shape.xcd));

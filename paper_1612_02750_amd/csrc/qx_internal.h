@@ -60,6 +60,8 @@ struct SrcState {
   int iters, updates, max_iter;
   int pend;         // p is still to be replaced by r + beta p (done by the next p pass)
   int have_rr;      // |r|^2 partials of the last x/r update await the beta step (fused engine)
+  int xpend;        // x_lo still lacks alpha p of the last x/r step (launch-per-pass and
+                    // persistent engines: the next p pass or reliable update adds it)
 };
 
 // One system of a solver launch: a lattice, its links in the inner precision
