@@ -101,8 +101,8 @@ PASS_BYTES = {
     # pass: (bytes per output site per launch, per served source)
     "doe": (LINK_B_F32_12, 2 * VEC_B_F32),   # p read, t written
     "deo": (LINK_B_F32_12, 3 * VEC_B_F32),   # t and p read, A p written
-    "xr": (0, 6 * VEC_B_F32),                # x, r, p, A p read; x, r written
-    "p": (0, 3 * VEC_B_F32),                 # r, p read; p written
+    "xr": (0, 3 * VEC_B_F32),                # r, A p read; r written (x += alpha p deferred)
+    "p": (0, 5 * VEC_B_F32),                 # r, p, x read; p, x written
 }
 
 # HBM-side bytes per launch of the dominant kernel (k_iter_deo of the
@@ -449,6 +449,20 @@ def multi_rhs_extras(torch, qx, synth, h):
     out["mixed_f16_links_batch_12_ms"] = round(t * 1e3, 2)
     out["mixed_f16_links_iters_max"] = max(s.iters for s in st16)
     del b16, x16
+    # the same batch in one cooperative launch per chunk of iterations (grid
+    # barriers between the passes), beside the launch-per-pass headline
+    xp = torch.empty_like(bd)
+    bp = qx.Batch([(g64, g32, bd, [m] * nsrc, xp)], tol=1e-10, mode=qx.CG_MIXED_F32,
+                  engine=qx.ENGINE_PERSISTENT)
+    bp.solve()
+    runs, stp = [], None
+    for _ in range(3):
+        t, stp = _sync_time(torch, bp.solve)
+        runs.append(round(t * 1e3, 2))
+    out["persistent_engine_batch_12"] = {
+        "ms": sorted(runs)[1], "runs_ms": runs, "iters_max": max(q.iters for q in stp),
+        "true_rel_residual_max": max(q.true_rel_residual for q in stp)}
+    del bp, xp
     one = {}
     for name, glo in (("f32_links", g32), ("f16_links", g16)):
         x1 = torch.empty_like(bd[:1])
@@ -461,6 +475,7 @@ def multi_rhs_extras(torch, qx, synth, h):
         del b1, x1
     out["one_source_mixed"] = one
     out["max_true_rel_residual"] = max([s.true_rel_residual for s in st16] +
+                                       [out["persistent_engine_batch_12"]["true_rel_residual_max"]] +
                                        [v["true_rel_residual"] for v in one.values()])
     log(f"32^4 x 12 sources, FP16 inner links and one source: {out}")
     return out

@@ -215,17 +215,36 @@ __host__ __device__ __forceinline__ int tile_block(int bl, const Geo& g, int ord
 // elements), so the load takes the scalar-base + 32-bit-lane-offset form and
 // costs one VGPR of address instead of a 64-bit pointer per element.  NT: a
 // non-temporal load, which streams past the caches.
+// The access goes through a global-address-space pointer: a generic pointer
+// would make it a flat access, which has no scalar-base form and takes a
+// 64-bit address per lane.  Every array read or written through these
+// helpers is in device memory.
+#define QX_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const QX_GLOBAL T* as_global(const void* p) {
+  return (const QX_GLOBAL T*)p;
+}
+// Element idx of a T array in device memory, the byte offset formed in 32
+// bits (scalar base + 32-bit lane offset addressing).
+template <typename T>
+__device__ __forceinline__ const QX_GLOBAL T* global_elem(const void* base, unsigned idx) {
+  return (const QX_GLOBAL T*)((const QX_GLOBAL char*)base + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ QX_GLOBAL T* as_global_w(void* p) {
+  return (QX_GLOBAL T*)p;
+}
+
 template <bool NT, typename R>
 __device__ __forceinline__ cplx<R> ld_cplx(const cplx<R>* __restrict__ base, unsigned idx) {
-  const cplx<R>* p =
-      reinterpret_cast<const cplx<R>*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(cplx<R>));
-  if constexpr (NT) {
-    typedef R v2 __attribute__((ext_vector_type(2)));
-    const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
-    return {t.x, t.y};
-  } else {
-    return *p;
-  }
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const QX_GLOBAL v2* q = global_elem<v2>(base, idx);
+  v2 t;
+  if constexpr (NT)
+    t = __builtin_nontemporal_load(q);
+  else
+    t = *q;
+  return {t.x, t.y};
 }
 
 // Element idx of an array of complex numbers stored as S, returned in the
@@ -233,8 +252,7 @@ __device__ __forceinline__ cplx<R> ld_cplx(const cplx<R>* __restrict__ base, uns
 template <bool NT, typename R, typename S>
 __device__ __forceinline__ cplx<R> ld_cplx_as(const cplx<S>* __restrict__ base, unsigned idx) {
   if constexpr (std::is_same_v<S, __half>) {
-    const unsigned* p = reinterpret_cast<const unsigned*>(reinterpret_cast<const char*>(base) +
-                                                          idx * (unsigned)sizeof(cplx<S>));
+    const QX_GLOBAL unsigned* p = global_elem<unsigned>(base, idx);
     unsigned w;
     if constexpr (NT)
       w = __builtin_nontemporal_load(p);
@@ -271,14 +289,14 @@ template <int NW, bool NT>
 __device__ __forceinline__ void ld_words(const char* __restrict__ base, unsigned off,
                                          unsigned (&w)[NW]) {
   if constexpr (NW == 1) {
-    const unsigned* q = reinterpret_cast<const unsigned*>(base + off);
+    const QX_GLOBAL unsigned* q = as_global<unsigned>(base + off);
     if constexpr (NT)
       w[0] = __builtin_nontemporal_load(q);
     else
       w[0] = *q;
   } else {
     typedef unsigned vw __attribute__((ext_vector_type(NW)));
-    const vw* q = reinterpret_cast<const vw*>(base + off);
+    const QX_GLOBAL vw* q = as_global<vw>(base + off);
     vw t;
     if constexpr (NT)
       t = __builtin_nontemporal_load(q);
@@ -394,8 +412,7 @@ struct FieldInH {
   __device__ __forceinline__ cplx<float> operator()(int j, int c, int site) const {
     const int jj = j < jmax ? j : jmax;
     // the three colours of a site read the same record: one load after CSE
-    const qx_u32x4 r =
-        reinterpret_cast<const qx_u32x4*>(p + (size_t)jj * 16 * hv)[(unsigned)site];
+    const qx_u32x4 r = *global_elem<qx_u32x4>(p + (size_t)jj * 16 * hv, (unsigned)site);
     return h2_scaled(c == 0 ? r.x : c == 1 ? r.y : r.z, __uint_as_float(r.w));
   }
 };
@@ -403,15 +420,15 @@ struct FieldInH {
 // *p = v, non-temporally when nt (outputs the next pass reads from far away).
 template <typename R>
 __device__ __forceinline__ void st_cplx(cplx<R>* p, const cplx<R>& v, bool nt) {
-  if (nt) {
-    typedef R v2 __attribute__((ext_vector_type(2)));
-    v2 t;
-    t.x = v.re;
-    t.y = v.im;
-    __builtin_nontemporal_store(t, reinterpret_cast<v2*>(p));
-  } else {
-    *p = v;
-  }
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  v2 t;
+  t.x = v.re;
+  t.y = v.im;
+  QX_GLOBAL v2* q = as_global_w<v2>(p);
+  if (nt)
+    __builtin_nontemporal_store(t, q);
+  else
+    *q = t;
 }
 
 // Store the colour vector v of site cb into an FP16 source (layout of
