@@ -490,6 +490,12 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   __syncthreads();  // the shared scratch is reused by the next tile
 }
 
+// |v|^2 in FP64 (one expression for every x/r pass, so that they round alike).
+template <typename R>
+__device__ __forceinline__ double norm2_d(const cplx<R>& v) {
+  return (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+}
+
 // x_lo += alpha p, r -= alpha Ap over vector tile `tile` of source k of a
 // system, and the partial of |r|^2.  Works for any block size.
 // (UPDATE_X false: r only; x_lo += alpha p is left pending, SrcState::xpend.)
@@ -502,19 +508,20 @@ __device__ __forceinline__ void xr_body(const SysDesc& d, int k, int tile, R al,
   const cplx<R>* p = slot<R>(d.vlo, pslot, vs) + k * n;
   const cplx<R>* Ap = slot<R>(d.vlo, 3, vs) + k * n;
   const double t = tile_sum(tile, n, sh, [&](size_t e) {
-    const cplx<R> av = Ap[e];
-    cplx<R> rv = r[e];
+    const unsigned u = (unsigned)e;
+    const cplx<R> av = ld_cplx<false>(Ap, u);
+    cplx<R> rv = ld_cplx<false>(r, u);
     if constexpr (UPDATE_X) {
-      const cplx<R> pv = p[e];
-      cplx<R> xv = x[e];
+      const cplx<R> pv = ld_cplx<false>(p, u);
+      cplx<R> xv = ld_cplx<false>(x, u);
       xv.re = fma(al, pv.re, xv.re);
       xv.im = fma(al, pv.im, xv.im);
-      x[e] = xv;
+      st_cplx(x + e, xv, false);
     }
     rv.re = fma(-al, av.re, rv.re);
     rv.im = fma(-al, av.im, rv.im);
-    r[e] = rv;
-    return (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+    st_cplx(r + e, rv, false);
+    return norm2_d(rv);
   });
   if (threadIdx.x == 0) d.partials_v[(size_t)k * d.vtiles + tile] = t;
 }
@@ -531,14 +538,15 @@ __device__ __forceinline__ void p_body(const SysDesc& d, int k, int tile, R be, 
   for (int t = threadIdx.x; t < kVTile; t += blockDim.x) {
     const size_t e = (size_t)tile * kVTile + t;
     if (e >= n) break;
-    const cplx<R> rv = r[e], pv = p[e];
+    const unsigned u = (unsigned)e;
+    const cplx<R> rv = ld_cplx<false>(r, u), pv = ld_cplx<false>(p, u);
     if (xp) {
-      cplx<R> xv = x[e];
+      cplx<R> xv = ld_cplx<false>(x, u);
       xv.re = fma(al, pv.re, xv.re);
       xv.im = fma(al, pv.im, xv.im);
-      x[e] = xv;
+      st_cplx(x + e, xv, false);
     }
-    p[e] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+    st_cplx(p + e, cplx<R>{fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)}, false);
   }
 }
 
@@ -564,10 +572,47 @@ __device__ __forceinline__ void p_tile(const SysDesc* __restrict__ sys, int nsys
   p_body<R>(d, k, tile, (R)rd<FRESH>(q.beta), rd<FRESH>(q.xpend) != 0, (R)rd<FRESH>(q.alpha));
 }
 
+// The p pass of the launch-per-pass engine: one wavefront per vector tile,
+// four elements per lane with all their loads issued before the stores (the
+// arithmetic of p_body).
 template <typename R>
-__global__ void __launch_bounds__(256) k_iter_p(const SysDesc* __restrict__ sys, int nsys,
-                                                const SrcState* st, int xcd) {
-  p_tile<R, false>(sys, nsys, st, logical_block(xcd));
+__global__ void __launch_bounds__(64) k_iter_p(const SysDesc* __restrict__ sys, int nsys,
+                                               const SrcState* st, int xcd) {
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const SrcState& q = st[d.src0 + k];
+  if (q.phase != PH_RUN || !q.pend) return;
+  const bool xp = q.xpend != 0;
+  const R be = (R)q.beta, al = (R)q.alpha;
+  const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
+  const cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
+  cplx<R>* p = slot<R>(d.vlo, 2, vs) + k * n;
+  cplx<R>* x = slot<R>(d.vlo, 0, vs) + k * n;
+  constexpr int U = kVTile / 64;
+  const unsigned e0 = (unsigned)tile * kVTile + threadIdx.x;
+  // elements past n (the last tile of a source) read and write nothing
+  const unsigned last = (unsigned)n - 1;
+  cplx<R> rv[U], pv[U], xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const unsigned e = e0 + 64 * u, ec = e < last ? e : last;
+    rv[u] = ld_cplx<false>(r, ec);
+    pv[u] = ld_cplx<false>(p, ec);
+    xv[u] = xp ? ld_cplx<false>(x, ec) : cplx<R>{(R)0, (R)0};
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const unsigned e = e0 + 64 * u;
+    if (e > last) break;
+    if (xp) {
+      cplx<R> xn = xv[u];
+      xn.re = fma(al, pv[u].re, xn.re);
+      xn.im = fma(al, pv[u].im, xn.im);
+      st_cplx(x + e, xn, false);
+    }
+    st_cplx(p + e, cplx<R>{fma(be, pv[u].re, rv[u].re), fma(be, pv[u].im, rv[u].im)}, false);
+  }
 }
 
 template <typename R, int RECON, int NBT, int LPS, typename LS>
@@ -586,11 +631,52 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDes
   deo_tile<R, RECON, NBT, LPS, false, LS>(sys, nsys, st, logical_block(xcd), xcd, pslot, sh, tot);
 }
 
+// The x/r pass of the launch-per-pass engine (x_lo += alpha p deferred): one
+// wavefront per vector tile, four elements per lane with their loads issued
+// together; the tile's |r|^2 partial is tile_sum's (a butterfly per 64
+// elements, the four added in order), so it matches xr_body bit for bit.
 template <typename R>
-__global__ void __launch_bounds__(256) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
-                                                 const SrcState* st, int xcd) {
-  __shared__ double sh[16];
-  xr_tile<R, false>(sys, nsys, st, logical_block(xcd), sh);
+__global__ void __launch_bounds__(64) k_iter_xr(const SysDesc* __restrict__ sys, int nsys,
+                                                const SrcState* st, int xcd) {
+  const int b = logical_block(xcd);
+  const SysDesc& d = sys_of_vblock(sys, nsys, b);
+  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+  const SrcState& q = st[d.src0 + k];
+  if (q.phase != PH_RUN) return;
+  const R al = (R)q.alpha;
+  const size_t n = (size_t)3 * d.g.hv, vs = n * d.nsrc;
+  cplx<R>* r = slot<R>(d.vlo, 1, vs) + k * n;
+  const cplx<R>* Ap = slot<R>(d.vlo, 3, vs) + k * n;
+  constexpr int U = kVTile / 64;
+  const unsigned e0 = (unsigned)tile * kVTile + threadIdx.x, last = (unsigned)n - 1;
+  cplx<R> av[U], rv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const unsigned e = e0 + 64 * u, ec = e < last ? e : last;
+    av[u] = ld_cplx<false>(Ap, ec);
+    rv[u] = ld_cplx<false>(r, ec);
+  }
+  double v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const unsigned e = e0 + 64 * u;
+    cplx<R> rn = rv[u];
+    rn.re = fma(-al, av[u].re, rn.re);
+    rn.im = fma(-al, av[u].im, rn.im);
+    v[u] = 0.0;
+    if (e <= last) {
+      st_cplx(r + e, rn, false);
+      v[u] = norm2_d(rn);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = wave_sum(v[u]);
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += v[u];
+    d.partials_v[(size_t)k * d.vtiles + tile] = t;
+  }
 }
 
 // ------------------------------------------------- fused launch sequence
@@ -1355,7 +1441,7 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   constexpr bool kWide = sizeof(R) == 4 && RECON != 36 && std::is_same_v<LS, R>;
   hipError_t e = with_nbt_lps<kWide>(c.shape.nbt, c.shape.lps, [&]<int NBT, int LPS>() {
     QX_TIMED(c, PASS_P, s,
-             hipLaunchKernelGGL(k_iter_p<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+             hipLaunchKernelGGL(k_iter_p<R>, vgrid, dim3(64), 0, s, c.d_sys, c.nsys, c.d_st,
                                 c.shape.xcd));
     QX_TIMED(c, PASS_DOE, s,
              hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
@@ -1368,7 +1454,7 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   if (e == hipSuccess) e = finalize(c, FIN_ALPHA, s);
   if (e == hipSuccess) {
     QX_TIMED(c, PASS_XR, s,
-             hipLaunchKernelGGL(k_iter_xr<R>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+             hipLaunchKernelGGL(k_iter_xr<R>, vgrid, dim3(64), 0, s, c.d_sys, c.nsys, c.d_st,
                                 c.shape.xcd));
     e = hipGetLastError();
   }
