@@ -1234,34 +1234,41 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
 
 // ========================================================= reliable update
 
+// The update kernels run in every update slot, usually with nothing to do:
+// they take a grid of at most kUpdGrid blocks that strides over the stencil
+// blocks or vector tiles, so that an idle launch costs little (the GPU
+// dispatches about one workgroup per clock: an idle grid of one block per
+// vector tile of a 32^4 twelve-source batch, 73 728 blocks, takes 30 us).
+constexpr int kUpdGrid = 2048;
+
 // R0: x_lo += alpha p for sources waiting for an update whose last x/r step
 // left that term pending (launch-per-pass and persistent engines), in the
 // arithmetic of xr_body.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ru_xfix(const SysDesc* __restrict__ sys, int nsys,
-                                                 const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
-  const SrcState& q = st[d.src0 + k];
-  const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
-  if (q.phase != PH_RU || !q.xpend || e >= n) return;
-  const size_t vs = n * d.nsrc, i = k * n + e;
-  const R al = (R)q.alpha;
-  const cplx<R> pv = slot<R>(d.vlo, 2, vs)[i];
-  cplx<R>* x = slot<R>(d.vlo, 0, vs);
-  cplx<R> xv = x[i];
-  xv.re = fma(al, pv.re, xv.re);
-  xv.im = fma(al, pv.im, xv.im);
-  x[i] = xv;
+                                                 const SrcState* st, int nvblk) {
+  for (int b = blockIdx.x; b < nvblk; b += gridDim.x) {
+    const SysDesc& d = sys_of_vblock(sys, nsys, b);
+    const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+    const SrcState& q = st[d.src0 + k];
+    const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
+    if (q.phase != PH_RU || !q.xpend || e >= n) continue;
+    const size_t vs = n * d.nsrc, i = k * n + e;
+    const R al = (R)q.alpha;
+    const cplx<R> pv = slot<R>(d.vlo, 2, vs)[i];
+    cplx<R>* x = slot<R>(d.vlo, 0, vs);
+    cplx<R> xv = x[i];
+    xv.re = fma(al, pv.re, xv.re);
+    xv.im = fma(al, pv.im, xv.im);
+    x[i] = xv;
+  }
 }
 
 // R1: t_hi = 2 D_oe (x_hi + x_lo) in FP64 for sources waiting for an update.
 template <typename Rlo, int RECON, int NBT>
-__global__ void __launch_bounds__((kMaxThreads<double, NBT>))
-    k_ru_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int xcd) {
+__device__ __forceinline__ void ru_doe_block(const SysDesc* __restrict__ sys, int nsys,
+                                             const SrcState* st, int b, int xcd) {
   const int lane = threadIdx.x & 63, grp = wave_id();
-  const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const unsigned long long ru = phase_bits<false>(st + d.src0, d.nsrc, PH_RU);
   const int cb = tile_block(b - d.blk0, d.g, xcd) * kTile + lane;
@@ -1287,6 +1294,12 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
   }
 }
 
+template <typename Rlo, int RECON, int NBT>
+__global__ void __launch_bounds__((kMaxThreads<double, NBT>))
+    k_ru_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int nblk, int xcd) {
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) ru_doe_block<Rlo, RECON, NBT>(sys, nsys, st, b, xcd);
+}
+
 // R2: x_hi += x_lo, x_lo = 0, r_hi = b - (m^2 x_hi - 1/4 (2D_eo) t_hi) and the
 // partials of |r_hi|^2, all in FP64.
 // st_copy (fused sequence, else null): the system's first block copies its
@@ -1295,13 +1308,11 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
 // the r slot and flag the updating sources (have_rr) for k_f2_doe, which takes
 // the update's last step.
 template <typename Rlo, int RECON, int NBT>
-__global__ void __launch_bounds__((kMaxThreads<double, NBT>))
-    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int xcd,
-                  SrcState* st_copy, int mark) {
-  __shared__ double sh[16 * 64];
-  __shared__ double tot[64];
+__device__ __forceinline__ void ru_residual_block(const SysDesc* __restrict__ sys, int nsys,
+                                                  SrcState* st, int b, int xcd,
+                                                  SrcState* st_copy, int mark, double* sh,
+                                                  double* tot) {
   const int lane = threadIdx.x & 63, grp = wave_id();
-  const int b = logical_block(xcd);
   const SysDesc& d = sys_of_block(sys, nsys, b);
   const SrcState* q0 = st + d.src0;
   if (st_copy && b == d.blk0)
@@ -1361,24 +1372,37 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
       if (ru >> k & 1ull) d.partials[(size_t)k * d.nblk + bl] = tot[k];
 }
 
+template <typename Rlo, int RECON, int NBT>
+__global__ void __launch_bounds__((kMaxThreads<double, NBT>))
+    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int nblk, int xcd,
+                  SrcState* st_copy, int mark) {
+  __shared__ double sh[16 * 64];
+  __shared__ double tot[64];
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    ru_residual_block<Rlo, RECON, NBT>(sys, nsys, st, b, xcd, st_copy, mark, sh, tot);
+    __syncthreads();  // sh and tot serve the next block
+  }
+}
+
 // R3: r = lo(r_hi), p = r + beta p for sources whose update did not converge.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ru_finish(const SysDesc* __restrict__ sys, int nsys,
-                                                   const SrcState* st, int xcd) {
-  const int b = logical_block(xcd);
-  const SysDesc& d = sys_of_vblock(sys, nsys, b);
-  const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
-  const SrcState& q = st[d.src0 + k];
-  const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
-  if (q.phase != PH_RU2 || e >= n) return;
-  const size_t vs = n * d.nsrc, i = k * n + e;
-  const R be = (R)q.beta;
-  const cplx<double> h = slot<double>(d.vhi, 1, vs)[i];
-  const cplx<R> rv = {(R)h.re, (R)h.im};
-  cplx<R>* p = slot<R>(d.vlo, 2, vs);
-  const cplx<R> pv = p[i];
-  slot<R>(d.vlo, 1, vs)[i] = rv;
-  p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+                                                   const SrcState* st, int nvblk) {
+  for (int b = blockIdx.x; b < nvblk; b += gridDim.x) {
+    const SysDesc& d = sys_of_vblock(sys, nsys, b);
+    const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
+    const SrcState& q = st[d.src0 + k];
+    const size_t n = (size_t)3 * d.g.hv, e = (size_t)tile * kVTile + threadIdx.x;
+    if (q.phase != PH_RU2 || e >= n) continue;
+    const size_t vs = n * d.nsrc, i = k * n + e;
+    const R be = (R)q.beta;
+    const cplx<double> h = slot<double>(d.vhi, 1, vs)[i];
+    const cplx<R> rv = {(R)h.re, (R)h.im};
+    cplx<R>* p = slot<R>(d.vlo, 2, vs);
+    const cplx<R> pv = p[i];
+    slot<R>(d.vlo, 1, vs)[i] = rv;
+    p[i] = {fma(be, pv.re, rv.re), fma(be, pv.im, rv.im)};
+  }
 }
 
 // =============================================== host side, one type pair
@@ -1474,20 +1498,22 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   // pass, except at the end of a chunk (the host reads the states there)
   const bool handoff = c.fused && c.two && !last;
   SrcState* copy = c.fused && !handoff ? c.d_st1 : nullptr;
+  // capped grids (kUpdGrid): most update slots find nothing to do
+  const dim3 ugrid(std::min(c.nblk_total, kUpdGrid)), uvgrid(std::min(c.nvblk_total, kUpdGrid));
   hipError_t e = hipSuccess;
   if (!c.fused) {
     QX_TIMED(c, PASS_UPDATE, s,
-             hipLaunchKernelGGL(k_ru_xfix<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                                c.shape.xcd));
+             hipLaunchKernelGGL(k_ru_xfix<Rlo>, uvgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                                c.nvblk_total));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = with_nbt(rsh.nbt, [&]<int NBT>() {
     QX_TIMED(c, PASS_UPDATE, s,
-             hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys, c.nsys,
-                                c.d_st, c.shape.xcd));
+             hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), ugrid, sblock, 0, s, c.d_sys, c.nsys,
+                                c.d_st, c.nblk_total, c.shape.xcd));
     QX_TIMED(c, PASS_UPDATE, s,
-             hipLaunchKernelGGL((k_ru_residual<Rlo, RECON, NBT>), sgrid, sblock, 0, s, c.d_sys,
-                                c.nsys, c.d_st, c.shape.xcd, copy, handoff ? 1 : 0));
+             hipLaunchKernelGGL((k_ru_residual<Rlo, RECON, NBT>), ugrid, sblock, 0, s, c.d_sys,
+                                c.nsys, c.d_st, c.nblk_total, c.shape.xcd, copy, handoff ? 1 : 0));
     return hipGetLastError();
   });
   if (handoff) return e;
@@ -1503,8 +1529,8 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   if (e == hipSuccess) e = finalize(c, FIN_RU, s);
   if (e == hipSuccess) {
     QX_TIMED(c, PASS_UPDATE, s,
-             hipLaunchKernelGGL(k_ru_finish<Rlo>, vgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                                c.shape.xcd));
+             hipLaunchKernelGGL(k_ru_finish<Rlo>, uvgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
+                                c.nvblk_total));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = finalize(c, FIN_COMMIT, s);
