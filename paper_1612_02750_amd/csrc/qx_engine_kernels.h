@@ -142,10 +142,17 @@ __device__ __forceinline__ double tile_sum(int tile, size_t n, double* sh, F&& f
 // wavefront of 64 lanes reduced by one butterfly, the four wavefront sums
 // added in order.  Every thread of the block calls it (the block is a whole
 // number of wavefronts) and every thread gets the result.  sh: 4 doubles.
-// A virtual lane's values are loaded eight at a time before they are added
-// (in the same order), so that a lane has eight loads in flight.
+// A virtual lane's values are loaded 32 (then 8) at a time before they are
+// added (in the same order), so that a lane has that many loads in flight.
 __device__ __forceinline__ double lane_sum(const double* __restrict__ a, int i, int n) {
   double v = 0.0;
+  for (; i + 31 * 256 < n; i += 32 * 256) {
+    double t[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) t[u] = a[i + u * 256];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) v += t[u];
+  }
   for (; i + 7 * 256 < n; i += 8 * 256) {
     double t[8];
 #pragma unroll
