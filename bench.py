@@ -51,6 +51,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MALL_BYTES = 256 << 20  # Infinity Cache of the MI355X
 FLOPS_SITE = 570
 FLOPS_SITE_NAIK = 1146  # 16 SU(3) x colour-vector products + 15 vector sums
 
@@ -70,6 +71,10 @@ def parse():
                     help="only the timed step, its FP64 comparisons and its pass timing")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the dominant-kernel timing and the copy probe (for counter runs)")
+    ap.add_argument("--dslash-point", default=None, metavar="NBT,LPS,ORDER,NRHS",
+                    help="only the standalone 32^4 FP32-12 half-Dslash of NRHS sources under "
+                         "the given shape: three plain launches and a graph-timed figure "
+                         "(for counter runs)")
     return ap.parse_args()
 
 
@@ -259,11 +264,17 @@ def _dslash_point(torch, qx, g, lat, nrhs, seed, link_b, vec_b, reps, plain, key
     # median of three timings of `reps` graph-replayed launches each
     t = sorted(qx.time_dslash(g, pin, 0, nrhs, out=pout, reps=reps) for _ in range(3))[1]
     by = (link_b + 2 * vec_b * nrhs) * lat.hv
+    # every operand of the launch (all links, the input and output vectors)
+    # fits the 256 MB Infinity Cache: the fraction is then a cache-served
+    # figure, not an HBM one
+    resident = by <= MALL_BYTES
     out[key] = {
         "us": round(t * 1e6, 2),
         "gflops": round(flops_site * nrhs * lat.hv / t / 1e9, 1),
         "gbs_algorithmic": round(by / t / 1e9, 1),
         "frac_hbm_peak": round(by / t / 1e9 / HBM_PEAK_GBS, 3),
+        "operands_mb": round(by / 1e6, 1),
+        "cache_resident": resident,
         "shape": list(g.launch(nrhs)),
     }
     log(f"{key}: {out[key]}")
@@ -513,6 +524,25 @@ def f16_links_weak32(torch, qx, synth):
     return out
 
 
+def dslash_point(torch, qx, synth, spec):
+    """The half-Dslash of the sweep's 32^4 FP32-12 point (Haar links, seed 0;
+    Gaussian sources, seed 1) for nrhs sources under a fixed launch shape:
+    three plain launches (what a counter run reads), then the graph-timed
+    average of 20."""
+    nbt, lps, order, nrhs = (int(v) for v in spec.split(","))
+    dims = (32, 32, 32, 32)
+    lat = qx.Lattice(dims)
+    g = qx.Gauge(lat, torch.from_numpy(synth.haar_gauge(dims, 0)).cuda(), "f32", 12)
+    xin = qx.pack(lat, torch.from_numpy(synth.gauss_source(nrhs, lat.hv, 1)).cuda(), "f32")
+    g.set_launch(nrhs, nbt, lps, order)
+    out = None
+    for _ in range(3):
+        out = qx.dslash(g, xin, 0, nrhs, out=out)
+    torch.cuda.synchronize()
+    t = qx.time_dslash(g, xin, 0, nrhs, out=out, reps=20)
+    return {"dslash_point": [nbt, lps, order, nrhs], "us": round(t * 1e6, 2)}
+
+
 def kernels_only(torch, qx, synth, shape):
     """Counter runs: the step's batch under the given solver launch shape,
     its first two chunks (32 iterations, every source served), eagerly."""
@@ -727,6 +757,10 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
+
+    if args.dslash_point:
+        print(json.dumps(dslash_point(torch, qx, synth, args.dslash_point)))
+        return
 
     if args.kernels_only:
         shape = [int(v) for v in (args.solver_shape or "4,2,0").split(",")]

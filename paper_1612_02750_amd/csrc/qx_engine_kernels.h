@@ -1248,12 +1248,24 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
 // vector tile of a 32^4 twelve-source batch, 73 728 blocks, takes 30 us).
 constexpr int kUpdGrid = 2048;
 
+// Does any source of the batch (all nsrc states) stand in `phase` (with
+// xpend set, when xp)?  The whole block answers at once, one state per
+// thread, so that an update kernel with nothing to do returns after one load
+// instead of visiting its blocks' states one after another.
+__device__ __forceinline__ bool any_source_in(const SrcState* st, int nsrc, int phase, bool xp) {
+  int hit = 0;
+  for (int k = threadIdx.x; k < nsrc; k += blockDim.x)
+    hit |= st[k].phase == phase && (!xp || st[k].xpend);
+  return __syncthreads_or(hit) != 0;
+}
+
 // R0: x_lo += alpha p for sources waiting for an update whose last x/r step
 // left that term pending (launch-per-pass and persistent engines), in the
 // arithmetic of xr_body.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ru_xfix(const SysDesc* __restrict__ sys, int nsys,
-                                                 const SrcState* st, int nvblk) {
+                                                 const SrcState* st, int nsrc, int nvblk) {
+  if (!any_source_in(st, nsrc, PH_RU, true)) return;
   for (int b = blockIdx.x; b < nvblk; b += gridDim.x) {
     const SysDesc& d = sys_of_vblock(sys, nsys, b);
     const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
@@ -1303,7 +1315,9 @@ __device__ __forceinline__ void ru_doe_block(const SysDesc* __restrict__ sys, in
 
 template <typename Rlo, int RECON, int NBT>
 __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
-    k_ru_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int nblk, int xcd) {
+    k_ru_doe(const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int nsrc, int nblk,
+             int xcd) {
+  if (!any_source_in(st, nsrc, PH_RU, false)) return;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) ru_doe_block<Rlo, RECON, NBT>(sys, nsys, st, b, xcd);
 }
 
@@ -1381,10 +1395,12 @@ __device__ __forceinline__ void ru_residual_block(const SysDesc* __restrict__ sy
 
 template <typename Rlo, int RECON, int NBT>
 __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
-    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int nblk, int xcd,
-                  SrcState* st_copy, int mark) {
+    k_ru_residual(const SysDesc* __restrict__ sys, int nsys, SrcState* st, int nsrc, int nblk,
+                  int xcd, SrcState* st_copy, int mark) {
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
+  // the state copy of the fused sequence is wanted even when nothing updates
+  if (!st_copy && !any_source_in(st, nsrc, PH_RU, false)) return;
   for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
     ru_residual_block<Rlo, RECON, NBT>(sys, nsys, st, b, xcd, st_copy, mark, sh, tot);
     __syncthreads();  // sh and tot serve the next block
@@ -1394,7 +1410,8 @@ __global__ void __launch_bounds__((kMaxThreads<double, NBT>))
 // R3: r = lo(r_hi), p = r + beta p for sources whose update did not converge.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ru_finish(const SysDesc* __restrict__ sys, int nsys,
-                                                   const SrcState* st, int nvblk) {
+                                                   const SrcState* st, int nsrc, int nvblk) {
+  if (!any_source_in(st, nsrc, PH_RU2, false)) return;
   for (int b = blockIdx.x; b < nvblk; b += gridDim.x) {
     const SysDesc& d = sys_of_vblock(sys, nsys, b);
     const int rel = b - d.vblk0, k = rel / d.vtiles, tile = rel - k * d.vtiles;
@@ -1511,16 +1528,17 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   if (!c.fused) {
     QX_TIMED(c, PASS_UPDATE, s,
              hipLaunchKernelGGL(k_ru_xfix<Rlo>, uvgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                                c.nvblk_total));
+                                c.nsrc_total, c.nvblk_total));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = with_nbt(rsh.nbt, [&]<int NBT>() {
     QX_TIMED(c, PASS_UPDATE, s,
              hipLaunchKernelGGL((k_ru_doe<Rlo, RECON, NBT>), ugrid, sblock, 0, s, c.d_sys, c.nsys,
-                                c.d_st, c.nblk_total, c.shape.xcd));
+                                c.d_st, c.nsrc_total, c.nblk_total, c.shape.xcd));
     QX_TIMED(c, PASS_UPDATE, s,
              hipLaunchKernelGGL((k_ru_residual<Rlo, RECON, NBT>), ugrid, sblock, 0, s, c.d_sys,
-                                c.nsys, c.d_st, c.nblk_total, c.shape.xcd, copy, handoff ? 1 : 0));
+                                c.nsys, c.d_st, c.nsrc_total, c.nblk_total, c.shape.xcd, copy,
+                                handoff ? 1 : 0));
     return hipGetLastError();
   });
   if (handoff) return e;
@@ -1537,7 +1555,7 @@ hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
   if (e == hipSuccess) {
     QX_TIMED(c, PASS_UPDATE, s,
              hipLaunchKernelGGL(k_ru_finish<Rlo>, uvgrid, vblock, 0, s, c.d_sys, c.nsys, c.d_st,
-                                c.nvblk_total));
+                                c.nsrc_total, c.nvblk_total));
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = finalize(c, FIN_COMMIT, s);
