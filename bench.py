@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the 32^4 FP16-link and one-source comparisons")
     ap.add_argument("--solver-shape", default=None,
-                    help="nbt,lps,order of the step's batch instead of its tuner (profiler runs)")
+                    help="nbt,lps,order[,deo_nbt,deo_lps] of the step's batch instead of its "
+                         "tuner (profiler runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the timed step, its FP64 comparisons and its pass timing")
     ap.add_argument("--kernels-only", action="store_true",
@@ -190,11 +191,12 @@ def headline(torch, qx, synth, args):
     x_mx = torch.empty_like(bd)
     mixed = qx.Batch([(g64, g32, bd, [m] * nsrc, x_mx)], tol=tol, mode=qx.CG_MIXED_F32)
     if args.solver_shape:  # a fixed shape (profiler runs), else the solver's own tuner
-        shape = [int(v) for v in args.solver_shape.split(",")]
-        mixed.set_launch(*shape)
+        set_solver_shape(mixed, args.solver_shape)
     else:
-        shape = list(mixed.tune(2))
-    log(f"step: solver launch shape {shape}")
+        mixed.tune(2)
+    main_shape, deo_shape = mixed.launch()
+    shape = list(main_shape) + list(deo_shape)
+    log(f"step: solver launch shape {shape} (nbt, lps, order; D_eo nbt, lps)")
     for _ in range(args.warmup):
         mixed.solve()
     times, st = [], None
@@ -543,14 +545,23 @@ def dslash_point(torch, qx, synth, spec):
     return {"dslash_point": [nbt, lps, order, nrhs], "us": round(t * 1e6, 2)}
 
 
-def kernels_only(torch, qx, synth, shape):
+def set_solver_shape(B, spec):
+    """spec "nbt,lps,order" or "nbt,lps,order,deo_nbt,deo_lps" (the D_eo pass
+    of the launch-per-pass engine under a shape of its own)."""
+    v = [int(x) for x in spec.split(",")]
+    B.set_launch(*v[:3])
+    if len(v) == 5 and tuple(v[3:]) != tuple(v[:2]):
+        B.set_deo_launch(*v[3:])
+
+
+def kernels_only(torch, qx, synth, spec):
     """Counter runs: the step's batch under the given solver launch shape,
     its first two chunks (32 iterations, every source served), eagerly."""
     m = 0.02
     lat, g64, g32, bd = config3_system(torch, qx, synth)
     x = torch.empty_like(bd)
     B = qx.Batch([(g64, g32, bd, [m] * bd.shape[0], x)], tol=1e-10, mode=qx.CG_MIXED_F32)
-    B.set_launch(*shape)
+    set_solver_shape(B, spec)
     passes, st = B.profile(2)
     torch.cuda.synchronize()
     return pass_roofline(passes, lat.hv), [s.iters for s in st]
@@ -763,7 +774,7 @@ def main():
         return
 
     if args.kernels_only:
-        shape = [int(v) for v in (args.solver_shape or "4,2,0").split(",")]
+        shape = args.solver_shape or "4,2,0"
         roof, iters = kernels_only(torch, qx, synth, shape)
         copy_probe(torch, qx, timed=False)
         print(json.dumps({"kernels_only": True, "solver_shape": shape, "passes": roof,
@@ -780,7 +791,9 @@ def main():
     sha = kernel_sha()
     traffic = None
     if TRAFFIC["sha"] == sha:
-        traffic = TRAFFIC["bytes"].get(",".join(str(v) for v in h["shape"]))
+        # keyed by the D_eo pass's (nbt, lps) and the block order
+        sh = h["shape"]
+        traffic = TRAFFIC["bytes"].get(f"{sh[3]},{sh[4]},{sh[2]}")
     torch.cuda.empty_cache()
 
     extras = {}
@@ -823,7 +836,7 @@ def main():
                         "residual per source)",
             "lattice": [32, 32, 32, 32],
             "nrhs": 12,
-            "solver_launch_shape": h["shape"],
+            "solver_launch_shape": h["shape"],  # nbt, lps, order; D_eo pass nbt, lps
         },
         "step_times_ms": h["times_ms"],
         "cg_time_to_solution_ms": {
@@ -842,9 +855,9 @@ def main():
                           "fp64_max": h["fp64_iters_max"]},
         "max_true_rel_residual": h["max_true_rel_residual"],
         "roofline": {
-            "kernel": f"k_iter_deo<float, 12, {h['shape'][0]}, {h['shape'][1]}, float> "
+            "kernel": f"k_iter_deo<float, 12, {h['shape'][3]}, {h['shape'][4]}, float> "
                       f"(D_eo half-Dslash of the step with the A epilogue and <p, Ap> partials; "
-                      f"solver launch shape {h['shape']})",
+                      f"block order {h['shape'][2]})",
             "bound": "hbm",
             "achieved": deo["gbs"],
             "peak": HBM_PEAK_GBS,

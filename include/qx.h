@@ -307,9 +307,12 @@ int qx_batch_solve(qx_batch_t* batch, qx_cg_stats_t* stats, hipStream_t stream);
    may be NULL).  The Dslash tuner times the stencil kernel alone; the
    solver's passes read what the previous pass wrote, so their best shape can
    differ.  A solve's result depends on the shape only through the rounding
-   order of the hop sums.  Uses the batch's workspace, never writes the
-   systems' x, synchronises the stream.  QX_EINVAL for a NULL batch, nchunks
-   outside 1..64 or the persistent engine. */
+   order of the hop sums.  Under the launch-per-pass engine it then times the
+   D_eo pass under other (sources per thread, wavefronts per site) beside the
+   best shape and keeps one that makes the chunks faster
+   (qx_batch_get_launch reports it).  Uses the batch's workspace, never writes
+   the systems' x, synchronises the stream.  QX_EINVAL for a NULL batch,
+   nchunks outside 1..64 or the persistent engine. */
 int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps, int* order,
                   hipStream_t stream);
 
@@ -318,6 +321,22 @@ int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps, int* order
    same shape.  Synchronises the stream.  QX_EINVAL for a shape the batch
    cannot launch or the persistent engine. */
 int qx_batch_set_launch(qx_batch_t* batch, int nbt, int lps, int order, hipStream_t stream);
+
+/* The launch shape a batch's solver runs under: *nbt, *lps, *order for every
+   stencil pass, and *deo_nbt, *deo_lps for the launch-per-pass engine's D_eo
+   pass (equal to *nbt, *lps unless qx_batch_tune or qx_batch_set_deo_launch
+   chose otherwise; the other engines ignore them).  Any pointer may be NULL.
+   QX_EINVAL for a NULL batch. */
+int qx_batch_get_launch(qx_batch_t* batch, int* nbt, int* lps, int* order, int* deo_nbt,
+                        int* deo_lps);
+
+/* Run the launch-per-pass engine's D_eo pass with deo_nbt sources per thread
+   and deo_lps wavefronts per site (the block order stays the batch's), e.g.
+   to repeat a tuned solve; qx_batch_set_launch resets it.  Results depend on
+   it only through the rounding order of the hop sums.  Synchronises the
+   stream.  QX_EINVAL for a shape the batch cannot launch or an engine other
+   than the launch-per-pass one. */
+int qx_batch_set_deo_launch(qx_batch_t* batch, int deo_nbt, int deo_lps, hipStream_t stream);
 
 /* Pass kinds of the solver's launches (qx_batch_profile): the p update
    p = r + beta p, the half-Dslash D_oe (t = D_oe p, with whatever the engine

@@ -123,6 +123,8 @@ def load():
         "qx_batch_profile": ([_P, _I, _P, _P, _P], _I),
         "qx_apply_A_noalloc": ([_P, _I, _P, _P, _P, _P], _I),
         "qx_batch_set_launch": ([_P, _I, _I, _I, _P], _I),
+        "qx_batch_get_launch": ([_P, _P, _P, _P, _P, _P], _I),
+        "qx_batch_set_deo_launch": ([_P, _I, _I, _P], _I),
         "qx_tune_dslash": ([_P, _I, _P, _P], _I),
         "qx_gauge_action": ([_P, _P, ctypes.c_double, _P, _SZ, _P, _P], _I),
         "qx_gauge_force": ([_P, _P, ctypes.c_double, _P, _I, _P], _I),
@@ -436,6 +438,17 @@ class Batch:
     def set_launch(self, nbt: int, lps: int, order: int, stream=None):
         """Solve under this launch shape from now on (as a tuner result)."""
         _check(load().qx_batch_set_launch(self._h, int(nbt), int(lps), int(order), _stream(stream)))
+
+    def set_deo_launch(self, nbt: int, lps: int, stream=None):
+        """Launch-per-pass engine: run the D_eo pass under (nbt, lps)."""
+        _check(load().qx_batch_set_deo_launch(self._h, int(nbt), int(lps), _stream(stream)))
+
+    def launch(self):
+        """((nbt, lps, order) of the stencil passes, (nbt, lps) of the
+        launch-per-pass engine's D_eo pass)."""
+        v = [ctypes.c_int() for _ in range(5)]
+        _check(load().qx_batch_get_launch(self._h, *(ctypes.byref(x) for x in v)))
+        return (v[0].value, v[1].value, v[2].value), (v[3].value, v[4].value)
 
     def profile(self, nchunks: int = 2, stream=None):
         """Event timing of nchunks chunks of this batch's solve, pass by pass:

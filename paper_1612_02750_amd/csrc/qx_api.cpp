@@ -494,6 +494,8 @@ struct qx_batch {
   int chunk = 16, ru_every = 4;
   bool forced = false;         // launch shape set by qx_batch_tune
   LaunchShape forced_shape{};
+  bool deo_forced = false;     // D_eo shape of the launch-per-pass engine set by qx_batch_tune
+  LaunchShape deo_shape{};
   bool use_graph = false;
   bool persistent = false;
   int pgrid = 0;
@@ -663,6 +665,13 @@ int build_plan(qx_batch* B, void* ws, size_t ws_bytes) {
                    (p.engine == QX_ENGINE_AUTO && max_nblk <= kFuseMaxBlocks);
   }
   B->cfg.two = B->cfg.fused && uses_two(B->specs, p.engine);
+  // the launch-per-pass D_eo pass: the tuner's own choice, else the shape of
+  // the other stencils
+  B->cfg.deo_shape = B->cfg.shape;
+  if (B->deo_forced && !B->cfg.fused && !B->persistent) {
+    B->cfg.deo_shape.nbt = B->deo_shape.nbt;
+    B->cfg.deo_shape.lps = B->deo_shape.lps;
+  }
   if (B->persistent) {
     B->chunk = p.chunk > 0 ? p.chunk : 512;
     B->ru_every = B->chunk;
@@ -939,7 +948,41 @@ extern "C" int qx_batch_set_launch(qx_batch_t* batch, int nbt, int lps, int orde
     return fail(QX_EINVAL, "qx_batch_set_launch: shape (%d, %d, %d) not available", nbt, lps, order);
   B->forced = true;
   B->forced_shape = sh;
+  B->deo_forced = false;
   return replan(B, stream);
+}
+
+extern "C" int qx_batch_set_deo_launch(qx_batch_t* batch, int deo_nbt, int deo_lps,
+                                       hipStream_t stream) {
+  if (!batch) return fail(QX_EINVAL, "qx_batch_set_deo_launch: NULL batch");
+  qx_batch* B = batch;
+  if (B->persistent || B->cfg.fused)
+    return fail(QX_EINVAL, "qx_batch_set_deo_launch: only for the launch-per-pass engine");
+  int nb = 1;
+  for (const auto& sp : B->specs) nb = std::max(nb, sp.nrhs);
+  const LaunchShape dsh{deo_nbt, deo_lps, B->cfg.shape.xcd};
+  const size_t csz = cplx_bytes(lo_prec(&B->params));
+  const bool wide = wide_compiled(B->cfg.prec_lo, B->cfg.recon_lo) && !B->cfg.links16;
+  if (!nbt_lps_instantiated(deo_nbt, deo_lps, wide) || !shape_ok(dsh, nb, csz))
+    return fail(QX_EINVAL, "qx_batch_set_deo_launch: shape (%d, %d) not available", deo_nbt,
+                deo_lps);
+  B->forced = true;
+  B->forced_shape = B->cfg.shape;
+  B->deo_forced = true;
+  B->deo_shape = dsh;
+  return replan(B, stream);
+}
+
+extern "C" int qx_batch_get_launch(qx_batch_t* batch, int* nbt, int* lps, int* order,
+                                   int* deo_nbt, int* deo_lps) {
+  if (!batch) return fail(QX_EINVAL, "qx_batch_get_launch: NULL batch");
+  const EngineCfg& c = batch->cfg;
+  if (nbt) *nbt = c.shape.nbt;
+  if (lps) *lps = c.shape.lps;
+  if (order) *order = c.shape.xcd;
+  if (deo_nbt) *deo_nbt = c.deo_shape.nbt;
+  if (deo_lps) *deo_lps = c.deo_shape.lps;
+  return QX_OK;
 }
 
 static_assert(PASS_P == QX_PASS_P && PASS_DOE == QX_PASS_DOE && PASS_DEO == QX_PASS_DEO &&
@@ -1042,6 +1085,7 @@ extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps,
   }
   // time one untimed and then `nchunks` timed chunks of the solve under each
   // candidate shape (the caller's x is not written: only the finish unpacks)
+  B->deo_forced = false;
   auto time_shape = [&](const LaunchShape& sh, float* ms) -> int {
     B->forced = true;
     B->forced_shape = sh;
@@ -1075,19 +1119,69 @@ extern "C" int qx_batch_tune(qx_batch_t* batch, int nchunks, int* nbt, int* lps,
           best = sh;
         }
       }
+  // The launch-per-pass engine's D_eo pass: other (sources per thread,
+  // wavefronts per site) under the best shape for the rest, kept when the
+  // chunks get faster, then the other passes' shape again beside the D_eo
+  // shape found (32^4 with twelve sources, FP32: D_eo 216 us under (4, 1)
+  // beside D_oe 191 us under (6, 2)).
+  LaunchShape best_deo = best;
+  if (rc == QX_OK && best_ms < 1e30f && !B->cfg.fused && !B->persistent) {
+    for (int nb_t : {1, 2, 4, 6, 12})
+      for (int l : {1, 2, 4, 8}) {
+        if (rc == QX_EHIP) break;
+        const LaunchShape dsh{nb_t, l, best.xcd};
+        if (nb_t == best.nbt && l == best.lps) continue;
+        if (!nbt_lps_instantiated(nb_t, l, wide) || !shape_ok(dsh, nb, csz)) continue;
+        if ((nb_t > 1 && nb_t > nb) || (split && l == 1)) continue;
+        B->deo_forced = true;
+        B->deo_shape = dsh;
+        float ms = 0.f;
+        rc = time_shape(best, &ms);
+        if (rc == QX_OK && ms < best_ms) {
+          best_ms = ms;
+          best_deo = dsh;
+        }
+      }
+    // the other stencils again, beside the D_eo shape found (the two passes'
+    // times add up nearly independently)
+    if (rc == QX_OK) {
+      B->deo_forced = true;
+      B->deo_shape = best_deo;
+      const LaunchShape first = best;
+      for (int nb_t : {1, 2, 4, 6, 12})
+        for (int l : {1, 2, 4, 8})
+          for (int x = 0; x <= kMaxOrder && rc != QX_EHIP; ++x) {
+            const LaunchShape sh{nb_t, l, x};
+            if (sh.nbt == first.nbt && sh.lps == first.lps && sh.xcd == first.xcd) continue;
+            if (!nbt_lps_instantiated(nb_t, l, wide) || !shape_ok(sh, nb, csz)) continue;
+            if ((nb_t > 1 && nb_t > nb) || (split && l == 1)) continue;
+            float ms = 0.f;
+            rc = time_shape(sh, &ms);
+            if (rc == QX_OK && ms < best_ms) {
+              best_ms = ms;
+              best = sh;
+            }
+          }
+      best_deo.xcd = best.xcd;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc == QX_EHIP) {
     B->forced = false;
+    B->deo_forced = false;
     return rc;
   }
   if (best_ms >= 1e30f) {
     B->forced = false;
+    B->deo_forced = false;
     replan(B, stream);
     return fail(QX_EINVAL, "qx_batch_tune: no launch shape could be timed");
   }
   B->forced = true;
   B->forced_shape = best;
+  B->deo_forced = best_deo.nbt != best.nbt || best_deo.lps != best.lps;
+  B->deo_shape = best_deo;
   rc = replan(B, stream);
   if (rc) return rc;
   if (nbt) *nbt = best.nbt;

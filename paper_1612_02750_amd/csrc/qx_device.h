@@ -618,6 +618,24 @@ __device__ __forceinline__ void for_each_item(const cplx<R> (&acc)[NBT][3], cplx
   }
 }
 
+// As for_each_item, with a value ld(j, c) per item (an epilogue operand in
+// device memory) loaded for all the thread's items before the first slot's
+// barrier, so that the slots' loads overlap instead of each waiting behind
+// the previous slot's barrier: f(j, c, v, loaded).
+template <typename R, int NBT, int LPS, typename L, typename F>
+__device__ __forceinline__ void for_each_item_ld(const cplx<R> (&acc)[NBT][3], cplx<R>* red,
+                                                 int dp, int grp, int lane, L&& ld, F&& f) {
+  using T = decltype(ld(0, 0));
+  T pre[NBT][3];
+#pragma unroll
+  for (int j = 0; j < NBT; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (LPS == 1 || (j * 3 + c) % LPS == dp) pre[j][c] = ld(j, c);
+  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane,
+                             [&](int j, int c, cplx<R> v) { f(j, c, v, pre[j][c]); });
+}
+
 // As for_each_item, but all three colours of a source slot meet in one
 // wavefront (part j % LPS), for outputs that need the whole colour vector of
 // a site at once (FP16 storage with a per-site scale): f(j, v[3]).

@@ -481,11 +481,15 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   const cplx<R>* p = slot<R>(d.vlo, pslot, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
   const bool nt = order_nt(order);
-  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+  // p of every item the thread finishes, loaded before the slots' barriers
+  const auto ld_p = [&](int j, int c) {
+    return (act >> j & 1u) ? p[(k0 + j) * ss + c * hv + cb] : cplx<R>{(R)0, (R)0};
+  };
+  for_each_item_ld<R, NBT, LPS>(acc, red, dp, grp, lane, ld_p,
+                                [&](int j, int c, cplx<R> v, cplx<R> pv) {
     if (!(act >> j & 1u)) return;
     const R m2 = (R)rd<FRESH>(q0[k0 + j].m2);
     const size_t i = (k0 + j) * ss + c * hv + cb;
-    const cplx<R> pv = p[i];
     const cplx<R> r = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
     st_cplx(Ap + i, r, nt);
     dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
@@ -1129,11 +1133,20 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
   const cplx<R>* r = slot<R>(d.vlo, rslot, vs);
   cplx<R>* Ap = slot<R>(d.vlo, 3, vs);
   const bool nt = order_nt(xcd);
-  for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
+  // p and r of every item the thread finishes, loaded before the slots' barriers
+  struct PR {
+    cplx<R> p, r;
+  };
+  const auto ld_pr = [&](int j, int c) {
+    const size_t i = (k0 + j) * ss + c * hv + cb;
+    return (act >> j & 1u) ? PR{p[i], r[i]} : PR{{(R)0, (R)0}, {(R)0, (R)0}};
+  };
+  for_each_item_ld<R, NBT, LPS>(acc, red, dp, grp, lane, ld_pr,
+                                [&](int j, int c, cplx<R> v, PR pr) {
     if (!(act >> j & 1u)) return;
     const R m2 = (R)q0[k0 + j].m2;
     const size_t i = (k0 + j) * ss + c * hv + cb;
-    const cplx<R> pv = p[i], rv = r[i];
+    const cplx<R> pv = pr.p, rv = pr.r;
     const cplx<R> a = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
     st_cplx(Ap + i, a, nt);
     dpa[j] += (double)pv.re * (double)a.re + (double)pv.im * (double)a.im;
@@ -1494,11 +1507,19 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     QX_TIMED(c, PASS_DOE, s,
              hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
                                 c.d_sys, c.nsys, c.d_st, c.shape.xcd));
-    QX_TIMED(c, PASS_DEO, s,
-             hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
-                                c.d_sys, c.nsys, c.d_st, 2, c.shape.xcd));
     return hipGetLastError();
   });
+  // the D_eo pass under its own (sources per thread, wavefronts per site)
+  if (e == hipSuccess)
+    e = with_nbt_lps<kWide>(c.deo_shape.nbt, c.deo_shape.lps, [&]<int NBT, int LPS>() {
+      const LaunchShape& dsh = c.deo_shape;
+      const dim3 dblock(64 * dsh.lps * shape_groups(dsh, c.nsrc_max));
+      const size_t dlds = shape_lds(dsh, c.nsrc_max, sizeof(cplx<R>));
+      QX_TIMED(c, PASS_DEO, s,
+               hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, dblock, dlds, s,
+                                  c.d_sys, c.nsys, c.d_st, 2, c.shape.xcd));
+      return hipGetLastError();
+    });
   if (e == hipSuccess) e = finalize(c, FIN_ALPHA, s);
   if (e == hipSuccess) {
     QX_TIMED(c, PASS_XR, s,

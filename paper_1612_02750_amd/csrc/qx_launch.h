@@ -149,6 +149,11 @@ struct EngineCfg {
   bool links16 = false;  // inner links stored as binary16 (prec_lo FP32: the vectors stay FP32)
   int nsrc_max = 1;  // most sources of any system (sets the groups of a block)
   LaunchShape shape;
+  // (sources per thread, wavefronts per site) of the launch-per-pass D_eo
+  // pass, which the solver tuner picks apart from the other stencils (its A
+  // epilogue and FP64 dot products change the register balance); the block
+  // order is shape's.  The other engines use `shape` throughout.
+  LaunchShape deo_shape;
   int nsys = 0, nblk_total = 0, nvblk_total = 0, nsrc_total = 0;
   const SysDesc* d_sys = nullptr;
   SrcState* d_st = nullptr;   // the source states (slot 0)

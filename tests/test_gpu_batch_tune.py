@@ -52,6 +52,12 @@ def test_batch_tune(qx, engine, stream):
         # small systems run the fused sequences, which take at most four sources per thread
         assert nbt in (1, 2, 4) and lps in (1, 2, 4, 8) and order in range(6)
         assert lps > 1  # batches of at most 1024 blocks per system split the hops
+        shape, deo = B.launch()
+        assert shape == (nbt, lps, order)
+        # only the launch-per-pass engine runs its D_eo pass under a shape of its own
+        if engine != "LAUNCH":
+            assert deo == (nbt, lps)
+        assert deo[0] in (1, 2, 4) and deo[1] > 1
         for k in keep:
             assert not to_host(k[4]).any()  # tuning writes no solution
         st = B.solve()
@@ -63,11 +69,44 @@ def test_batch_tune(qx, engine, stream):
         for k in keep:
             k[4].zero_()
         B2 = qx.Batch(systems, tol=1e-10, engine=getattr(qx, "ENGINE_" + engine))
+        if deo != (nbt, lps):
+            B2.set_deo_launch(*deo)
+        # (the plan may take another block order, which changes no bits)
+        assert B2.launch()[0][:2] == shape[:2] and B2.launch()[1] == deo
         st2 = B2.solve()
         torch.cuda.synchronize()
     for k, t in zip(keep, tuned):
         assert np.array_equal(to_host(k[4]), t)
     assert [s.iters for s in st] == [s.iters for s in st2]
+
+
+def test_batch_deo_launch(qx):
+    """qx_batch_set_deo_launch: the launch-per-pass engine's D_eo pass under a
+    shape of its own solves to the oracle's 1e-10, qx_batch_get_launch reports
+    it, qx_batch_set_launch resets it; other engines and unavailable shapes
+    are refused."""
+    import torch
+
+    systems, keep = _systems(qx, torch, [((8, 4, 6, 8), 3)])
+    B = qx.Batch(systems, tol=1e-10, mode=qx.CG_MIXED_F32, engine=qx.ENGINE_LAUNCH)
+    B.set_launch(1, 2, 1)
+    B.set_deo_launch(4, 1)
+    assert B.launch() == ((1, 2, 1), (4, 1))
+    st = B.solve()
+    torch.cuda.synchronize()
+    _check(keep, st)
+    B.set_launch(2, 2, 0)
+    assert B.launch() == ((2, 2, 0), (2, 2))
+    with pytest.raises(qx.QXError) as e:
+        B.set_deo_launch(3, 1)
+    assert e.value.code == qx.EINVAL
+    F = qx.Batch(systems, tol=1e-10, engine=qx.ENGINE_FUSED2)
+    with pytest.raises(qx.QXError) as e:
+        F.set_deo_launch(1, 2)
+    assert e.value.code == qx.EINVAL
+    L = qx.load()
+    assert L.qx_batch_get_launch(None, None, None, None, None, None) == qx.EINVAL
+    assert L.qx_batch_set_deo_launch(None, 1, 2, None) == qx.EINVAL
 
 
 def test_batch_tune_rejects(qx):
