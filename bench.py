@@ -17,10 +17,11 @@ Reported beside it (same run):
     FP64 single-source solves one after another (medians of three), i.e. the
     time-to-solution comparison mixed vs FP64 at equal and at single batching;
   * the roofline of the dominant kernel of the step, the D_eo pass of the
-    iteration (half-Dslash with the A epilogue and the <p, A p> partials),
-    from HIP events around each of its launches in an event-timed run of the
-    same batch (two chunks of its solve, eager launches), and the other passes
-    of the iteration from the same run;
+    iteration (half-Dslash with the A epilogue and the <p, A p> partials,
+    under the launch shape the solver tuner gave it), from HIP events around
+    each of its launches in an event-timed run of the same batch (two chunks
+    of its solve, eager launches), and the other passes of the iteration
+    from the same run;
   * the 16^4 weak-field single-source solve (mixed vs FP64, every engine, FP16
     inner links);
   * the half-Dslash on 32^4 and 48^4 in FP32-12, FP64-18 and FP16-12, one and
@@ -117,8 +118,8 @@ PASS_BYTES = {
 # counters read for the library's copy and read probes on 1 GiB (FETCH x 2,
 # WRITE x 1), from profiles/cg_mixed_32x32x32x32_12src_counters.md.  Reported
 # only while the engine sources and the launch shape are the ones the counters
-# were taken with; keyed by "nbt,lps,order".
-TRAFFIC = {"sha": "3153b9fb2af85281", "bytes": {"6,2,0": 983612224}}
+# were taken with; keyed by the D_eo pass's "nbt,lps,order".
+TRAFFIC = {"sha": "bc7fa093d38242da", "bytes": {"4,1,0": 1065778368, "6,1,0": 1232096096}}
 KERNEL_SOURCES = ("qx_engine_kernels.h", "qx_device.h", "qx_internal.h", "qx_launch.h",
                   "qx_dispatch.h")
 
