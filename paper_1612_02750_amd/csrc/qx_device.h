@@ -393,6 +393,42 @@ struct FieldIn {
   }
 };
 
+// Colour vectors of FP32/FP64 sources as FieldIn, for a wavefront that covers
+// the 64 consecutive sites [cb0, cb0 + 64) of a tile: the x and y neighbours
+// that fall inside the tile are taken from the lane that loaded that index
+// (ds_bpermute) instead of being loaded again.  Every lane first loads the
+// colour vectors at its own index of the input parity (`own`, stencil_hops):
+// one of a site's two x neighbours has that index and the other lies in the
+// same row, and the y neighbours of all but the tile's first or last row are
+// other lanes' own indices.  Lanes whose neighbour is outside the tile (a
+// row split by the tile boundary, the first and last rows' y hops, the y
+// wrap-around) load it.  The values are the same bits as FieldIn's.
+template <typename R>
+struct FieldInXY {
+  const cplx<R>* __restrict__ p;  // first source of the thread
+  size_t ss, hv;
+  int jmax;  // last readable slot
+  int cb0;   // first site of the wavefront's tile
+  __device__ __forceinline__ cplx<R> operator()(int j, int c, int site) const {
+    const int jj = j < jmax ? j : jmax;
+    return ld_cplx<false>(p + jj * ss + c * hv, (unsigned)site);
+  }
+};
+template <typename In>
+struct is_xy_input : std::false_type {};
+template <typename R>
+struct is_xy_input<FieldInXY<R>> : std::true_type {};
+
+// The lane's own-index colour vectors of every slot (for FieldInXY).
+template <typename R, int NBT>
+struct OwnVals {
+  cplx<R> v[NBT][3];
+  bool ok;  // loaded: the wavefront holds both x or both y hops
+};
+
+__device__ __forceinline__ float lane_shfl(float v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ double lane_shfl(double v, int src) { return __shfl(v, src, 64); }
+
 // FP16 colour vectors: per source [hv] records of 16 bytes, one per site:
 // the three colours as half-precision complex numbers (12 bytes) and the
 // site's FP32 scale; element = half * scale.  A site is one 16-byte load.
@@ -464,7 +500,8 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
                                             const cplx<LS>* __restrict__ lb,
                                             const cplx<LS>* __restrict__ lf3,
                                             const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
-                                            const In& in, cplx<R> (&acc)[NBT][3]) {
+                                            const In& in, const OwnVals<R, NBT>& own,
+                                            cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   constexpr int mu = H & 3;
   constexpr bool fwd = (H & 4) == 0;
@@ -481,10 +518,30 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
   }
   const int nb = s.template nbr<H>();
   cplx<R> v[NBT][3];
+  const auto load_all = [&]() {
 #pragma unroll
-  for (int j = 0; j < NBT; ++j)
+    for (int j = 0; j < NBT; ++j)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[j][c] = in(j, c, nb);
+      for (int c = 0; c < 3; ++c) v[j][c] = in(j, c, nb);
+  };
+  if constexpr (is_xy_input<In>::value && !three && mu < 2) {
+    if (own.ok) {
+      // in-tile neighbours from the lane that holds them, the rest loaded
+      const unsigned o = (unsigned)(nb - in.cb0);
+      const bool inside = o < 64u;
+      const int src = inside ? (int)o : (int)(threadIdx.x & 63);
+#pragma unroll
+      for (int j = 0; j < NBT; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          v[j][c] = {lane_shfl(own.v[j][c].re, src), lane_shfl(own.v[j][c].im, src)};
+      if (!inside) load_all();
+    } else {
+      load_all();
+    }
+  } else {
+    load_all();
+  }
   cplx<R> u[9];
   const cplx<LS>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
   load_link<R, RECON, NT>(u, base + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv, sign);
@@ -510,22 +567,39 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
 
 // acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT.
 // Each hop is its own instantiation, guarded by a wavefront-uniform test.
+// The hops of a direction are taken one after the other (x+, x-, y+, y-, z+,
+// z-, t+, t-), so that a wavefront with FieldInXY input uses the own-index
+// values it loaded for both x (or both y) hops.
 template <typename R, int RECON, int NBT, int LPS, bool NT, typename In, typename LS>
 __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __restrict__ lf,
                                              const cplx<LS>* __restrict__ lb,
                                              const cplx<LS>* __restrict__ lf3,
                                              const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
                                              int dp, const In& in, cplx<R> (&acc)[NBT][3]) {
+  OwnVals<R, NBT> own;
+  own.ok = false;
+  if constexpr (is_xy_input<In>::value) {
+    // hop h goes to part h % LPS: with LPS <= 4 parts 0 and 1 hold both x
+    // hops and both y hops (with LPS 8 each part holds one hop: no gain)
+    own.ok = LPS == 1 || (LPS <= 4 && dp < 2);
+    if (own.ok) {
+      const int ci = cb < (int)g.hv ? cb : (int)g.hv - 1;
+#pragma unroll
+      for (int j = 0; j < NBT; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) own.v[j][c] = in(j, c, ci);
+    }
+  }
 #define QX_HOP(H)                               \
   if (LPS == 1 || (H) % LPS == dp)              \
-  stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, acc)
+  stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, own, acc)
   QX_HOP(0);
-  QX_HOP(1);
-  QX_HOP(2);
-  QX_HOP(3);
   QX_HOP(4);
+  QX_HOP(1);
   QX_HOP(5);
+  QX_HOP(2);
   QX_HOP(6);
+  QX_HOP(3);
   QX_HOP(7);
   if constexpr (RECON == 36) {
     QX_HOP(8);

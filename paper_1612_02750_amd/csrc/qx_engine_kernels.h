@@ -439,9 +439,16 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(
-        d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
-        FieldIn<R>{slot<R>(d.vlo, 2, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0}, acc);
+    const cplx<R>* in = slot<R>(d.vlo, 2, vs) + k0 * ss;
+    // x and y neighbours shuffled from the lanes that hold them while the
+    // own-index values fit beside the hop's (six FP32 or two FP64 sources per thread)
+    if constexpr (sizeof(cplx<R>) * NBT <= 48)
+      stencil_part<R, RECON, NBT, LPS>(
+          d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
+          FieldInXY<R>{in, ss, hv, d.nsrc - 1 - k0, cb & ~(kTile - 1)}, acc);
+    else
+      stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
+                                       FieldIn<R>{in, ss, hv, d.nsrc - 1 - k0}, acc);
   }
   cplx<R>* t = slot<R>(d.vlo, 4, vs);
   const bool nt = order_nt(order);
