@@ -119,7 +119,7 @@ PASS_BYTES = {
 # WRITE x 1), from profiles/cg_mixed_32x32x32x32_12src_counters.md.  Reported
 # only while the engine sources and the launch shape are the ones the counters
 # were taken with; keyed by the D_eo pass's "nbt,lps,order".
-TRAFFIC = {"sha": "bc7fa093d38242da", "bytes": {"4,1,0": 1065778368, "6,1,0": 1232096096}}
+TRAFFIC = {"sha": "dce74afceffa3fea", "bytes": {"4,1,0": 992553680}}
 KERNEL_SOURCES = ("qx_engine_kernels.h", "qx_device.h", "qx_internal.h", "qx_launch.h",
                   "qx_dispatch.h")
 

@@ -567,10 +567,13 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
 
 // acc[j] += the hops of part dp (of LPS) applied to in_j, j < NBT.
 // Each hop is its own instantiation, guarded by a wavefront-uniform test.
-// The hops of a direction are taken one after the other (x+, x-, y+, y-, z+,
-// z-, t+, t-), so that a wavefront with FieldInXY input uses the own-index
-// values it loaded for both x (or both y) hops.
-template <typename R, int RECON, int NBT, int LPS, bool NT, typename In, typename LS>
+// PAIRED (the solver's passes): the hops of a direction are taken one after
+// the other (x+, x-, y+, y-, z+, z-, t+, t-), so that a wavefront with
+// FieldInXY input uses the own-index values it loaded for both x (or both y)
+// hops; every engine's stencils sum their hops in this order, so the engines
+// round alike.  Otherwise (the standalone operator) the order is x+, y+, z+,
+// t+, x-, ..., which the compiler schedules with fewer registers there.
+template <typename R, int RECON, int NBT, int LPS, bool NT, bool PAIRED, typename In, typename LS>
 __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __restrict__ lf,
                                              const cplx<LS>* __restrict__ lb,
                                              const cplx<LS>* __restrict__ lf3,
@@ -593,14 +596,25 @@ __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __res
 #define QX_HOP(H)                               \
   if (LPS == 1 || (H) % LPS == dp)              \
   stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, own, acc)
-  QX_HOP(0);
-  QX_HOP(4);
-  QX_HOP(1);
-  QX_HOP(5);
-  QX_HOP(2);
-  QX_HOP(6);
-  QX_HOP(3);
-  QX_HOP(7);
+  if constexpr (PAIRED) {
+    QX_HOP(0);
+    QX_HOP(4);
+    QX_HOP(1);
+    QX_HOP(5);
+    QX_HOP(2);
+    QX_HOP(6);
+    QX_HOP(3);
+    QX_HOP(7);
+  } else {
+    QX_HOP(0);
+    QX_HOP(1);
+    QX_HOP(2);
+    QX_HOP(3);
+    QX_HOP(4);
+    QX_HOP(5);
+    QX_HOP(6);
+    QX_HOP(7);
+  }
   if constexpr (RECON == 36) {
     QX_HOP(8);
     QX_HOP(9);
@@ -617,7 +631,7 @@ __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __res
 // The same for the links of output parity pout; whether the links stream past
 // the caches is decided once per launch (Geo::stream_links).  The caller runs
 // it only for sites of the lattice (every slot of the thread is computed).
-template <typename R, int RECON, int NBT, int LPS, typename In, typename LS>
+template <typename R, int RECON, int NBT, int LPS, bool PAIRED = true, typename In, typename LS>
 __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __restrict__ links,
                                              int pout, int cb, const Site& s, int dp, const In& in,
                                              cplx<R> (&acc)[NBT][3]) {
@@ -633,14 +647,14 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __res
     Site s3 = s;
     three_hop_geometry(g, cb, s3);
     if (g.stream_links)
-      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s3, dp, in, acc);
+      stencil_hops<R, RECON, NBT, LPS, true, PAIRED>(g, lf, lb, lf3, lb3, cb, s3, dp, in, acc);
     else
-      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s3, dp, in, acc);
+      stencil_hops<R, RECON, NBT, LPS, false, PAIRED>(g, lf, lb, lf3, lb3, cb, s3, dp, in, acc);
   } else {
     if (g.stream_links)
-      stencil_hops<R, RECON, NBT, LPS, true>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
+      stencil_hops<R, RECON, NBT, LPS, true, PAIRED>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
     else
-      stencil_hops<R, RECON, NBT, LPS, false>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
+      stencil_hops<R, RECON, NBT, LPS, false, PAIRED>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
   }
 }
 

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const c
   if (cb < g.hv && jmax >= 0) {
     Site s;
     site_geometry(g, pout, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(g, links, pout, cb, s, dp,
+    stencil_part<R, RECON, NBT, LPS, false>(g, links, pout, cb, s, dp,
                                      FieldIn<R>{in + k0 * ss, ss, hv, jmax}, acc);
   }
   for_each_item<R, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, int c, cplx<R> v) {
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_dslash_h(
   if (cb < g.hv && jmax >= 0) {
     Site s;
     site_geometry(g, pout, cb, s);
-    stencil_part<float, RECON, NBT, LPS>(g, links, pout, cb, s, dp,
+    stencil_part<float, RECON, NBT, LPS, false>(g, links, pout, cb, s, dp,
                                          FieldInH{in + k0 * ss, hv, jmax}, acc);
   }
   for_each_slot<float, NBT, LPS>(acc, red, dp, grp, lane, [&](int j, const cplx<float>(&v)[3]) {
@@ -92,7 +92,8 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_deo_axpy(Geo g, const
   zero_acc<R, NBT>(acc);
   Site s;
   site_geometry(g, 0, cb, s);
-  stencil_part<R, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldIn<R>{t + k0 * ss, ss, hv, jmax}, acc);
+  stencil_part<R, RECON, NBT, 1, false>(g, links, 0, cb, s, 0, FieldIn<R>{t + k0 * ss, ss, hv, jmax},
+                                        acc);
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     if (j > jmax) continue;
@@ -121,7 +122,8 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_deo_axpy_h(
   zero_acc<float, NBT>(acc);
   Site s;
   site_geometry(g, 0, cb, s);
-  stencil_part<float, RECON, NBT, 1>(g, links, 0, cb, s, 0, FieldInH{t + k0 * ss, hv, jmax}, acc);
+  stencil_part<float, RECON, NBT, 1, false>(g, links, 0, cb, s, 0, FieldInH{t + k0 * ss, hv, jmax},
+                                            acc);
   const FieldInH pin{p + k0 * ss, hv, jmax};
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
