@@ -337,6 +337,19 @@ __device__ __forceinline__ void load_link_chunks(cplx<R> (&u)[9], const char* __
   }
 }
 
+// Row 2 of a 12-real link from rows 0 and 1: for W = s U with U in SU(3) and
+// s = +-1, row2(W) = s * conj(row0(W) x row1(W)).
+template <typename R>
+__device__ __forceinline__ void reconstruct_row2(cplx<R> (&u)[9], int sign) {
+  const R s = (R)sign;
+  const cplx<R> c0 = cmul(u[1], u[5]), c0b = cmul(u[2], u[4]);
+  const cplx<R> c1 = cmul(u[2], u[3]), c1b = cmul(u[0], u[5]);
+  const cplx<R> c2 = cmul(u[0], u[4]), c2b = cmul(u[1], u[3]);
+  u[6] = {s * (c0.re - c0b.re), -s * (c0.im - c0b.im)};
+  u[7] = {s * (c1.re - c1b.re), -s * (c1.im - c1b.im)};
+  u[8] = {s * (c2.re - c2b.re), -s * (c2.im - c2b.im)};
+}
+
 // Link idx of the region that starts at base (element 0 of direction mu of one
 // parity).  Links are read once per half-Dslash: when they cannot stay in the
 // Infinity Cache anyway they are loaded non-temporally (NT), so that the
@@ -353,16 +366,7 @@ __device__ __forceinline__ void load_link(cplx<R> (&u)[9], const cplx<LS>* __res
   } else {
     load_link_chunks<R, LS, NT, E, 0>(u, reinterpret_cast<const char*>(base), idx, hv);
   }
-  if constexpr (RECON == 12) {
-    // For W = s U with U in SU(3), s = +-1: row2(W) = s * conj(row0(W) x row1(W)).
-    const R s = (R)sign;
-    const cplx<R> c0 = cmul(u[1], u[5]), c0b = cmul(u[2], u[4]);
-    const cplx<R> c1 = cmul(u[2], u[3]), c1b = cmul(u[0], u[5]);
-    const cplx<R> c2 = cmul(u[0], u[4]), c2b = cmul(u[1], u[3]);
-    u[6] = {s * (c0.re - c0b.re), -s * (c0.im - c0b.im)};
-    u[7] = {s * (c1.re - c1b.re), -s * (c1.im - c1b.im)};
-    u[8] = {s * (c2.re - c2b.re), -s * (c2.im - c2b.im)};
-  }
+  if constexpr (RECON == 12) reconstruct_row2(u, sign);
 }
 
 // ---------------------------------------------------------------- stencil
@@ -489,18 +493,122 @@ __device__ __forceinline__ void st_field_h(char* __restrict__ src, int cb,
   reinterpret_cast<qx_u32x4*>(src)[cb] = r;
 }
 
+// ------------------------------------------------- links shared through LDS
+//
+// When a block's wavefronts serve different source groups of the same 64
+// sites (one wavefront per group and site), each would load every link of
+// the tile itself: the same bytes through the vector memory pipeline once per
+// group.  Instead the wavefronts share the loads: wavefront w of G loads the
+// links of the hops h with h % G == w into LDS, the block meets at one
+// barrier, and every wavefront reads all eight hops' links from LDS.  Chunk J
+// of the link of hop h for lane l sits at ll[(h * NC + J) * 64 + l], 16 bytes
+// (a partial last chunk in its first words), in the storage format of the
+// link regions (link_elem_offset), so the values are the same bits as
+// load_link's.
+template <typename LS, int E>
+constexpr int link_chunks() {
+  return (int)((E * sizeof(cplx<LS>) + 15) / 16);
+}
+
+// LDS bytes of a tile's staged one-hop links (eight hops, 64 lanes), or 0
+// where they are not staged (three-hop links, or more than 64 KB).
+template <int RECON, typename LS>
+constexpr size_t kLinkLdsBytes =
+    RECON == 36 || 8 * link_chunks<LS, RECON == 12 ? 6 : 9>() * 64 * 16 > 65536
+        ? 0
+        : (size_t)8 * link_chunks<LS, RECON == 12 ? 6 : 9>() * 64 * 16;
+
+template <typename LS, int E, bool NT, int J>
+__device__ __forceinline__ void stage_link_chunks(qx_u32x4* __restrict__ ll, const char* region,
+                                                  unsigned idx, size_t hv) {
+  constexpr int C = (int)sizeof(cplx<LS>), K = 16, W = K / C;
+  if constexpr (J * W < E) {
+    constexpr int N = (E - J * W) < W ? (E - J * W) : W;
+    unsigned w[N * C / 4];
+    ld_words<N * C / 4, NT>(region + (size_t)J * K * hv, idx * (unsigned)(N * C), w);
+    qx_u32x4 t = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < N * C / 4; ++i) t[i] = w[i];
+    ll[J * 64] = t;
+    stage_link_chunks<LS, E, NT, J + 1>(ll, region, idx, hv);
+  }
+}
+
+// The links of hop H of the calling lane's output site into LDS (layout above).
+template <int H, int RECON, bool NT, typename LS>
+__device__ __forceinline__ void stage_hop_link(const Geo& g, const cplx<LS>* __restrict__ lf,
+                                               const cplx<LS>* __restrict__ lb, int cb,
+                                               const Site& s, qx_u32x4* ll, int lane) {
+  constexpr int E = RECON == 12 ? 6 : 9, NC = link_chunks<LS, E>();
+  constexpr int mu = H & 3;
+  constexpr bool fwd = (H & 4) == 0;
+  const cplx<LS>* base = (fwd ? lf : lb) + (size_t)mu * E * (size_t)g.hv;
+  stage_link_chunks<LS, E, NT, 0>(ll + H * NC * 64 + lane, reinterpret_cast<const char*>(base),
+                                  (unsigned)(fwd ? cb : s.template nbr<H>()), (size_t)g.hv);
+}
+
+// The eight hops' links of output parity pout for the tile, shared by the G
+// wavefronts of the block (w: the caller's wavefront).  Every lane takes
+// part (a lane past the lattice passes a clamped site); the caller then
+// synchronises the block before any wavefront reads ll.
+template <int RECON, typename LS>
+__device__ __forceinline__ void stage_links(const Geo& g, const cplx<LS>* __restrict__ links,
+                                            int pout, int cb, const Site& s, int w, int G,
+                                            qx_u32x4* ll, int lane) {
+  static_assert(RECON != 36, "one-hop links only");
+  constexpr int E = RECON == 12 ? 6 : 9;
+  const size_t hv = (size_t)g.hv;
+  const cplx<LS>* lf = links + (size_t)pout * 4 * E * hv;
+  const cplx<LS>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
+#define QX_STAGE(H)                                                                  \
+  if ((H) % G == w) {                                                                \
+    if (g.stream_links)                                                              \
+      stage_hop_link<H, RECON, true>(g, lf, lb, cb, s, ll, lane);                    \
+    else                                                                             \
+      stage_hop_link<H, RECON, false>(g, lf, lb, cb, s, ll, lane);                   \
+  }
+  QX_STAGE(0);
+  QX_STAGE(1);
+  QX_STAGE(2);
+  QX_STAGE(3);
+  QX_STAGE(4);
+  QX_STAGE(5);
+  QX_STAGE(6);
+  QX_STAGE(7);
+#undef QX_STAGE
+}
+
+// Link of hop H from LDS (stage_links), as load_link returns it.
+template <typename R, int RECON, typename LS>
+__device__ __forceinline__ void lds_link(cplx<R> (&u)[9], const qx_u32x4* __restrict__ ll, int H,
+                                         int lane, int sign) {
+  constexpr int E = RECON == 12 ? 6 : 9, NC = link_chunks<LS, E>();
+  constexpr int C = (int)sizeof(cplx<LS>), W = 16 / C;
+#pragma unroll
+  for (int J = 0; J < NC; ++J) {
+    const qx_u32x4 t = ll[(H * NC + J) * 64 + lane];
+    const unsigned w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int n = 0; n < W; ++n)
+      if (J * W + n < E) u[J * W + n] = cplx_from_words<R, LS>(w + n * (C / 4));
+  }
+  if constexpr (RECON == 12) reconstruct_row2(u, sign);
+}
+
 // acc[j] += hop H applied to in_j for every slot j < NBT.  The colour vectors
 // of all slots are loaded before any product is formed and no slot is
 // skipped: a per-slot test would put every slot's loads behind its own branch
 // and let a wavefront have only one slot's loads in flight.  Callers mask
 // unused slots when they store.
 // Hops 8..15 (RECON == 36) are the three-hop terms, with the links at lf3/lb3.
-template <int H, typename R, int RECON, int NBT, bool NT, typename In, typename LS>
+// LL: the one-hop links come from LDS (stage_links) instead of memory.
+template <int H, typename R, int RECON, int NBT, bool NT, bool LL, typename In, typename LS>
 __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __restrict__ lf,
                                             const cplx<LS>* __restrict__ lb,
                                             const cplx<LS>* __restrict__ lf3,
                                             const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
                                             const In& in, const OwnVals<R, NBT>& own,
+                                            const qx_u32x4* __restrict__ ll,
                                             cplx<R> (&acc)[NBT][3]) {
   constexpr int E = RECON == 12 ? 6 : 9;
   constexpr int mu = H & 3;
@@ -543,8 +651,12 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
     load_all();
   }
   cplx<R> u[9];
-  const cplx<LS>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
-  load_link<R, RECON, NT>(u, base + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv, sign);
+  if constexpr (LL && !three) {
+    lds_link<R, RECON, LS>(u, ll, H, (int)(threadIdx.x & 63), sign);
+  } else {
+    const cplx<LS>* base = three ? (fwd ? lf3 : lb3) : (fwd ? lf : lb);
+    load_link<R, RECON, NT>(u, base + (size_t)mu * E * hv, (unsigned)(fwd ? cb : nb), hv, sign);
+  }
 #pragma unroll
   for (int j = 0; j < NBT; ++j) {
     if constexpr (fwd) {
@@ -573,12 +685,14 @@ __device__ __forceinline__ void stencil_hop(const Geo& g, const cplx<LS>* __rest
 // hops; every engine's stencils sum their hops in this order, so the engines
 // round alike.  Otherwise (the standalone operator) the order is x+, y+, z+,
 // t+, x-, ..., which the compiler schedules with fewer registers there.
-template <typename R, int RECON, int NBT, int LPS, bool NT, bool PAIRED, typename In, typename LS>
+template <typename R, int RECON, int NBT, int LPS, bool NT, bool PAIRED, bool LL = false,
+          typename In, typename LS>
 __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __restrict__ lf,
                                              const cplx<LS>* __restrict__ lb,
                                              const cplx<LS>* __restrict__ lf3,
                                              const cplx<LS>* __restrict__ lb3, int cb, const Site& s,
-                                             int dp, const In& in, cplx<R> (&acc)[NBT][3]) {
+                                             int dp, const In& in, cplx<R> (&acc)[NBT][3],
+                                             const qx_u32x4* __restrict__ ll = nullptr) {
   OwnVals<R, NBT> own;
   own.ok = false;
   if constexpr (is_xy_input<In>::value) {
@@ -595,7 +709,7 @@ __device__ __forceinline__ void stencil_hops(const Geo& g, const cplx<LS>* __res
   }
 #define QX_HOP(H)                               \
   if (LPS == 1 || (H) % LPS == dp)              \
-  stencil_hop<H, R, RECON, NBT, NT>(g, lf, lb, lf3, lb3, cb, s, in, own, acc)
+  stencil_hop<H, R, RECON, NBT, NT, LL>(g, lf, lb, lf3, lb3, cb, s, in, own, ll, acc)
   if constexpr (PAIRED) {
     QX_HOP(0);
     QX_HOP(4);
@@ -656,6 +770,20 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __res
     else
       stencil_hops<R, RECON, NBT, LPS, false, PAIRED>(g, lf, lb, lf3, lb3, cb, s, dp, in, acc);
   }
+}
+
+// stencil_part (one wavefront per site: all eight hops) with the links read
+// from LDS, where stage_links put them before the block's barrier.
+template <typename R, int RECON, int NBT, typename In, typename LS>
+__device__ __forceinline__ void stencil_part_ll(const Geo& g, const cplx<LS>* __restrict__ links,
+                                                int cb, const Site& s, const In& in,
+                                                const qx_u32x4* __restrict__ ll,
+                                                cplx<R> (&acc)[NBT][3]) {
+  static_assert(RECON != 36, "one-hop links only");
+  const cplx<LS>* none = nullptr;
+  (void)links;
+  stencil_hops<R, RECON, NBT, 1, false, true, true>(g, none, none, none, none, cb, s, 0, in, acc,
+                                                    ll);
 }
 
 template <typename R, int NBT>

@@ -421,9 +421,11 @@ hipError_t finalize(const EngineCfg& c, int kind, hipStream_t s) {
 // kernels and the persistent kernel.
 
 // E1: t = 2 D_oe p for running sources.
-template <typename R, int RECON, int NBT, int LPS, bool FRESH, typename LS>
+// LL: as in deo_tile, the source groups share the tile's links through LDS.
+template <typename R, int RECON, int NBT, int LPS, bool FRESH, typename LS, bool LL = false>
 __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b, int order) {
+  static_assert(!LL || LPS == 1, "shared links need one wavefront per site");
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
@@ -436,13 +438,30 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
-  if (act) {
+  const cplx<R>* in = slot<R>(d.vlo, 2, vs) + k0 * ss;
+  // x and y neighbours shuffled from the lanes that hold them while the
+  // own-index values fit beside the hop's (six FP32 or two FP64 sources per thread)
+  constexpr bool kXY = sizeof(cplx<R>) * NBT <= 48;
+  if constexpr (LL) {
+    const qx_u32x4* ll = reinterpret_cast<const qx_u32x4*>(qx_lds);
+    Site s;
+    site_geometry(d.g, 1, cb < d.g.hv ? cb : d.g.hv - 1, s);
+    stage_links<RECON>(d.g, (const cplx<LS>*)d.links_lo, 1, cb < d.g.hv ? cb : d.g.hv - 1, s, w,
+                       (int)(blockDim.x >> 6), reinterpret_cast<qx_u32x4*>(qx_lds), lane);
+    __syncthreads();
+    if (act) {
+      if constexpr (kXY)
+        stencil_part_ll<R, RECON, NBT>(
+            d.g, (const cplx<LS>*)d.links_lo, cb, s,
+            FieldInXY<R>{in, ss, hv, d.nsrc - 1 - k0, cb & ~(kTile - 1)}, ll, acc);
+      else
+        stencil_part_ll<R, RECON, NBT>(d.g, (const cplx<LS>*)d.links_lo, cb, s,
+                                       FieldIn<R>{in, ss, hv, d.nsrc - 1 - k0}, ll, acc);
+    }
+  } else if (act) {
     Site s;
     site_geometry(d.g, 1, cb, s);
-    const cplx<R>* in = slot<R>(d.vlo, 2, vs) + k0 * ss;
-    // x and y neighbours shuffled from the lanes that hold them while the
-    // own-index values fit beside the hop's (six FP32 or two FP64 sources per thread)
-    if constexpr (sizeof(cplx<R>) * NBT <= 48)
+    if constexpr (kXY)
       stencil_part<R, RECON, NBT, LPS>(
           d.g, (const cplx<LS>*)d.links_lo, 1, cb, s, dp,
           FieldInXY<R>{in, ss, hv, d.nsrc - 1 - k0, cb & ~(kTile - 1)}, acc);
@@ -459,10 +478,14 @@ __device__ __forceinline__ void doe_tile(const SysDesc* __restrict__ sys, int ns
 }
 
 // E2: Ap = m^2 p - 1/4 (2D_eo) t and the partials of Re<p, Ap>.
-template <typename R, int RECON, int NBT, int LPS, bool FRESH, typename LS>
+// LL (one wavefront per site, LPS 1): the block's source groups share the
+// tile's link loads through LDS (stage_links), which then holds no reduction
+// buffer.
+template <typename R, int RECON, int NBT, int LPS, bool FRESH, typename LS, bool LL = false>
 __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int nsys,
                                          const SrcState* st, int b, int order, int pslot,
                                          double* sh, double* tot) {
+  static_assert(!LL || LPS == 1, "shared links need one wavefront per site");
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id(), dp = w % LPS, grp = w / LPS;
   const SysDesc& d = sys_of_block(sys, nsys, b);
@@ -475,12 +498,19 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
   const unsigned act = cb < d.g.hv ? group_bits<NBT>(run, k0) : 0u;
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
-  if (act) {
+  const FieldIn<R> tin{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0};
+  if constexpr (LL) {
+    const qx_u32x4* ll = reinterpret_cast<const qx_u32x4*>(qx_lds);
+    Site s;
+    site_geometry(d.g, 0, cb < d.g.hv ? cb : d.g.hv - 1, s);
+    stage_links<RECON>(d.g, (const cplx<LS>*)d.links_lo, 0, cb < d.g.hv ? cb : d.g.hv - 1, s, w,
+                       (int)(blockDim.x >> 6), reinterpret_cast<qx_u32x4*>(qx_lds), lane);
+    __syncthreads();
+    if (act) stencil_part_ll<R, RECON, NBT>(d.g, (const cplx<LS>*)d.links_lo, cb, s, tin, ll, acc);
+  } else if (act) {
     Site s;
     site_geometry(d.g, 0, cb, s);
-    stencil_part<R, RECON, NBT, LPS>(
-        d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp,
-        FieldIn<R>{slot<R>(d.vlo, 4, vs) + k0 * ss, ss, hv, d.nsrc - 1 - k0}, acc);
+    stencil_part<R, RECON, NBT, LPS>(d.g, (const cplx<LS>*)d.links_lo, 0, cb, s, dp, tin, acc);
   }
   double dot[NBT];
 #pragma unroll
@@ -633,11 +663,11 @@ __global__ void __launch_bounds__(64) k_iter_p(const SysDesc* __restrict__ sys, 
   }
 }
 
-template <typename R, int RECON, int NBT, int LPS, typename LS>
+template <typename R, int RECON, int NBT, int LPS, typename LS, bool LL = false>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_doe(const SysDesc* __restrict__ sys,
                                                                     int nsys, const SrcState* st,
                                                                     int xcd) {
-  doe_tile<R, RECON, NBT, LPS, false, LS>(sys, nsys, st, logical_block(xcd), xcd);
+  doe_tile<R, RECON, NBT, LPS, false, LS, LL>(sys, nsys, st, logical_block(xcd), xcd);
 }
 
 template <typename R, int RECON, int NBT, int LPS, typename LS>
@@ -647,6 +677,25 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo(const SysDes
   __shared__ double sh[16 * 64];
   __shared__ double tot[64];
   deo_tile<R, RECON, NBT, LPS, false, LS>(sys, nsys, st, logical_block(xcd), xcd, pslot, sh, tot);
+}
+
+// Dynamic LDS of k_iter_deo_ll for G source groups of NBT: the staged links,
+// then the group sums' 16 and 1 doubles per source of the block.
+template <int RECON, typename LS>
+inline size_t deo_ll_lds(int G, int NBT) {
+  return kLinkLdsBytes<RECON, LS> + (size_t)G * NBT * 17 * sizeof(double);
+}
+
+// k_iter_deo with one wavefront per site and several source groups, which
+// share the tile's link loads through LDS.
+template <typename R, int RECON, int NBT, typename LS>
+__global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_iter_deo_ll(
+    const SysDesc* __restrict__ sys, int nsys, const SrcState* st, int pslot, int xcd) {
+  double* sh = reinterpret_cast<double*>(reinterpret_cast<char*>(qx_lds) +
+                                         kLinkLdsBytes<RECON, LS>);
+  const int ns = (int)(blockDim.x >> 6) * NBT;
+  deo_tile<R, RECON, NBT, 1, false, LS, true>(sys, nsys, st, logical_block(xcd), xcd, pslot, sh,
+                                              sh + 16 * ns);
 }
 
 // The x/r pass of the launch-per-pass engine (x_lo += alpha p deferred): one
@@ -1511,6 +1560,16 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
     QX_TIMED(c, PASS_P, s,
              hipLaunchKernelGGL(k_iter_p<R>, vgrid, dim3(64), 0, s, c.d_sys, c.nsys, c.d_st,
                                 c.shape.xcd));
+    // several source groups of one wavefront per site share the link loads
+    constexpr size_t kLL = kLinkLdsBytes<RECON, LS>;
+    if constexpr (LPS == 1 && kLL != 0) {
+      if (G >= 2) {
+        QX_TIMED(c, PASS_DOE, s,
+                 hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, 1, LS, true>), sgrid, sblock, kLL,
+                                    s, c.d_sys, c.nsys, c.d_st, c.shape.xcd));
+        return hipGetLastError();
+      }
+    }
     QX_TIMED(c, PASS_DOE, s,
              hipLaunchKernelGGL((k_iter_doe<R, RECON, NBT, LPS, LS>), sgrid, sblock, lds, s,
                                 c.d_sys, c.nsys, c.d_st, c.shape.xcd));
@@ -1520,7 +1579,19 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
   if (e == hipSuccess)
     e = with_nbt_lps<kWide>(c.deo_shape.nbt, c.deo_shape.lps, [&]<int NBT, int LPS>() {
       const LaunchShape& dsh = c.deo_shape;
-      const dim3 dblock(64 * dsh.lps * shape_groups(dsh, c.nsrc_max));
+      const int dg = shape_groups(dsh, c.nsrc_max);
+      const dim3 dblock(64 * dsh.lps * dg);
+      // several source groups of one wavefront per site share the link loads
+      constexpr size_t kLL = kLinkLdsBytes<RECON, LS>;
+      if constexpr (LPS == 1 && kLL != 0) {
+        if (dg >= 2) {
+          const size_t llds = deo_ll_lds<RECON, LS>(dg, NBT);
+          QX_TIMED(c, PASS_DEO, s,
+                   hipLaunchKernelGGL((k_iter_deo_ll<R, RECON, NBT, LS>), sgrid, dblock, llds, s,
+                                      c.d_sys, c.nsys, c.d_st, 2, c.shape.xcd));
+          return hipGetLastError();
+        }
+      }
       const size_t dlds = shape_lds(dsh, c.nsrc_max, sizeof(cplx<R>));
       QX_TIMED(c, PASS_DEO, s,
                hipLaunchKernelGGL((k_iter_deo<R, RECON, NBT, LPS, LS>), sgrid, dblock, dlds, s,
