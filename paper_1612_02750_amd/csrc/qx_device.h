@@ -774,7 +774,7 @@ __device__ __forceinline__ void stencil_part(const Geo& g, const cplx<LS>* __res
 
 // stencil_part (one wavefront per site: all eight hops) with the links read
 // from LDS, where stage_links put them before the block's barrier.
-template <typename R, int RECON, int NBT, typename In, typename LS>
+template <typename R, int RECON, int NBT, bool PAIRED = true, typename In, typename LS>
 __device__ __forceinline__ void stencil_part_ll(const Geo& g, const cplx<LS>* __restrict__ links,
                                                 int cb, const Site& s, const In& in,
                                                 const qx_u32x4* __restrict__ ll,
@@ -782,8 +782,8 @@ __device__ __forceinline__ void stencil_part_ll(const Geo& g, const cplx<LS>* __
   static_assert(RECON != 36, "one-hop links only");
   const cplx<LS>* none = nullptr;
   (void)links;
-  stencil_hops<R, RECON, NBT, 1, false, true, true>(g, none, none, none, none, cb, s, 0, in, acc,
-                                                    ll);
+  stencil_hops<R, RECON, NBT, 1, false, PAIRED, true>(g, none, none, none, none, cb, s, 0, in, acc,
+                                                      ll);
 }
 
 template <typename R, int NBT>

@@ -13,12 +13,14 @@ namespace qx {
 
 // out_k = scale * (2D in_k) at the sites of parity pout.  Block: 64 sites and
 // LPS * G wavefronts; wavefront w takes hop part w % LPS of the sources
-// (w / LPS) * NBT ... + NBT - 1.
-template <typename R, int RECON, int NBT, int LPS>
+// (w / LPS) * NBT ... + NBT - 1.  LL (LPS 1, G >= 2): the G wavefronts share
+// the tile's link loads through LDS (stage_links).
+template <typename R, int RECON, int NBT, int LPS, bool LL = false>
 __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const cplx<R>* __restrict__ links, int pout,
                                                  const cplx<R>* __restrict__ in,
                                                  cplx<R>* __restrict__ out, int nsrc, R scale,
                                                  int xcd) {
+  static_assert(!LL || LPS == 1, "shared links need one wavefront per site");
   cplx<R>* red = reinterpret_cast<cplx<R>*>(qx_lds);
   const int lane = threadIdx.x & 63, w = wave_id();
   const int dp = w % LPS, grp = w / LPS;
@@ -29,7 +31,18 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_dslash(Geo g, const c
   const bool nt = order_nt(xcd);
   cplx<R> acc[NBT][3];
   zero_acc<R, NBT>(acc);
-  if (cb < g.hv && jmax >= 0) {
+  if constexpr (LL) {
+    const int ci = cb < g.hv ? cb : g.hv - 1;
+    Site s;
+    site_geometry(g, pout, ci, s);
+    stage_links<RECON>(g, links, pout, ci, s, w, (int)(blockDim.x >> 6),
+                       reinterpret_cast<qx_u32x4*>(qx_lds), lane);
+    __syncthreads();
+    if (cb < g.hv && jmax >= 0)
+      stencil_part_ll<R, RECON, NBT, false>(g, links, cb, s,
+                                            FieldIn<R>{in + k0 * ss, ss, hv, jmax},
+                                            reinterpret_cast<const qx_u32x4*>(qx_lds), acc);
+  } else if (cb < g.hv && jmax >= 0) {
     Site s;
     site_geometry(g, pout, cb, s);
     stencil_part<R, RECON, NBT, LPS, false>(g, links, pout, cb, s, dp,
@@ -180,6 +193,16 @@ hipError_t launch_dslash(const Geo& g, int prec, int recon, const void* links, i
     }
     hipError_t e = with_prec_recon(prec, recon, [&]<typename R, int RECON>() {
       return with_nbt_lps<(sizeof(R) == 4 && RECON != 36)>(sh.nbt, sh.lps, [&]<int NBT, int LPS>() {
+        // several source groups of one wavefront per site share the link loads
+        constexpr size_t kLL = kLinkLdsBytes<RECON, R>;
+        if constexpr (LPS == 1 && kLL != 0) {
+          if (shape_groups(sh, n) >= 2) {
+            hipLaunchKernelGGL((k_dslash<R, RECON, NBT, 1, true>), dim3(grid), dim3(threads), kLL,
+                               s, gl, (const cplx<R>*)links, pout, (const cplx<R>*)pin,
+                               (cplx<R>*)po, n, (R)scale, sh.xcd);
+            return hipGetLastError();
+          }
+        }
         hipLaunchKernelGGL((k_dslash<R, RECON, NBT, LPS>), dim3(grid), dim3(threads), lds, s, gl,
                            (const cplx<R>*)links, pout, (const cplx<R>*)pin, (cplx<R>*)po, n,
                            (R)scale, sh.xcd);
