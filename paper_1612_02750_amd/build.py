@@ -48,6 +48,10 @@ def _flags():
         f"--offload-arch={ARCH}",
         "-fPIC",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # products and sums round as written (fused only where fma() is
+        # called), so every kernel that evaluates an expression rounds it
+        # alike, whatever its surrounding code lets the compiler fuse
+        "-ffp-contract=off",
         "-Wno-unused-command-line-argument",
         "-I", os.path.join(ROOT, "include"),
         "-I", CSRC,

@@ -337,17 +337,38 @@ __device__ __forceinline__ void load_link_chunks(cplx<R> (&u)[9], const char* __
   }
 }
 
+// Fused multiply-add in the type of its operands.
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// a b - c d for complex a, b, c, d, every step an explicit multiply or fused
+// multiply-add, so that no kernel's contraction of products and sums changes
+// the rounding (the same link gives the same bits in every kernel).
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul_sub(const cplx<R>& a, const cplx<R>& b, const cplx<R>& c,
+                                            const cplx<R>& d) {
+  R re = a.re * b.re;
+  re = fmadd(-a.im, b.im, re);
+  re = fmadd(-c.re, d.re, re);
+  re = fmadd(c.im, d.im, re);
+  R im = a.re * b.im;
+  im = fmadd(a.im, b.re, im);
+  im = fmadd(-c.re, d.im, im);
+  im = fmadd(-c.im, d.re, im);
+  return {re, im};
+}
+
 // Row 2 of a 12-real link from rows 0 and 1: for W = s U with U in SU(3) and
 // s = +-1, row2(W) = s * conj(row0(W) x row1(W)).
 template <typename R>
 __device__ __forceinline__ void reconstruct_row2(cplx<R> (&u)[9], int sign) {
   const R s = (R)sign;
-  const cplx<R> c0 = cmul(u[1], u[5]), c0b = cmul(u[2], u[4]);
-  const cplx<R> c1 = cmul(u[2], u[3]), c1b = cmul(u[0], u[5]);
-  const cplx<R> c2 = cmul(u[0], u[4]), c2b = cmul(u[1], u[3]);
-  u[6] = {s * (c0.re - c0b.re), -s * (c0.im - c0b.im)};
-  u[7] = {s * (c1.re - c1b.re), -s * (c1.im - c1b.im)};
-  u[8] = {s * (c2.re - c2b.re), -s * (c2.im - c2b.im)};
+  const cplx<R> c0 = cmul_sub(u[1], u[5], u[2], u[4]);
+  const cplx<R> c1 = cmul_sub(u[2], u[3], u[0], u[5]);
+  const cplx<R> c2 = cmul_sub(u[0], u[4], u[1], u[3]);
+  u[6] = {s * c0.re, -s * c0.im};
+  u[7] = {s * c1.re, -s * c1.im};
+  u[8] = {s * c2.re, -s * c2.im};
 }
 
 // Link idx of the region that starts at base (element 0 of direction mu of one
@@ -560,8 +581,10 @@ __device__ __forceinline__ void stage_links(const Geo& g, const cplx<LS>* __rest
   const size_t hv = (size_t)g.hv;
   const cplx<LS>* lf = links + (size_t)pout * 4 * E * hv;
   const cplx<LS>* lb = links + (size_t)(1 - pout) * 4 * E * hv;
+  unsigned mine = 0;  // the hops h = w, w + G, ... of this wavefront
+  for (int h = w; h < 8; h += G) mine |= 1u << h;
 #define QX_STAGE(H)                                                                  \
-  if ((H) % G == w) {                                                                \
+  if (mine >> (H) & 1u) {                                                            \
     if (g.stream_links)                                                              \
       stage_hop_link<H, RECON, true>(g, lf, lb, cb, s, ll, lane);                    \
     else                                                                             \

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>)) k_deo_axpy(Geo g, const
     for (int c = 0; c < 3; ++c) {
       const size_t i = (k0 + j) * ss + c * hv + cb;
       const cplx<R> pv = p[i];
-      out[i] = {m2 * pv.re - (R)0.25 * acc[j][c].re, m2 * pv.im - (R)0.25 * acc[j][c].im};
+      out[i] = {fmadd(m2, pv.re, (R)-0.25 * acc[j][c].re), fmadd(m2, pv.im, (R)-0.25 * acc[j][c].im)};
     }
   }
 }
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__((kMaxThreads<float, NBT>)) k_deo_axpy_h(
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cplx<float> pv = pin(j, c, cb);
-      o[c] = {m2 * pv.re - 0.25f * acc[j][c].re, m2 * pv.im - 0.25f * acc[j][c].im};
+      o[c] = {fmadd(m2, pv.re, -0.25f * acc[j][c].re), fmadd(m2, pv.im, -0.25f * acc[j][c].im)};
     }
     st_field_h(out + (k0 + j) * ss, cb, o);
   }

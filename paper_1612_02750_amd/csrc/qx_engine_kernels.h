@@ -527,7 +527,8 @@ __device__ __forceinline__ void deo_tile(const SysDesc* __restrict__ sys, int ns
     if (!(act >> j & 1u)) return;
     const R m2 = (R)rd<FRESH>(q0[k0 + j].m2);
     const size_t i = (k0 + j) * ss + c * hv + cb;
-    const cplx<R> r = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
+    // one rounding (a quarter of v is exact), whatever the kernel contracts
+    const cplx<R> r = {fmadd(m2, pv.re, (R)-0.25 * v.re), fmadd(m2, pv.im, (R)-0.25 * v.im)};
     st_cplx(Ap + i, r, nt);
     dot[j] += (double)pv.re * (double)r.re + (double)pv.im * (double)r.im;
   });
@@ -1203,7 +1204,7 @@ __global__ void __launch_bounds__((kMaxThreads<R, NBT>))
     const R m2 = (R)q0[k0 + j].m2;
     const size_t i = (k0 + j) * ss + c * hv + cb;
     const cplx<R> pv = pr.p, rv = pr.r;
-    const cplx<R> a = {m2 * pv.re - (R)0.25 * v.re, m2 * pv.im - (R)0.25 * v.im};
+    const cplx<R> a = {fmadd(m2, pv.re, (R)-0.25 * v.re), fmadd(m2, pv.im, (R)-0.25 * v.im)};
     st_cplx(Ap + i, a, nt);
     dpa[j] += (double)pv.re * (double)a.re + (double)pv.im * (double)a.im;
     dra[j] += (double)rv.re * (double)a.re + (double)rv.im * (double)a.im;
@@ -1445,8 +1446,8 @@ __device__ __forceinline__ void ru_residual_block(const SysDesc* __restrict__ sy
         xhi[i] = xv;
         xlo[i] = {(Rlo)0, (Rlo)0};
         const cplx<double> bv = bb[i];
-        const cplx<double> r = {bv.re - (m2 * xv.re - 0.25 * acc[j][c].re),
-                                bv.im - (m2 * xv.im - 0.25 * acc[j][c].im)};
+        const cplx<double> r = {bv.re - fmadd(m2, xv.re, -0.25 * acc[j][c].re),
+                                bv.im - fmadd(m2, xv.im, -0.25 * acc[j][c].im)};
         rhi[i] = r;
         if (mark) slot<Rlo>(d.vlo, 1, vs)[i] = {(Rlo)r.re, (Rlo)r.im};
         rr[j] += r.re * r.re + r.im * r.im;
