@@ -112,14 +112,14 @@ PASS_BYTES = {
     "p": (0, 5 * VEC_B_F32),                 # r, p, x read; p, x written
 }
 
-# HBM-side bytes per launch of the dominant kernel (k_iter_deo of the
+# HBM-side bytes per launch of the dominant kernel (the D_eo pass of the
 # twelve-source step, all sources served) from two rocprofv3 counter runs
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
 # counters read for the library's copy and read probes on 1 GiB (FETCH x 2,
 # WRITE x 1), from profiles/cg_mixed_32x32x32x32_12src_counters.md.  Reported
 # only while the engine sources and the launch shape are the ones the counters
 # were taken with; keyed by the D_eo pass's "nbt,lps,order".
-TRAFFIC = {"sha": "dce74afceffa3fea", "bytes": {"4,1,0": 992553680}}
+TRAFFIC = {"sha": "12a40d2c611a9499", "bytes": {"4,1,0": 1174254160, "1,1,0": 867489056}}
 KERNEL_SOURCES = ("qx_engine_kernels.h", "qx_device.h", "qx_internal.h", "qx_launch.h",
                   "qx_dispatch.h")
 
@@ -546,6 +546,15 @@ def dslash_point(torch, qx, synth, spec):
     return {"dslash_point": [nbt, lps, order, nrhs], "us": round(t * 1e6, 2)}
 
 
+def deo_kernel_name(nbt, lps, nsrc=12):
+    """The D_eo kernel of the launch-per-pass engine for nsrc FP32-12 sources
+    under (nbt, lps): with one wavefront per site and two or more source
+    groups the block's groups share the link loads through LDS."""
+    if lps == 1 and -(-nsrc // nbt) >= 2:
+        return f"k_iter_deo_ll<float, 12, {nbt}, float>"
+    return f"k_iter_deo<float, 12, {nbt}, {lps}, float>"
+
+
 def set_solver_shape(B, spec):
     """spec "nbt,lps,order" or "nbt,lps,order,deo_nbt,deo_lps" (the D_eo pass
     of the launch-per-pass engine under a shape of its own)."""
@@ -856,7 +865,7 @@ def main():
                           "fp64_max": h["fp64_iters_max"]},
         "max_true_rel_residual": h["max_true_rel_residual"],
         "roofline": {
-            "kernel": f"k_iter_deo<float, 12, {h['shape'][3]}, {h['shape'][4]}, float> "
+            "kernel": f"{deo_kernel_name(h['shape'][3], h['shape'][4])} "
                       f"(D_eo half-Dslash of the step with the A epilogue and <p, Ap> partials; "
                       f"block order {h['shape'][2]})",
             "bound": "hbm",
