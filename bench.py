@@ -464,7 +464,12 @@ def multi_rhs_extras(torch, qx, synth, h):
     out["mixed_f16_links_iters_max"] = max(s.iters for s in st16)
     del b16, x16
     # the same batch in one cooperative launch per chunk of iterations (grid
-    # barriers between the passes), beside the launch-per-pass headline
+    # barriers between the passes), beside the launch-per-pass headline.  The
+    # persistent engine takes its shape from the inner-link handle and has no
+    # tuner of its own: it runs under (4, 2, 1), the fastest of the shapes
+    # measured for it here (2.9 s; one source per thread and one wavefront per
+    # site, which the Dslash tuner may pick for the kernel alone, 4.9 s)
+    g32.set_launch(nsrc, 4, 2, 1)
     xp = torch.empty_like(bd)
     bp = qx.Batch([(g64, g32, bd, [m] * nsrc, xp)], tol=1e-10, mode=qx.CG_MIXED_F32,
                   engine=qx.ENGINE_PERSISTENT)
