@@ -119,7 +119,7 @@ PASS_BYTES = {
 # WRITE x 1), from profiles/cg_mixed_32x32x32x32_12src_counters.md.  Reported
 # only while the engine sources and the launch shape are the ones the counters
 # were taken with; keyed by the D_eo pass's "nbt,lps,order".
-TRAFFIC = {"sha": "12a40d2c611a9499", "bytes": {"4,1,0": 1174254160, "1,1,0": 867489056}}
+TRAFFIC = {"sha": "790b325ec7814658", "bytes": {"4,1,0": 1176544528, "1,1,0": 867501792}}
 KERNEL_SOURCES = ("qx_engine_kernels.h", "qx_device.h", "qx_internal.h", "qx_launch.h",
                   "qx_dispatch.h")
 

@@ -1613,8 +1613,15 @@ hipError_t iteration_impl(const EngineCfg& c, int parity, hipStream_t s) {
 // RECON: the storage of the FP64 links (the update works on them).
 template <typename Rlo, int RECON>
 hipError_t reliable_update_impl(const EngineCfg& c, bool last, hipStream_t s) {
-  // FP64 stencils: at most four sources per thread (ru_nbt)
-  const LaunchShape rsh{narrow_nbt(c.shape.nbt), 1, c.shape.xcd};
+  // FP64 stencils: at most two sources per thread where the batch's sources
+  // fit one block that way (with four, the update kernels spill: 450-500
+  // bytes per lane), else at most four
+  LaunchShape rsh{narrow_nbt(c.shape.nbt), 1, c.shape.xcd};
+  if (rsh.nbt > 2) {
+    LaunchShape r2 = rsh;
+    r2.nbt = 2;
+    if (shape_ok(r2, c.nsrc_max, cplx_bytes(0))) rsh = r2;
+  }
   const int G = shape_groups(rsh, c.nsrc_max);
   const dim3 sgrid(c.nblk_total), sblock(64 * G);
   const dim3 vgrid(c.nvblk_total), vblock(kVTile);
