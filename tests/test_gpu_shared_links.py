@@ -72,3 +72,46 @@ def test_engines_shared_links_bitwise(qx, inner):
     for k in range(n):
         rr = oracle.true_residual(DIMS, U, masses[k], b[k], x[k], oracle.BC_T_ANTIPERIODIC)
         assert rr <= 1e-10 and sa[k].status == 0, (k, rr)
+
+
+def test_uneven_batch_shared_links_bitwise(qx):
+    """Two lattices of 5 and 2 sources in one batch under (2, 1, 0): every
+    block has three source groups, so in the smaller system's blocks two
+    groups have no source and still stage their share of the links.  The
+    launch-per-pass engine (shared links) and the persistent engine (not
+    shared) give the same bits, and every source meets the oracle's 1e-10."""
+    import torch
+
+    specs = [((6, 4, 4, 6), 5), ((4, 4, 4, 6), 2)]
+    systems, keep = [], []
+    for k, (dims, n) in enumerate(specs):
+        lat = qx.Lattice(dims, antiperiodic_t=True)
+        U = gauge(dims, seed=51 + k)
+        Ud = to_dev(U)
+        g64 = qx.Gauge(lat, Ud, "f64", 12)
+        g32 = qx.Gauge(lat, Ud, "f32", 12)
+        b = synth.gauss_source(n, lat.hv, 61 + k)
+        masses = [0.05 + 0.04 * j for j in range(n)]
+        systems.append([g64, g32, to_dev(b), masses, None])
+        keep.append((dims, U, b, masses))
+    # the batch takes its shape from the first system's inner links
+    systems[0][1].set_launch(5, 2, 1, 0)
+    runs = []
+    for engine in (qx.ENGINE_LAUNCH, qx.ENGINE_PERSISTENT):
+        for s in systems:
+            s[4] = torch.zeros_like(s[2])
+        B = qx.Batch([tuple(s) for s in systems], tol=1e-10, engine=engine)
+        assert B.launch()[0][:2] == (2, 1)
+        st = B.solve()
+        torch.cuda.synchronize()
+        runs.append(([to_host(s[4]) for s in systems], st))
+    (xa, sa), (xb, sb) = runs
+    for a, b in zip(xa, xb):
+        assert np.array_equal(a, b)
+    assert [s.iters for s in sa] == [s.iters for s in sb]
+    j = 0
+    for (dims, U, b, masses), x in zip(keep, xa):
+        for k in range(b.shape[0]):
+            rr = oracle.true_residual(dims, U, masses[k], b[k], x[k], oracle.BC_T_ANTIPERIODIC)
+            assert rr <= 1e-10 and sa[j].status == 0, (dims, k, rr)
+            j += 1
