@@ -521,12 +521,18 @@ int qx_meson_correlators(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_
    a private stream that waits for `stream`).  A stencil block covers 64
    sites with lps * groups wavefronts: lps (1, 2, 4, 8) wavefronts share the
    eight hops of each site (more loads in flight on small lattices), and each
-   of the groups = ceil(nrhs / nbt) takes nbt (1, 2, 4) sources, every link
-   loaded once per wavefront and applied to all of its sources.  xcd_order
+   of the groups = ceil(nrhs / nbt) takes nbt (1, 2, 4; 6 and 12 for FP32
+   one-hop links) sources, every link applied to all of the wavefront's
+   sources.  With one wavefront per site and two or more groups the groups
+   share the tile's link loads through LDS (up to 64 KB of one-hop links per
+   tile: not FP64 18-real links, not the improved operator); otherwise each
+   wavefront loads its links.  xcd_order
    is the block order: 0 as dispatched, 1 gives each of the eight XCDs a
    contiguous range of sites, 2 and 3 do the same and walk the (z, t) planes
    in tiles of 2 x 8 and 4 x 4 planes (when Lh * L1 is a multiple of 64),
-   which keeps the colour vectors of many sources in L2 between their uses.  scratch: two
+   which keeps the colour vectors of many sources in L2 between their uses;
+   4 and 5 give each XCD a slab of z or t planes, walked plane by plane, with
+   non-temporal output stores.  scratch: two
    packed fields of nrhs sources of the handle's precision
    (2 * qx_field_bytes).  The result is used by every later call with this
    handle and nrhs (Dslash, A and the solvers) and cached per (lattice,
