@@ -524,9 +524,9 @@ int qx_meson_correlators(const qx_gauge_t* g64, const qx_gauge_t* glo, const qx_
    of the groups = ceil(nrhs / nbt) takes nbt (1, 2, 4; 6 and 12 for FP32
    one-hop links) sources, every link applied to all of the wavefront's
    sources.  With one wavefront per site and two or more groups the groups
-   share the tile's link loads through LDS (up to 64 KB of one-hop links per
-   tile: not FP64 18-real links, not the improved operator); otherwise each
-   wavefront loads its links.  xcd_order
+   share the tile's link loads through LDS (FP32 and FP64 handles with up to
+   64 KB of one-hop links per tile: not FP64 18-real links, not the improved
+   operator, not F16 handles); otherwise each wavefront loads its links.  xcd_order
    is the block order: 0 as dispatched, 1 gives each of the eight XCDs a
    contiguous range of sites, 2 and 3 do the same and walk the (z, t) planes
    in tiles of 2 x 8 and 4 x 4 planes (when Lh * L1 is a multiple of 64),
