@@ -14,7 +14,7 @@ the sustained GFLOP/s of the median step.
 
 Reported beside it (same run):
   * the same twelve systems in plain FP64: as one FP64 batch and as twelve
-    FP64 single-source solves one after another (medians of three), i.e. the
+    FP64 single-source solves one after another (medians of five), i.e. the
     time-to-solution comparison mixed vs FP64 at equal and at single batching;
   * the roofline of the dominant kernel of the step, the D_eo pass of the
     iteration (half-Dslash with the A epilogue and the <p, A p> partials,
@@ -222,7 +222,7 @@ def headline(torch, qx, synth, args):
     out["fp64_batch_shape"] = list(b64.tune(2))
     b64.solve()
     tb = []
-    for _ in range(3):
+    for _ in range(5):
         t, stb = _sync_time(torch, b64.solve)
         tb.append(t)
     del b64, x_b
@@ -234,7 +234,7 @@ def headline(torch, qx, synth, args):
         b.set_launch(*shape1)
     singles[0].solve()
     ts = []
-    for _ in range(3):
+    for _ in range(5):
         t, st1 = _sync_time(torch, lambda: [b.solve()[0] for b in singles])
         ts.append(t)
     del singles, x_s
